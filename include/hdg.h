@@ -1,0 +1,192 @@
+/*
+ * hdg.h - C ABI of the MI355X hot path of one implicit hybridized-DG Newton step
+ * for the 2-D compressible Euler and Navier-Stokes equations
+ * (Woopen, Balan, May, Schuetz, arXiv:1308.3995).
+ *
+ * The Newton system of Sec. 3.3 (eq. linearsystem) is split as in Sec. 3.4
+ * (eq. ls, cons, hybridsystem): element-local unknowns U_K (Navier-Stokes: the
+ * gradient q then w; Euler: w) and skeleton unknowns Lambda on interior faces.
+ * Per element K the library assembles the Jacobian blocks
+ *     A_K = dR_K/dU_K,  B_K = dR_K/dLambda,  C_K = dR_lam,K/dU_K,  D_K = dR_lam,K/dLambda
+ * and right-hand sides r_K = -R_K, r_lam,K = -R_lam,K, condenses them to
+ *     S_K = D_K - C_K A_K^-1 B_K,   g_K = r_lam,K - C_K A_K^-1 r_K,
+ * sums S_K and g_K into the skeleton system K dLambda = E, solves it with
+ * block-Jacobi preconditioned restarted GMRES, and reconstructs
+ *     dU_K = A_K^-1 (r_K - B_K dLambda_K).
+ *
+ * Conventions shared by every call:
+ *   - Pointers named *_dev are device pointers owned by the caller; the library
+ *     never frees them. Pointers named *_host are host pointers read during
+ *     the call only.
+ *   - Calls that take a hipStream_t are stream-ordered; their outputs are valid
+ *     once that stream has synchronised. Calls that return host scalars
+ *     (iterations, residuals) synchronise the stream themselves.
+ *   - Inputs are never modified; outputs are overwritten, never accumulated.
+ *   - No C++ exception crosses this interface. On failure a call returns a
+ *     status other than HDG_OK and hdg_last_error() describes it.
+ *   - Mesh: counter-clockwise triangles; local face i of a triangle is the edge
+ *     (v_i, v_(i+1) mod 3); every boundary edge is a far-field boundary.
+ *   - Interior faces are numbered in canonical order: sorted by (lower vertex id,
+ *     higher vertex id). Face f carries 4 (p_f + 1) skeleton unknowns with
+ *     p_f = max of its two neighbours' degrees (Sec. 3.1), ordered field-major
+ *     (a (p_f + 1) + k, a in rho, rho u, rho v, E; k the Legendre mode), and
+ *     skeleton vectors concatenate the faces in canonical order.
+ *   - State arrays are padded to NP = (pmax+1)(pmax+2)/2 modes per field, pmax the
+ *     largest element degree of the plan:
+ *         w[e][a][i]         e < n_elements, a < 4,  i < NP   (float64)
+ *         q[e][4 d + a][i]   Navier-Stokes gradient unknowns, d < 2
+ *     Modes beyond an element's own degree are ignored on input and written as 0.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HDG_OK = 0,
+    HDG_ERR_INVALID_ARG = 1,     /* bad pointer, size, degree or mesh */
+    HDG_ERR_OOM = 2,             /* device allocation failed */
+    HDG_ERR_SINGULAR_LOCAL = 3,  /* zero pivot in a local or face-diagonal block, or a degenerate triangle */
+    HDG_ERR_NONFINITE = 4,       /* a non-finite value in the state or the assembled blocks */
+    HDG_ERR_NOT_CONVERGED = 5,   /* GMRES stopped at max_iter above rtol; the best iterate is returned */
+    HDG_ERR_HIP = 6              /* a HIP runtime call failed */
+} hdg_status;
+
+typedef enum { HDG_EULER = 0, HDG_NS = 1 } hdg_physics;
+
+/* HDG_FP64: every step in float64.
+ * HDG_MIXED: the skeleton solve runs its inner GMRES on a float32 copy of the
+ *            preconditioned skeleton matrix, wrapped in float64 iterative
+ *            refinement on the float64 skeleton matrix (residuals, Krylov
+ *            vectors and orthogonalisation stay float64). */
+typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;
+
+typedef struct {
+    int32_t physics;      /* hdg_physics */
+    int32_t precision;    /* hdg_precision */
+    double gamma;         /* ratio of specific heats (Sec. 2.1) */
+    double mach;          /* free-stream Mach number; rho_inf = 1, p_inf = 1/gamma */
+    double aoa_rad;       /* angle of attack of the free stream */
+    double reynolds;      /* Navier-Stokes: mu = rho_inf |v_inf| / Re (constant viscosity) */
+    double prandtl;       /* Navier-Stokes: heat flux (mu gamma / Pr) grad e */
+    double stab_alpha;    /* trace-flux constant alpha (Sec. 3.2); <= 0 selects |v_inf| + c_inf */
+} hdg_params;
+
+typedef struct {
+    int64_t n_elements;
+    int64_t n_faces;           /* interior faces */
+    int64_t n_boundary_faces;
+    int64_t n_skel_dof;        /* length of skeleton vectors */
+    int64_t np_max;            /* NP, modes per field in the padded state arrays */
+    int64_t n_fields;          /* 4 (Euler) or 12 (Navier-Stokes: 8 gradient + 4 conserved) */
+    int64_t bsr_blocks;        /* stored blocks of the skeleton matrix */
+    int64_t bsr_values;        /* float64 values of the skeleton matrix */
+    int64_t local_store_bytes; /* bytes of the element local-solution store (X_K, y_K) */
+    int64_t workspace_bytes;   /* bytes of scratch needed by every call below */
+    int64_t n_buckets;         /* (degree, face-degree) element buckets */
+} hdg_sizes;
+
+typedef struct hdg_plan hdg_plan;
+
+/* Build the plan of a mesh (Sec. 3.1): faces, face degrees p_f = max(p_K-, p_K+),
+ * skeleton offsets, the block pattern of the skeleton matrix (one diagonal and up to
+ * four off-diagonal blocks per face row, Sec. 3.4), element geometry, degree buckets,
+ * basis and quadrature tables, and far-field projectors. Host inputs:
+ *   xy_host[nv][2] vertex coordinates, tri_host[ne][3] vertex ids (counter-clockwise),
+ *   degree_host[ne] element degrees in 1..5.
+ * Allocates device memory on `device`; the plan is immutable afterwards and may be
+ * used from several streams. Errors: HDG_ERR_INVALID_ARG (bad sizes, ids, degrees,
+ * an edge shared by more than two triangles), HDG_ERR_SINGULAR_LOCAL (a triangle of
+ * non-positive area), HDG_ERR_OOM, HDG_ERR_HIP. */
+hdg_status hdg_plan_create(hdg_plan** out, const double* xy_host, int32_t nv,
+                           const int32_t* tri_host, int32_t ne, const int8_t* degree_host,
+                           const hdg_params* prm, int device);
+
+/* Sizes of every buffer the caller allocates. */
+hdg_status hdg_plan_sizes(const hdg_plan* plan, hdg_sizes* out);
+
+/* Face tables (host outputs, any may be NULL): face_vertices_host[n_faces][2] (sorted
+ * vertex pair), face_offset_host[n_faces + 1] (skeleton offsets), face_degree_host[n_faces]. */
+hdg_status hdg_plan_faces(const hdg_plan* plan, int32_t* face_vertices_host,
+                          int64_t* face_offset_host, int32_t* face_degree_host);
+
+/* Block pattern of the skeleton matrix (host outputs, any may be NULL):
+ * row_ptr_host[n_faces + 1], col_host[bsr_blocks] (face index of each block),
+ * val_off_host[bsr_blocks] (offset of each block in bsr_values). Block (f, f2) is
+ * 4(p_f+1) x 4(p_f2+1), stored column-major; the diagonal block is first in its row. */
+hdg_status hdg_plan_pattern(const hdg_plan* plan, int64_t* row_ptr_host, int32_t* col_host,
+                            int64_t* val_off_host);
+
+/* Assemble and condense (Sec. 3.2 eq. hdg_ls1..hdg_cont, Sec. 3.3 eq. linearsystem,
+ * Sec. 3.4 eq. hybridsystem). For every element: quadrature assembly of r_K, A_K,
+ * B_K, C_K, D_K in float64 with the trace flux f(lam).n - alpha (lam - w) and the
+ * far-field boundary state, local solves X_K = A_K^-1 B_K and y_K = A_K^-1 r_K by
+ * elimination with partial pivoting, S_K and g_K, then the sum into the skeleton matrix.
+ * Inputs: w_dev, q_dev (Navier-Stokes only, else NULL) in the padded state layout,
+ *         lam_dev[n_skel_dof] the current skeleton state.
+ * Outputs: bsr_values_dev[bsr_values] the skeleton matrix K (float64, pattern above),
+ *          rhs_dev[n_skel_dof] the right-hand side E,
+ *          local_store_dev[local_store_bytes] X_K and y_K for hdg_back_substitute.
+ * workspace_dev: workspace_bytes of scratch. elem_status_dev (optional, int32[ne]):
+ * per element 0, or HDG_ERR_SINGULAR_LOCAL / HDG_ERR_NONFINITE. res_norm_host
+ * (optional): if non-NULL the call synchronises and returns ||E||_2. The call itself
+ * returns HDG_ERR_SINGULAR_LOCAL or HDG_ERR_NONFINITE only when res_norm_host or
+ * elem_status_dev asks it to look (that needs a synchronisation). */
+hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const double* q_dev,
+                                 const double* lam_dev, double* bsr_values_dev, double* rhs_dev,
+                                 void* local_store_dev, void* workspace_dev,
+                                 int32_t* elem_status_dev, double* res_norm_host,
+                                 hipStream_t stream);
+
+/* Skeleton solve K dLambda = E (Sec. 3.4 eq. hybridsystem): restarted GMRES(restart)
+ * with right block-Jacobi preconditioning on the face-diagonal blocks and classical
+ * Gram-Schmidt with one re-orthogonalisation, all in float64 (HDG_MIXED: inner
+ * solves on a float32 preconditioned matrix inside float64 iterative refinement).
+ * Stops when ||E - K dLambda||_2 <= rtol ||E||_2 or after max_iter inner iterations.
+ * Outputs dlambda_dev[n_skel_dof]; iters_out (total inner iterations) and relres_out
+ * (true relative residual, recomputed in float64) may be NULL. Returns
+ * HDG_ERR_NOT_CONVERGED with the best iterate when max_iter is reached,
+ * HDG_ERR_SINGULAR_LOCAL when a face-diagonal block is singular. Synchronises. */
+hdg_status hdg_skeleton_solve(hdg_plan* plan, const double* bsr_values_dev, const double* rhs_dev,
+                              double* dlambda_dev, double rtol, int32_t restart, int32_t max_iter,
+                              void* workspace_dev, hipStream_t stream, int32_t* iters_out,
+                              double* relres_out);
+
+/* Back-substitution (Sec. 3.4): dU_K = y_K - X_K dLambda_K from the stored local
+ * solutions. Outputs dw_dev in the padded w layout and, for Navier-Stokes, dq_dev in
+ * the padded q layout (NULL for Euler). */
+hdg_status hdg_back_substitute(hdg_plan* plan, const void* local_store_dev,
+                               const double* dlambda_dev, double* dw_dev, double* dq_dev,
+                               void* workspace_dev, hipStream_t stream);
+
+/* Inspection entry for tests: the uncondensed element blocks of one element in the
+ * unknown order documented above (element: Navier-Stokes gradient fields 4d+a first,
+ * then w fields, each mode-minor; faces: interior local faces in order, each
+ * field-major), computed by the same device code as hdg_assemble_condense.
+ * Host outputs, each column-major: A_host[n*n], B_host[n*f], C_host[f*n], D_host[f*f],
+ * r_host[n], rl_host[f]; n_out and f_out receive n and f. Synchronises. */
+hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const double* w_dev,
+                                    const double* q_dev, const double* lam_dev,
+                                    double* A_host, double* B_host, double* C_host, double* D_host,
+                                    double* r_host, double* rl_host, int32_t* n_out, int32_t* f_out);
+
+/* Inspection entry for tests: X_K (n x f, column-major) and y_K of one element read
+ * back from a local store written by hdg_assemble_condense. Synchronises. */
+hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev, int64_t element,
+                                    double* X_host, double* y_host, int32_t* n_out, int32_t* f_out);
+
+/* Thread-local description of the last error of the calling thread. */
+const char* hdg_last_error(void);
+
+void hdg_plan_destroy(hdg_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

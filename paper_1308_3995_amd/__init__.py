@@ -1,0 +1,161 @@
+"""MI355X (gfx950) hot path of one implicit hybridized-DG Newton step for the 2-D
+compressible Euler and Navier-Stokes equations (arXiv:1308.3995).
+
+The numerical work runs in libhdg.so (hand-written HIP); this package marshals
+arguments to its C ABI and uses PyTorch only for device memory and streams. The
+method names mirror the C entry points of include/hdg.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional
+
+import numpy as np
+
+from ._lib import (HDG_EULER, HDG_FP64, HDG_MIXED, HDG_NS, HdgError, HdgParams, HdgSizes, check,  # noqa: F401
+                   load)
+
+__all__ = ["load", "HDGPlan", "HdgError", "HDG_FP64", "HDG_MIXED"]
+
+
+def _vp(t) -> Optional[C.c_void_p]:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class HDGPlan:
+    """A mesh plan plus the device buffers of one Newton step.
+
+    Buffers (torch tensors on the plan's device): `bsr` (skeleton matrix values, float64),
+    `rhs` (E), `store` (local solutions X_K, y_K), `ws` (workspace)."""
+
+    def __init__(self, xy, tri, degree, physics: str = "euler", mach: float = 0.5, aoa_deg: float = 0.0,
+                 reynolds: float = 0.0, prandtl: float = 0.72, gamma: float = 1.4, precision: str = "fp64",
+                 alpha: float = 0.0, device: int = 0):
+        import torch
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        deg = np.ascontiguousarray(degree, dtype=np.int8)
+        self.physics = physics
+        self.precision = precision
+        prm = HdgParams(HDG_NS if physics == "ns" else HDG_EULER, HDG_MIXED if precision == "mixed" else HDG_FP64,
+                        gamma, mach, math.radians(aoa_deg), reynolds, prandtl, alpha)
+        h = C.c_void_p()
+        check(self.lib.hdg_plan_create(C.byref(h), xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],
+                                       deg.ctypes.data, C.byref(prm), device))
+        self.handle = h
+        sz = HdgSizes()
+        check(self.lib.hdg_plan_sizes(h, C.byref(sz)))
+        self.sizes = {f: getattr(sz, f) for f, _ in HdgSizes._fields_}
+        nf = sz.n_faces
+        self.face_vertices = np.zeros((nf, 2), dtype=np.int32)
+        self.face_offset = np.zeros(nf + 1, dtype=np.int64)
+        self.face_degree = np.zeros(nf, dtype=np.int32)
+        check(self.lib.hdg_plan_faces(h, self.face_vertices.ctypes.data, self.face_offset.ctypes.data,
+                                      self.face_degree.ctypes.data))
+        self.n_skel = int(sz.n_skel_dof)
+        self.npmax = int(sz.np_max)
+        self.ne = int(sz.n_elements)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.bsr = torch.empty(max(1, sz.bsr_values), **f64)
+        self.rhs = torch.empty(max(1, self.n_skel), **f64)
+        self.store = torch.empty(max(1, (sz.local_store_bytes + 7) // 8), **f64)
+        self.ws = torch.empty(max(1, sz.workspace_bytes), dtype=torch.uint8, device=self.device)
+
+    @classmethod
+    def from_case(cls, case, precision: str = "fp64", device: int = 0, alpha: float = 0.0) -> "HDGPlan":
+        return cls(case.xy, case.tri, case.degree, physics=case.physics, mach=case.mach, aoa_deg=case.aoa_deg,
+                   reynolds=case.reynolds, prandtl=case.prandtl, gamma=case.gamma, precision=precision,
+                   alpha=alpha, device=device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.hdg_plan_destroy(h)
+            self.handle = None
+
+    # ---- layout helpers (host-side marshalling)
+    def pack_lambda(self, lam_padded: np.ndarray) -> np.ndarray:
+        """Compact skeleton vector from a (n_faces, 4, >= p_f + 1) array in canonical face order."""
+        out = np.empty(self.n_skel)
+        for f in range(len(self.face_degree)):
+            pe = self.face_degree[f]
+            out[self.face_offset[f]: self.face_offset[f + 1]] = lam_padded[f, :, : pe + 1].reshape(-1)
+        return out
+
+    def pattern(self):
+        nb = self.sizes["bsr_blocks"]
+        rp = np.zeros(len(self.face_degree) + 1, dtype=np.int64)
+        col = np.zeros(nb, dtype=np.int32)
+        voff = np.zeros(nb, dtype=np.int64)
+        check(self.lib.hdg_plan_pattern(self.handle, rp.ctypes.data, col.ctypes.data, voff.ctypes.data))
+        return rp, col, voff
+
+    # ---- the three calls of the hot path
+    def hdg_assemble_condense(self, w, lam, q=None, elem_status=None, want_norm: bool = False, stream=None):
+        nrm = C.c_double(0.0)
+        check(self.lib.hdg_assemble_condense(self.handle, _vp(w), _vp(q), _vp(lam), _vp(self.bsr), _vp(self.rhs),
+                                             _vp(self.store), _vp(self.ws), _vp(elem_status),
+                                             C.byref(nrm) if want_norm else None, _stream(stream)))
+        return nrm.value if want_norm else None
+
+    def hdg_skeleton_solve(self, dlam, rtol: float = 1e-12, restart: int = 30, max_iter: int = 200000,
+                           stream=None, raise_on_fail: bool = True):
+        it = C.c_int32(0)
+        rr = C.c_double(0.0)
+        st = self.lib.hdg_skeleton_solve(self.handle, _vp(self.bsr), _vp(self.rhs), _vp(dlam), rtol, restart,
+                                         max_iter, _vp(self.ws), _stream(stream), C.byref(it), C.byref(rr))
+        if raise_on_fail:
+            check(st)
+        return it.value, rr.value, st
+
+    def hdg_back_substitute(self, dlam, dw, dq=None, stream=None):
+        check(self.lib.hdg_back_substitute(self.handle, _vp(self.store), _vp(dlam), _vp(dw), _vp(dq), _vp(self.ws),
+                                           _stream(stream)))
+
+    # ---- inspection (tests)
+    def debug_element_blocks(self, element: int, w, lam, q=None):
+        n = self.sizes["n_fields"] * 21
+        f = 72
+        bufs = {k: np.zeros(s) for k, s in (("A", n * n), ("B", n * f), ("C", f * n), ("D", f * f), ("r", n),
+                                            ("rl", f))}
+        no, fo = C.c_int32(0), C.c_int32(0)
+        check(self.lib.hdg_debug_element_blocks(self.handle, element, _vp(w), _vp(q), _vp(lam),
+                                                *[bufs[k].ctypes.data for k in ("A", "B", "C", "D", "r", "rl")],
+                                                C.byref(no), C.byref(fo)))
+        n, f = no.value, fo.value
+        return dict(A=bufs["A"][: n * n].reshape(n, n).T, B=bufs["B"][: n * f].reshape(f, n).T,
+                    C=bufs["C"][: f * n].reshape(n, f).T, D=bufs["D"][: f * f].reshape(f, f).T,
+                    r=bufs["r"][:n].copy(), rl=bufs["rl"][:f].copy())
+
+    def debug_local_solution(self, element: int):
+        n = self.sizes["n_fields"] * 21
+        X = np.zeros(n * 72)
+        y = np.zeros(n)
+        no, fo = C.c_int32(0), C.c_int32(0)
+        check(self.lib.hdg_debug_local_solution(self.handle, _vp(self.store), element, X.ctypes.data, y.ctypes.data,
+                                                C.byref(no), C.byref(fo)))
+        n, f = no.value, fo.value
+        return X[: n * f].reshape(f, n).T, y[:n].copy()
+
+    def skeleton_matrix_dense(self) -> np.ndarray:
+        """Dense copy of the assembled skeleton matrix (small meshes only)."""
+        rp, col, voff = self.pattern()
+        vals = self.bsr.cpu().numpy()
+        K = np.zeros((self.n_skel, self.n_skel))
+        for f in range(len(self.face_degree)):
+            sf = self.face_offset[f + 1] - self.face_offset[f]
+            for b in range(rp[f], rp[f + 1]):
+                g = col[b]
+                sg = self.face_offset[g + 1] - self.face_offset[g]
+                blk = vals[voff[b]: voff[b] + sf * sg].reshape(sg, sf).T
+                K[self.face_offset[f]: self.face_offset[f + 1], self.face_offset[g]: self.face_offset[g + 1]] = blk
+        return K

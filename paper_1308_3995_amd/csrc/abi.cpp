@@ -1,0 +1,330 @@
+// C ABI: argument checking, error reporting and the call sequence of one Newton step.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hdg_internal.h"
+
+namespace hdg {
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int ne, const int8_t* degree,
+                      const hdg_params& prm, int device);
+void free_plan(Plan& P);
+}  // namespace hdg
+
+using namespace hdg;
+
+struct hdg_plan {
+    Plan p;
+};
+
+#define CHECK_HIP(x)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (x);                                                \
+        if (e_ != hipSuccess) {                                             \
+            set_error(std::string(#x) + ": " + hipGetErrorString(e_));      \
+            return e_ == hipErrorOutOfMemory ? HDG_ERR_OOM : HDG_ERR_HIP;   \
+        }                                                                   \
+    } while (0)
+
+extern "C" {
+
+const char* hdg_last_error(void) { return g_err.c_str(); }
+
+hdg_status hdg_plan_create(hdg_plan** out, const double* xy_host, int32_t nv, const int32_t* tri_host, int32_t ne,
+                           const int8_t* degree_host, const hdg_params* prm, int device) {
+    if (!out || !xy_host || !tri_host || !degree_host || !prm) {
+        set_error("hdg_plan_create: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    hdg_plan* h = new (std::nothrow) hdg_plan();
+    if (!h) {
+        set_error("host allocation failed");
+        return HDG_ERR_OOM;
+    }
+    hdg_status st = build_plan(h->p, xy_host, nv, tri_host, ne, degree_host, *prm, device);
+    if (st != HDG_OK) {
+        free_plan(h->p);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return HDG_OK;
+}
+
+void hdg_plan_destroy(hdg_plan* plan) {
+    if (!plan) return;
+    free_plan(plan->p);
+    delete plan;
+}
+
+hdg_status hdg_plan_sizes(const hdg_plan* plan, hdg_sizes* out) {
+    if (!plan || !out) {
+        set_error("hdg_plan_sizes: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    const Plan& p = plan->p;
+    out->n_elements = p.ne;
+    out->n_faces = p.nf;
+    out->n_boundary_faces = p.nbf;
+    out->n_skel_dof = p.face_off.back();
+    out->np_max = p.npmax;
+    out->n_fields = p.ns ? 12 : 4;
+    out->bsr_blocks = (int64_t)p.col.size();
+    out->bsr_values = p.bsr_values;
+    out->local_store_bytes = p.local_store_doubles * 8;
+    out->workspace_bytes = p.ws_total;
+    out->n_buckets = (int64_t)p.buckets.size();
+    return HDG_OK;
+}
+
+hdg_status hdg_plan_faces(const hdg_plan* plan, int32_t* fv, int64_t* off, int32_t* deg) {
+    if (!plan) {
+        set_error("hdg_plan_faces: null plan");
+        return HDG_ERR_INVALID_ARG;
+    }
+    const Plan& p = plan->p;
+    if (fv) std::memcpy(fv, p.face_vertices.data(), p.face_vertices.size() * 4);
+    if (off) std::memcpy(off, p.face_off.data(), p.face_off.size() * 8);
+    if (deg) std::memcpy(deg, p.face_deg.data(), p.face_deg.size() * 4);
+    return HDG_OK;
+}
+
+hdg_status hdg_plan_pattern(const hdg_plan* plan, int64_t* rp, int32_t* col, int64_t* voff) {
+    if (!plan) {
+        set_error("hdg_plan_pattern: null plan");
+        return HDG_ERR_INVALID_ARG;
+    }
+    const Plan& p = plan->p;
+    if (rp) std::memcpy(rp, p.row_ptr.data(), p.row_ptr.size() * 8);
+    if (col) std::memcpy(col, p.col.data(), p.col.size() * 4);
+    if (voff) std::memcpy(voff, p.val_off.data(), p.col.size() * 8);
+    return HDG_OK;
+}
+
+static hdg_status check_status(const Plan& p, const int32_t* status, const int32_t* flag, hipStream_t s) {
+    int32_t fl = 0;
+    CHECK_HIP(hipMemcpyAsync(&fl, flag, 4, hipMemcpyDeviceToHost, s));
+    CHECK_HIP(hipStreamSynchronize(s));
+    if (fl == 0) return HDG_OK;
+    std::vector<int32_t> st(p.ne);
+    CHECK_HIP(hipMemcpy(st.data(), status, (size_t)p.ne * 4, hipMemcpyDeviceToHost));
+    for (int e = 0; e < p.ne; ++e)
+        if (st[e] != 0) {
+            set_error("element " + std::to_string(e) + ": " +
+                      (st[e] == HDG_ERR_SINGULAR_LOCAL ? "singular local block" : "non-finite value"));
+            return (hdg_status)st[e];
+        }
+    return HDG_OK;
+}
+
+hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const double* q_dev, const double* lam_dev,
+                                 double* bsr_values_dev, double* rhs_dev, void* local_store_dev, void* workspace_dev,
+                                 int32_t* elem_status_dev, double* res_norm_host, hipStream_t stream) {
+    if (!plan || !w_dev || !lam_dev || !bsr_values_dev || !rhs_dev || !local_store_dev || !workspace_dev) {
+        set_error("hdg_assemble_condense: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (p.ns && !q_dev) {
+        set_error("hdg_assemble_condense: Navier-Stokes needs the gradient unknowns q");
+        return HDG_ERR_INVALID_ARG;
+    }
+    if (p.ns) {
+        set_error("hdg_assemble_condense: Navier-Stokes condensation is not built in this library");
+        return HDG_ERR_INVALID_ARG;
+    }
+    char* ws = (char*)workspace_dev;
+    int32_t* status = elem_status_dev ? elem_status_dev : (int32_t*)(ws + p.ws_status);
+    int32_t* flag = (int32_t*)(ws + p.ws_status) + p.ne;
+    CHECK_HIP(hipSetDevice(p.device));
+    CHECK_HIP(hipMemsetAsync(status, 0, (size_t)p.ne * 4, stream));
+    CHECK_HIP(hipMemsetAsync(flag, 0, 4, stream));
+    hipError_t e = launch_condense(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
+                                   (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag, nullptr, -1,
+                                   stream);
+    if (e == hipErrorInvalidValue) {
+        set_error("hdg_assemble_condense: element degree or face degree outside the built kernels (1..4)");
+        return HDG_ERR_INVALID_ARG;
+    }
+    CHECK_HIP(e);
+    CHECK_HIP(launch_diag_sum(p, (double*)(ws + p.ws_diag_part), (double*)(ws + p.ws_g_part), bsr_values_dev, rhs_dev,
+                              stream));
+    if (res_norm_host || elem_status_dev) {
+        hdg_status st = check_status(p, status, flag, stream);
+        if (st != HDG_OK) return st;
+    }
+    if (res_norm_host) {
+        const int64_t n = p.face_off.back();
+        std::vector<double> h(n);
+        CHECK_HIP(hipMemcpyAsync(h.data(), rhs_dev, n * 8, hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipStreamSynchronize(stream));
+        double s = 0.0;
+        for (double v : h) s += v * v;
+        *res_norm_host = std::sqrt(s);
+        if (!std::isfinite(*res_norm_host)) {
+            set_error("non-finite condensed right-hand side");
+            return HDG_ERR_NONFINITE;
+        }
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_skeleton_solve(hdg_plan* plan, const double* bsr_values_dev, const double* rhs_dev, double* dlambda_dev,
+                              double rtol, int32_t restart, int32_t max_iter, void* workspace_dev, hipStream_t stream,
+                              int32_t* iters_out, double* relres_out) {
+    if (!plan || !bsr_values_dev || !rhs_dev || !dlambda_dev || !workspace_dev) {
+        set_error("hdg_skeleton_solve: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    if (!(rtol > 0.0) || max_iter < 1) {
+        set_error("hdg_skeleton_solve: rtol must be > 0 and max_iter >= 1");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    CHECK_HIP(hipSetDevice(p.device));
+    int it = 0;
+    double rr = 0.0;
+    hdg_status st = skeleton_solve(p, bsr_values_dev, rhs_dev, dlambda_dev, rtol, restart, max_iter,
+                                   (char*)workspace_dev, stream, &it, &rr);
+    if (iters_out) *iters_out = it;
+    if (relres_out) *relres_out = rr;
+    return st;
+}
+
+hdg_status hdg_back_substitute(hdg_plan* plan, const void* local_store_dev, const double* dlambda_dev, double* dw_dev,
+                               double* dq_dev, void* workspace_dev, hipStream_t stream) {
+    (void)workspace_dev;
+    if (!plan || !local_store_dev || !dlambda_dev || !dw_dev) {
+        set_error("hdg_back_substitute: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (p.ns && !dq_dev) {
+        set_error("hdg_back_substitute: Navier-Stokes needs dq");
+        return HDG_ERR_INVALID_ARG;
+    }
+    CHECK_HIP(hipSetDevice(p.device));
+    hipError_t e = launch_back_substitute(p, (const double*)local_store_dev, dlambda_dev, dw_dev, dq_dev, stream);
+    if (e == hipErrorInvalidValue) {
+        set_error("hdg_back_substitute: element degree outside the built kernels");
+        return HDG_ERR_INVALID_ARG;
+    }
+    CHECK_HIP(e);
+    return HDG_OK;
+}
+
+hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const double* w_dev, const double* q_dev,
+                                    const double* lam_dev, double* A_host, double* B_host, double* C_host,
+                                    double* D_host, double* r_host, double* rl_host, int32_t* n_out, int32_t* f_out) {
+    if (!plan || !w_dev || !lam_dev) {
+        set_error("hdg_debug_element_blocks: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (element < 0 || element >= p.ne) {
+        set_error("element out of range");
+        return HDG_ERR_INVALID_ARG;
+    }
+    if (p.ns) {
+        set_error("hdg_debug_element_blocks: Navier-Stokes is not built in this library");
+        return HDG_ERR_INVALID_ARG;
+    }
+    const int slot = p.slot_of_elem[element];
+    const ElemInfo& ei = p.einfo[slot];
+    int bi = 0;
+    while (!(slot >= p.buckets[bi].start && slot < p.buckets[bi].start + p.buckets[bi].count)) ++bi;
+    const Bucket& bk = p.buckets[bi];
+    const int np = n_modes(bk.p), N = 4 * np, NPF = bk.pf + 1, F = 12 * NPF, NC = N + F + 1;
+    const int64_t total = (int64_t)NC * N + (int64_t)N * F + (int64_t)F * F + F;
+    CHECK_HIP(hipSetDevice(p.device));
+    double* dbg = nullptr;
+    CHECK_HIP(hipMalloc((void**)&dbg, total * 8));
+    CHECK_HIP(hipMemset(dbg, 0, total * 8));
+    hipError_t e = launch_condense(p, w_dev, q_dev, lam_dev, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, dbg,
+                                   slot, 0);
+    if (e != hipSuccess) {
+        (void)hipFree(dbg);
+        set_error(std::string("debug launch: ") + hipGetErrorString(e));
+        return HDG_ERR_HIP;
+    }
+    std::vector<double> h(total);
+    CHECK_HIP(hipMemcpy(h.data(), dbg, total * 8, hipMemcpyDeviceToHost));
+    (void)hipFree(dbg);
+    // compact face columns: interior faces only, modes up to p_f
+    std::vector<int> fmap;
+    for (int lf = 0; lf < 3; ++lf) {
+        if (ei.face[lf] < 0) continue;
+        for (int b = 0; b < 4; ++b)
+            for (int k = 0; k <= ei.pe[lf]; ++k) fmap.push_back((lf * 4 + b) * NPF + k);
+    }
+    const int f = (int)fmap.size();
+    if (n_out) *n_out = N;
+    if (f_out) *f_out = f;
+    const double* Ab = h.data();
+    const double* Cb = h.data() + (int64_t)NC * N;
+    const double* Db = Cb + (int64_t)N * F;
+    const double* rl = Db + (int64_t)F * F;
+    if (A_host)
+        for (int c = 0; c < N; ++c)
+            for (int r = 0; r < N; ++r) A_host[c * N + r] = Ab[c * N + r];
+    if (B_host)
+        for (int c = 0; c < f; ++c)
+            for (int r = 0; r < N; ++r) B_host[c * N + r] = Ab[(int64_t)(N + fmap[c]) * N + r];
+    if (r_host)
+        for (int r = 0; r < N; ++r) r_host[r] = Ab[(int64_t)(NC - 1) * N + r];
+    if (C_host)
+        for (int c = 0; c < N; ++c)
+            for (int r = 0; r < f; ++r) C_host[c * f + r] = Cb[(int64_t)c * F + fmap[r]];
+    if (D_host)
+        for (int c = 0; c < f; ++c)
+            for (int r = 0; r < f; ++r) D_host[c * f + r] = Db[(int64_t)fmap[c] * F + fmap[r]];
+    if (rl_host)
+        for (int r = 0; r < f; ++r) rl_host[r] = rl[fmap[r]];
+    return HDG_OK;
+}
+
+hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev, int64_t element, double* X_host,
+                                    double* y_host, int32_t* n_out, int32_t* f_out) {
+    if (!plan || !local_store_dev) {
+        set_error("hdg_debug_local_solution: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (element < 0 || element >= p.ne) {
+        set_error("element out of range");
+        return HDG_ERR_INVALID_ARG;
+    }
+    const int slot = p.slot_of_elem[element];
+    const ElemInfo& ei = p.einfo[slot];
+    int bi = 0;
+    while (!(slot >= p.buckets[bi].start && slot < p.buckets[bi].start + p.buckets[bi].count)) ++bi;
+    const Bucket& bk = p.buckets[bi];
+    const int np = n_modes(bk.p), N = 4 * np, NPF = bk.pf + 1, F = 12 * NPF;
+    const int64_t per = (int64_t)(F + 1) * N;
+    std::vector<double> h(per);
+    CHECK_HIP(hipSetDevice(p.device));
+    CHECK_HIP(hipMemcpy(h.data(), (const double*)local_store_dev + bk.store_off + (int64_t)(slot - bk.start) * per,
+                        per * 8, hipMemcpyDeviceToHost));
+    std::vector<int> fmap;
+    for (int lf = 0; lf < 3; ++lf) {
+        if (ei.face[lf] < 0) continue;
+        for (int b = 0; b < 4; ++b)
+            for (int k = 0; k <= ei.pe[lf]; ++k) fmap.push_back((lf * 4 + b) * NPF + k);
+    }
+    const int f = (int)fmap.size();
+    if (n_out) *n_out = N;
+    if (f_out) *f_out = f;
+    if (X_host)
+        for (int c = 0; c < f; ++c)
+            for (int r = 0; r < N; ++r) X_host[c * N + r] = h[(int64_t)fmap[c] * N + r];
+    if (y_host)
+        for (int r = 0; r < N; ++r) y_host[r] = h[(int64_t)F * N + r];
+    return HDG_OK;
+}
+
+}  // extern "C"

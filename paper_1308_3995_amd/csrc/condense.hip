@@ -1,0 +1,529 @@
+// Fused per-element assembly and static condensation for the Euler equations (gfx950).
+//
+// One 64-lane wavefront owns one element. Lanes first evaluate the state, convective
+// flux and its Jacobian at the volume and face quadrature points (Sec. 2.1, Sec. 3.2),
+// staging the weighted point data in LDS. Lane r then assembles row r of the augmented
+// local system [A_K | B_K | r_K] in registers (eq. hdg_ls2..hdg_ls4 linearised as in
+// eq. linearsystem), and the wave eliminates it with partial pivoting (Gauss-Jordan,
+// one row per lane, the pivot row broadcast through LDS). The eliminated rows are the
+// local solutions X_K = A_K^-1 B_K and y_K = A_K^-1 r_K kept for the reconstruction
+// (Sec. 3.4). Lanes then take the skeleton rows (local face, field, mode) and form
+//   S_K = D_K - C_K X_K,   g_K = r_lam,K - C_K y_K        (eq. hybridsystem)
+// where, for the trace flux f(lam).n - alpha (lam - w), C_K = alpha (trace mass) acts
+// field by field and D_K is block-diagonal over the element's faces. Off-diagonal face
+// blocks of S_K have one owner element and are stored straight into the skeleton
+// matrix; the diagonal blocks and g_K go to per-face slots summed by k_diag_sum in a
+// fixed order, so the assembly is deterministic and atomic-free.
+#include "hdg_internal.h"
+
+namespace hdg {
+
+struct CondArgs {
+    const ElemInfo* einfo;
+    const double* vphi;   // [q][i]
+    const double* vgrad;  // [r][q][i]
+    const double* vw;     // [q]
+    const double* fphi;   // face table of this degree
+    const double* leg;    // [rule][g][k]
+    const double* gw;     // [rule][g]
+    const double* bproj;  // [16] per boundary face
+    const int64_t* face_off;
+    const int64_t* diag_off;
+    const double* w;
+    const double* lam;
+    double* bsr;
+    double* diag_part;
+    double* g_part;
+    double* store;        // bucket store base
+    int32_t* status;      // [ne] per-element status
+    int32_t* flag;        // set to 1 when any element reports a failure
+    double* debug;
+    int debug_slot;
+    int start;            // first slot of the bucket
+    int npmax;
+    int ne;
+    double winf[4];
+    double alpha, gamma;
+};
+
+// Convective flux f_x, f_y and Jacobians A_x = df_x/dw, A_y = df_y/dw (row-major 4x4)
+// of the Euler equations with p = (gamma - 1)(E - rho |v|^2 / 2).
+__device__ __forceinline__ void euler_flux_jac(const double* w, double gm, double* fx, double* fy,
+                                               double* Ax, double* Ay) {
+    const double rho = w[0], ir = 1.0 / rho;
+    const double u = w[1] * ir, v = w[2] * ir, E = w[3];
+    const double q2 = u * u + v * v;
+    const double g1 = gm - 1.0;
+    const double p = g1 * (E - 0.5 * rho * q2);
+    const double H = (E + p) * ir;
+    const double phi = 0.5 * g1 * q2;
+    fx[0] = w[1];
+    fx[1] = w[1] * u + p;
+    fx[2] = w[2] * u;
+    fx[3] = u * (E + p);
+    fy[0] = w[2];
+    fy[1] = w[1] * v;
+    fy[2] = w[2] * v + p;
+    fy[3] = v * (E + p);
+    Ax[0] = 0.0;             Ax[1] = 1.0;               Ax[2] = 0.0;            Ax[3] = 0.0;
+    Ax[4] = phi - u * u;     Ax[5] = (3.0 - gm) * u;    Ax[6] = -g1 * v;        Ax[7] = g1;
+    Ax[8] = -u * v;          Ax[9] = v;                 Ax[10] = u;             Ax[11] = 0.0;
+    Ax[12] = u * (phi - H);  Ax[13] = H - g1 * u * u;   Ax[14] = -g1 * u * v;   Ax[15] = gm * u;
+    Ay[0] = 0.0;             Ay[1] = 0.0;               Ay[2] = 1.0;            Ay[3] = 0.0;
+    Ay[4] = -u * v;          Ay[5] = v;                 Ay[6] = u;              Ay[7] = 0.0;
+    Ay[8] = phi - v * v;     Ay[9] = -g1 * u;           Ay[10] = (3.0 - gm) * v; Ay[11] = g1;
+    Ay[12] = v * (phi - H);  Ay[13] = -g1 * u * v;      Ay[14] = H - g1 * v * v; Ay[15] = gm * v;
+}
+
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+}
+
+template <int P, int PF, bool DBG>
+__global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
+    constexpr int NP = n_modes(P);
+    constexpr int N = 4 * NP;
+    constexpr int NPF = PF + 1;
+    constexpr int F = 12 * NPF;
+    constexpr int NC = N + F + 1;
+    constexpr int Q = n_vol_q(P);
+    constexpr int QF = PF + 2;
+    static_assert(N <= 64, "one row per lane");
+    static_assert(Q <= 64, "one volume point per lane");
+
+    __shared__ double sW[4 * NP];
+    __shared__ double sLam[3][4][NPF];
+    __shared__ double sK[Q][2][16];
+    __shared__ double sF[Q][2][4];
+    __shared__ double sJA[3][QF][16];
+    __shared__ double sJB[3][QF][16];
+    __shared__ double sFH[3][QF][4];
+    __shared__ double sRow[2][NC];
+    __shared__ double sX[(F + 1) * N];
+
+    const int lane = threadIdx.x;
+    const int slot = a.start + blockIdx.x;
+    if (DBG && slot != a.debug_slot) return;
+    const ElemInfo* E = a.einfo + slot;
+    const int e = E->elem;
+    const double alpha = a.alpha, gm = a.gamma;
+
+    // ---- phase 0: element state and face traces into LDS
+    for (int t = lane; t < 4 * NP; t += 64) {
+        const int fa = t / NP, i = t % NP;
+        sW[t] = a.w[((int64_t)e * 4 + fa) * a.npmax + i];
+    }
+    for (int t = lane; t < 12 * NPF; t += 64) {
+        const int lf = t / (4 * NPF), r = t % (4 * NPF), fa = r / NPF, k = r % NPF;
+        const int f = E->face[lf];
+        double v = 0.0;
+        if (f >= 0 && k <= E->pe[lf]) v = a.lam[a.face_off[f] + fa * (E->pe[lf] + 1) + k];
+        sLam[lf][fa][k] = v;
+    }
+    __syncthreads();
+
+    // ---- phase 1: volume points (one per lane)
+    if (lane < Q) {
+        double wq[4];
+#pragma unroll
+        for (int fa = 0; fa < 4; ++fa) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) s += a.vphi[lane * NP + i] * sW[fa * NP + i];
+            wq[fa] = s;
+        }
+        double fx[4], fy[4], Ax[16], Ay[16];
+        euler_flux_jac(wq, gm, fx, fy, Ax, Ay);
+        const double sc = a.vw[lane] * E->detj;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const double j0 = sc * E->jinv[2 * r], j1 = sc * E->jinv[2 * r + 1];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sF[lane][r][c] = j0 * fx[c] + j1 * fy[c];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) sK[lane][r][c] = j0 * Ax[c] + j1 * Ay[c];
+        }
+    }
+    // ---- phase 2: face points (lane = 8 lf + g)
+    if (lane < 24) {
+        const int lf = lane >> 3, g = lane & 7;
+        const int pe = E->pe[lf], nq = pe + 2, o = E->orient[lf];
+        if (g < nq) {
+            const int rule = nq - kMinFaceQ;
+            const double wl = a.gw[rule * kMaxFaceQ + g] * 0.5 * E->len[lf];
+            const double nx = E->nrm[lf][0], ny = E->nrm[lf][1];
+            double wt[4];
+#pragma unroll
+            for (int fa = 0; fa < 4; ++fa) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) s += a.fphi[face_phi_index(NP, lf, o, nq, g, i)] * sW[fa * NP + i];
+                wt[fa] = s;
+            }
+            double fx[4], fy[4], Ax[16], Ay[16];
+            if (E->face[lf] >= 0) {
+                double lm[4];
+#pragma unroll
+                for (int fa = 0; fa < 4; ++fa) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NPF; ++k)
+                        s += (k <= pe ? a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k] : 0.0) * sLam[lf][fa][k];
+                    lm[fa] = s;
+                }
+                euler_flux_jac(lm, gm, fx, fy, Ax, Ay);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sFH[lf][g][c] = wl * (nx * fx[c] + ny * fy[c] - alpha * (lm[c] - wt[c]));
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const double d = (r == c) ? alpha : 0.0;
+                        sJB[lf][g][r * 4 + c] = wl * (nx * Ax[r * 4 + c] + ny * Ay[r * 4 + c] - d);
+                        sJA[lf][g][r * 4 + c] = wl * d;
+                    }
+            } else {
+                // far-field state w_b = P+ w + (I - P+) w_inf (Sec. 2.1), affine in w
+                const double* Pp = a.bproj + 16 * E->bproj[lf];
+                double wb[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) s += Pp[r * 4 + c] * (wt[c] - a.winf[c]);
+                    wb[r] = a.winf[r] + s;
+                }
+                euler_flux_jac(wb, gm, fx, fy, Ax, Ay);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sFH[lf][g][c] = wl * (nx * fx[c] + ny * fy[c]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) s += (nx * Ax[r * 4 + k] + ny * Ay[r * 4 + k]) * Pp[k * 4 + c];
+                        sJA[lf][g][r * 4 + c] = wl * s;
+                        sJB[lf][g][r * 4 + c] = 0.0;
+                    }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 3: row assembly, lane r = fa * NP + i
+    double m[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) m[c] = 0.0;
+    const int rr = lane < N ? lane : N - 1;
+    const int fa = rr / NP, ii = rr % NP;
+    {
+        double rhs = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
+            double s[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) s[b] = -(g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]);
+            rhs += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const double ph = a.vphi[q * NP + j];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) m[b * NP + j] += s[b] * ph;
+            }
+        }
+#pragma unroll
+        for (int lf = 0; lf < 3; ++lf) {
+            const int pe = E->pe[lf], nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+            const bool interior = E->face[lf] >= 0;
+            for (int g = 0; g < nq; ++g) {
+                const double phi_i = a.fphi[face_phi_index(NP, lf, o, nq, g, ii)];
+                double t[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) t[b] = phi_i * sJA[lf][g][fa * 4 + b];
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const double ph = a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) m[b * NP + j] += t[b] * ph;
+                }
+                rhs -= phi_i * sFH[lf][g][fa];
+                if (interior) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) t[b] = phi_i * sJB[lf][g][fa * 4 + b];
+#pragma unroll
+                    for (int k = 0; k < NPF; ++k) {
+                        const double ps = k <= pe ? a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k] : 0.0;
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) m[N + (lf * 4 + b) * NPF + k] += t[b] * ps;
+                    }
+                }
+            }
+        }
+        m[NC - 1] = rhs;
+    }
+
+    if (DBG) {
+        if (lane < N) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a.debug[(int64_t)c * N + lane] = m[c];
+        }
+    }
+
+    // ---- phase 4: Gauss-Jordan elimination with partial pivoting, one row per lane
+    int mykk = 0;
+    double mypv = 1.0;
+    if (!DBG) {
+        bool used = lane >= N;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double v = used ? -1.0 : fabs(m[k]);
+            int idx = lane;
+            wave_argmax(v, idx);
+            const int piv = __builtin_amdgcn_readfirstlane(idx);
+            double* buf = sRow[k & 1];
+            if (lane == piv) {
+#pragma unroll
+                for (int c = k; c < NC; ++c) buf[c] = m[c];
+            }
+            __syncthreads();
+            const double pv = buf[k];
+            const double f = (lane == piv || lane >= N) ? 0.0 : m[k] / pv;
+#pragma unroll
+            for (int c = k + 1; c < NC; ++c) m[c] -= f * buf[c];
+            if (lane == piv) {
+                used = true;
+                mykk = k;
+                mypv = pv;
+            }
+        }
+        // ---- phase 5: X_K, y_K to the local store and to LDS
+        if (lane < N) {
+            const double inv = 1.0 / mypv;
+            const int bslot = slot - a.start;
+            double* st = a.store + (int64_t)bslot * ((F + 1) * N);
+            bool bad = !(fabs(mypv) > 0.0) || !isfinite(inv);
+#pragma unroll
+            for (int c = 0; c <= F; ++c) {
+                const double x = m[N + c] * inv;
+                bad |= !isfinite(x);
+                sX[c * N + mykk] = x;
+                st[c * N + mykk] = x;
+            }
+            if (bad) {
+                a.status[e] = (!(fabs(mypv) > 0.0) || !isfinite(inv)) ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+                a.flag[0] = 1;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 6: skeleton rows (lf, field, mode): S_K = D_K - C_K X_K, g_K = r_lam - C_K y_K
+    for (int r = lane; r < F; r += 64) {
+        const int lf = r / (4 * NPF), b = (r / NPF) % 4, k = r % NPF;
+        const int f = E->face[lf], pe = E->pe[lf];
+        if (!DBG && (f < 0 || k > pe)) continue;
+        const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+        const bool valid = f >= 0 && k <= pe;
+        const double hl = 0.5 * E->len[lf];
+        // trace mass T[j] = int_e psi_k phi_j
+        double T[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) T[j] = 0.0;
+        double rl = 0.0;
+        if (valid) {
+            for (int g = 0; g < nq; ++g) {
+                const double pk = a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
+                const double wpk = a.gw[rule * kMaxFaceQ + g] * hl * pk;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) T[j] += wpk * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
+                rl -= pk * sFH[lf][g][b];
+            }
+        }
+        const int se = 4 * (pe + 1);
+        const int row = b * (pe + 1) + k;
+        if (DBG) {
+            // C_K row (field-diagonal trace mass), D_K row, r_lam
+#pragma unroll
+            for (int c2 = 0; c2 < N; ++c2) a.debug[(int64_t)NC * N + (int64_t)c2 * F + r] = (c2 / NP == b) ? alpha * T[c2 % NP] : 0.0;
+        } else {
+            double gy = rl;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) gy -= alpha * T[j] * sX[F * N + b * NP + j];
+            a.g_part[2 * a.face_off[f] + E->side[lf] * se + row] = gy;
+        }
+#pragma unroll
+        for (int c2 = 0; c2 < F; ++c2) {
+            const int lf2 = c2 / (4 * NPF), b2 = (c2 / NPF) % 4, l = c2 % NPF;
+            double dv = 0.0;
+            if (lf2 == lf && valid && l <= pe) {
+                for (int g = 0; g < nq; ++g) {
+                    const double* lg = a.leg + (rule * kMaxFaceQ + g) * (kMaxDegree + 1);
+                    dv += lg[k] * lg[l] * sJB[lf][g][b * 4 + b2];
+                }
+            }
+            if (DBG) {
+                a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)c2 * F + r] = dv;
+                continue;
+            }
+            const int f2 = E->face[lf2], pe2 = E->pe[lf2];
+            if (f2 < 0 || l > pe2) continue;
+            double cx = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cx += T[j] * sX[c2 * N + b * NP + j];
+            const double sv = dv - alpha * cx;
+            const int colc = b2 * (pe2 + 1) + l;
+            if (lf2 == lf) {
+                a.diag_part[a.diag_off[f] + (int64_t)E->side[lf] * se * se + (int64_t)colc * se + row] = sv;
+            } else {
+                a.bsr[E->boff[lf][lf2] + (int64_t)colc * se + row] = sv;
+            }
+        }
+        if (DBG) a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)F * F + r] = rl;
+    }
+}
+
+// Sum the two diagonal contributions of every face in a fixed order and the two halves
+// of the condensed right-hand side.
+__global__ void k_diag_sum(int nf, const int64_t* face_off, const int64_t* diag_off, const int64_t* row_ptr,
+                           const int64_t* val_off, const double* dp, const double* gp, double* bsr, double* rhs) {
+    const int f = blockIdx.x;
+    if (f >= nf) return;
+    const int64_t s = face_off[f + 1] - face_off[f];
+    const double* d0 = dp + diag_off[f];
+    double* dst = bsr + val_off[row_ptr[f]];
+    for (int64_t t = threadIdx.x; t < s * s; t += blockDim.x) dst[t] = d0[t] + d0[s * s + t];
+    const double* g0 = gp + 2 * face_off[f];
+    for (int64_t t = threadIdx.x; t < s; t += blockDim.x) rhs[face_off[f] + t] = g0[t] + g0[s + t];
+}
+
+// Reconstruction dU_K = y_K - X_K dLambda_K (Sec. 3.4), one wave per element.
+template <int P, int PF>
+__global__ __launch_bounds__(64) void k_backsub_euler(const ElemInfo* einfo, int start, const double* store,
+                                                      const int64_t* face_off, const double* dlam, double* dw,
+                                                      int npmax) {
+    constexpr int NP = n_modes(P), N = 4 * NP, NPF = PF + 1, F = 12 * NPF;
+    __shared__ double sL[F];
+    __shared__ double sD[N];
+    const int lane = threadIdx.x;
+    const int slot = start + blockIdx.x;
+    const ElemInfo* E = einfo + slot;
+    for (int c = lane; c < F; c += 64) {
+        const int lf = c / (4 * NPF), b = (c / NPF) % 4, k = c % NPF;
+        const int f = E->face[lf];
+        sL[c] = (f >= 0 && k <= E->pe[lf]) ? dlam[face_off[f] + b * (E->pe[lf] + 1) + k] : 0.0;
+    }
+    __syncthreads();
+    const double* st = store + (int64_t)blockIdx.x * ((F + 1) * N);
+    if (lane < N) {
+        double v = st[F * N + lane];
+        for (int c = 0; c < F; ++c) v -= st[c * N + lane] * sL[c];
+        sD[lane] = v;
+    }
+    __syncthreads();
+    const int e = E->elem;
+    for (int t = lane; t < 4 * npmax; t += 64) {
+        const int fa = t / npmax, i = t % npmax;
+        dw[(int64_t)e * 4 * npmax + t] = i < NP ? sD[fa * NP + i] : 0.0;
+    }
+}
+
+template <int P, int PF>
+static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, hipStream_t s) {
+    a.vphi = p.d_tab + p.tix.vol_phi[P];
+    a.vgrad = p.d_tab + p.tix.vol_grad[P];
+    a.vw = p.d_tab + p.tix.vol_w[P];
+    a.fphi = p.d_tab + p.tix.face_phi[P];
+    a.start = bk.start;
+    if (dbg)
+        hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+static hipError_t dispatch_condense(const Plan& p, const Bucket& bk, const CondArgs& a, bool dbg, hipStream_t s) {
+#define HDG_CASE(PP, FF) \
+    if (bk.p == PP && bk.pf == FF) return launch_bucket<PP, FF>(p, bk, a, dbg, s);
+    HDG_CASE(1, 1) HDG_CASE(1, 2) HDG_CASE(1, 3) HDG_CASE(1, 4)
+    HDG_CASE(2, 2) HDG_CASE(2, 3) HDG_CASE(2, 4)
+    HDG_CASE(3, 3) HDG_CASE(3, 4)
+    HDG_CASE(4, 4)
+#undef HDG_CASE
+    return hipErrorInvalidValue;
+}
+
+static bool bucket_supported(const Bucket& bk) { return bk.p >= 1 && bk.p <= 4 && bk.pf >= bk.p && bk.pf <= 4; }
+
+hipError_t launch_condense(const Plan& p, const double* w, const double* q, const double* lam, double* bsr,
+                           double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag,
+                           double* debug, int debug_slot, hipStream_t s) {
+    (void)q;
+    CondArgs a{};
+    a.einfo = p.d_einfo;
+    a.leg = p.d_tab + p.tix.leg;
+    a.gw = p.d_tab + p.tix.gw;
+    a.bproj = p.d_bproj;
+    a.face_off = p.d_face_off;
+    a.diag_off = p.d_diag_off;
+    a.w = w;
+    a.lam = lam;
+    a.bsr = bsr;
+    a.diag_part = diag_part;
+    a.g_part = g_part;
+    a.status = status;
+    a.flag = flag;
+    a.debug = debug;
+    a.debug_slot = debug_slot;
+    a.npmax = p.npmax;
+    a.ne = p.ne;
+    for (int i = 0; i < 4; ++i) a.winf[i] = p.winf[i];
+    a.alpha = p.alpha;
+    a.gamma = p.prm.gamma;
+    for (const Bucket& bk : p.buckets) {
+        if (!bucket_supported(bk)) return hipErrorInvalidValue;
+        if (debug && !(debug_slot >= bk.start && debug_slot < bk.start + bk.count)) continue;
+        a.store = store + bk.store_off;
+        hipError_t e = dispatch_condense(p, bk, a, debug != nullptr, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double* g_part, double* bsr, double* rhs,
+                           hipStream_t s) {
+    if (p.nf == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag_sum, dim3(p.nf), dim3(256), 0, s, p.nf, p.d_face_off, p.d_diag_off, p.d_row_ptr,
+                       p.d_val_off, diag_part, g_part, bsr, rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_back_substitute(const Plan& p, const double* store, const double* dlam, double* dw, double* dq,
+                                  hipStream_t s) {
+    (void)dq;
+    for (const Bucket& bk : p.buckets) {
+        if (!bucket_supported(bk)) return hipErrorInvalidValue;
+#define HDG_CASE(PP, FF)                                                                                    \
+    if (bk.p == PP && bk.pf == FF) {                                                                        \
+        hipLaunchKernelGGL((k_backsub_euler<PP, FF>), dim3(bk.count), dim3(64), 0, s, p.d_einfo, bk.start, \
+                           store + bk.store_off, p.d_face_off, dlam, dw, p.npmax);                          \
+        continue;                                                                                           \
+    }
+        HDG_CASE(1, 1) HDG_CASE(1, 2) HDG_CASE(1, 3) HDG_CASE(1, 4)
+        HDG_CASE(2, 2) HDG_CASE(2, 3) HDG_CASE(2, 4)
+        HDG_CASE(3, 3) HDG_CASE(3, 4)
+        HDG_CASE(4, 4)
+#undef HDG_CASE
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hdg

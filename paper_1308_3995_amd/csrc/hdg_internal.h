@@ -1,0 +1,133 @@
+// Internal data structures shared by the host plan and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+
+namespace hdg {
+
+constexpr int kMaxDegree = 5;
+constexpr int kMaxFaceQ = 8;          // face Gauss points stored per rule (p_f + 2 <= 7 used)
+constexpr int kMinFaceQ = 2;
+constexpr int kNumFaceRules = kMaxFaceQ - kMinFaceQ + 1;
+
+__host__ __device__ constexpr int n_modes(int p) { return (p + 1) * (p + 2) / 2; }
+__host__ __device__ constexpr int n_vol_q(int p) { return (p + 2) * (p + 2); }
+
+// Per-element data, stored in bucket order (elements of one (p, p_face_max) bucket
+// are contiguous). Geometry is affine: x = v0 + J (xi + 1), J = [v1 - v0, v2 - v0] / 2.
+struct ElemInfo {
+    double jinv[4];       // d xi / d x, d xi / d y, d eta / d x, d eta / d y
+    double detj;          // det J = |K| / 2
+    double nrm[3][2];     // outward unit normal of local face lf
+    double len[3];        // edge length
+    int32_t face[3];      // interior face id, -1 on the boundary
+    int32_t orient[3];    // 1 when the face's global direction runs against the local one
+    int32_t pe[3];        // face degree (interior) or the element degree (boundary)
+    int32_t side[3];      // slot (0/1) of this element in the face's diagonal parts
+    int32_t bproj[3];     // boundary projector index, -1 for interior faces
+    int32_t elem;         // element id in the caller's numbering
+    int32_t slot;         // position in bucket order
+    int32_t pad;
+    int64_t boff[3][3];   // value offset of skeleton block (face[lf], face[lf2]); -1 if absent
+};
+
+// Offsets (in doubles) of the reference tables inside one device array.
+struct TableIndex {
+    int64_t vol_phi[kMaxDegree + 1];    // [q][i]
+    int64_t vol_grad[kMaxDegree + 1];   // [r][q][i], r = reference direction
+    int64_t vol_w[kMaxDegree + 1];      // [q]
+    int64_t face_phi[kMaxDegree + 1];   // [lf][o][rule][g < kMaxFaceQ][i]
+    int64_t leg;                        // [rule][g][k <= kMaxDegree]  orthonormal Legendre at Gauss points
+    int64_t gw;                         // [rule][g]  Gauss weights
+};
+
+__host__ __device__ inline int64_t face_phi_index(int np, int lf, int o, int nq, int g, int i) {
+    return ((((int64_t)(lf * 2 + o) * kNumFaceRules + (nq - kMinFaceQ)) * kMaxFaceQ + g) * np + i);
+}
+
+struct Bucket {
+    int p;            // element degree
+    int pf;           // largest face degree of its interior faces (>= p)
+    int start;        // first slot in bucket order
+    int count;
+    int64_t store_off;  // offset (doubles) of the bucket's local-store region
+};
+
+struct Plan {
+    int device = 0;
+    hdg_params prm{};
+    bool ns = false;
+    int ne = 0, nv = 0, nf = 0, nbf = 0;
+    int pmax = 1;
+    int npmax = 3;
+    double winf[4];
+    double alpha = 0.0;
+    double mu = 0.0;
+
+    // host mirrors
+    std::vector<int32_t> face_vertices;   // [nf][2]
+    std::vector<int64_t> face_off;        // [nf+1] skeleton offsets
+    std::vector<int32_t> face_deg;        // [nf]
+    std::vector<int64_t> row_ptr;         // [nf+1] blocks per face row
+    std::vector<int32_t> col;             // [nblk]
+    std::vector<int64_t> val_off;         // [nblk+1]
+    std::vector<int64_t> diag_off;        // [nf+1] offsets of the two diagonal parts (2 s^2 each)
+    std::vector<ElemInfo> einfo;          // bucket order
+    std::vector<int32_t> slot_of_elem;    // [ne]
+    std::vector<Bucket> buckets;
+    std::vector<int64_t> hat_row_ptr;     // off-diagonal block pattern of the preconditioned matrix
+    std::vector<int32_t> hat_col;
+    std::vector<int64_t> hat_val_off;     // [nhat+1]; blocks of a row are contiguous (a row slab)
+    std::vector<int64_t> hat_src;         // value offset of the corresponding block of K
+    TableIndex tix{};
+    int64_t local_store_doubles = 0;
+    int64_t bsr_values = 0;
+
+    // device copies
+    ElemInfo* d_einfo = nullptr;
+    double* d_tab = nullptr;
+    double* d_bproj = nullptr;
+    int64_t* d_face_off = nullptr;
+    int32_t* d_face_deg = nullptr;
+    int64_t* d_row_ptr = nullptr;
+    int32_t* d_col = nullptr;
+    int64_t* d_val_off = nullptr;
+    int64_t* d_diag_off = nullptr;
+    int64_t* d_hat_row_ptr = nullptr;
+    int32_t* d_hat_col = nullptr;
+    int64_t* d_hat_val_off = nullptr;
+    int64_t* d_hat_src = nullptr;
+
+    // workspace layout (offsets in bytes)
+    int64_t ws_diag_part = 0, ws_g_part = 0, ws_status = 0, ws_solver = 0, ws_total = 0;
+    int64_t hat_values = 0;
+    int solver_restart_max = 0;
+    int gmres_groups = 0;
+};
+
+// Workspace carving for the skeleton solver (offsets in bytes from ws_solver).
+struct SolverLayout {
+    int64_t minv, hat, hat32, V, w, w2, x, y, r, partial, hess, scal, total;
+};
+SolverLayout solver_layout(const Plan& p, int restart);
+
+// kernel launchers (condense.hip, skeleton.hip)
+hipError_t launch_condense(const Plan& p, const double* w, const double* q, const double* lam,
+                           double* bsr, double* diag_part, double* g_part, double* store,
+                           int32_t* status, int32_t* flag, double* debug, int debug_slot, hipStream_t s);
+hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double* g_part, double* bsr,
+                           double* rhs, hipStream_t s);
+hipError_t launch_back_substitute(const Plan& p, const double* store, const double* dlam, double* dw,
+                                  double* dq, hipStream_t s);
+hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol,
+                          int restart, int max_iter, char* ws, hipStream_t s, int* iters, double* relres);
+
+void set_error(const std::string& msg);
+
+}  // namespace hdg
