@@ -1,0 +1,155 @@
+"""Benchmark of one implicit-HDG Newton step on one MI355X.
+
+Workload: 2-D Euler, uniform p = 3 on a jittered 64 x 64 unit-square mesh split into
+8192 triangles (local blocks 40 x 40, 3 faces x 4 nodes x 4 fields), Mach 0.5,
+alpha 2 deg free stream plus a seeded perturbation of amplitude 1e-2; synthetic,
+seeded inputs resident in HBM before timing starts.
+
+A step is the whole hot path: assemble + condense (hdg_assemble_condense), block-Jacobi
+GMRES on the skeleton (hdg_skeleton_solve) to a relative residual of 1e-10, and
+back-substitution (hdg_back_substitute). Both precision modes are timed; the reported
+`value` is condensed elements per second of full Newton steps of the mixed mode.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(ng: int = 16):
+    """The CPU oracle, untouched, on the same recipe at a bounded size (full Newton step)."""
+    import hdg_inputs as hi
+    from oracle import hdg_oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:
+        limiter = None
+    case = hi.config_case("c2", ng=ng)
+    t0 = time.perf_counter()
+    step = O.newton_step(case)
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": case.n_elements / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"same recipe at {ng}x{ng} (p=3, {case.n_elements} elements, {step.mesh.n_skel} skeleton dofs): "
+                      f"one full oracle Newton step (complex-step blocks, LU condensation, direct skeleton solve, "
+                      f"reconstruction) took {dt:.2f} s on 1 thread",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--modes", default="fp64,mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import hdg_inputs as hi
+    import paper_1308_3995_amd as hdg
+
+    hdg.load()
+    case = hi.config_case("c2")
+    dev = torch.device("cuda", 0)
+    results = {}
+    for mode in args.modes.split(","):
+        log(f"[bench] mode {mode}: plan")
+        plan = hdg.HDGPlan.from_case(case, precision=mode)
+        w = torch.tensor(case.W, dtype=torch.float64, device=dev).contiguous()
+        lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
+        dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=dev)
+        dw = torch.zeros_like(w)
+        stream = torch.cuda.current_stream()
+
+        def step():
+            plan.hdg_assemble_condense(w, lam)
+            it, rr, _ = plan.hdg_skeleton_solve(dlam, rtol=args.rtol, restart=args.restart)
+            plan.hdg_back_substitute(dlam, dw)
+            return it, rr
+
+        for i in range(args.warmup):
+            it, rr = step()
+            log(f"[bench] mode {mode}: warmup {i} gmres iters {it} relres {rr:.2e}")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        iters = []
+        e0.record(stream)
+        for i in range(args.steps):
+            it, rr = step()
+            iters.append((it, rr))
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = e0.elapsed_time(e1) / args.steps
+        log(f"[bench] mode {mode}: {ms_step:.3f} ms/step, gmres iters {iters[-1][0]}, relres {iters[-1][1]:.2e}")
+        # condensation alone
+        reps = max(5, args.steps)
+        e0.record(stream)
+        for _ in range(reps):
+            plan.hdg_assemble_condense(w, lam)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_cond = e0.elapsed_time(e1) / reps
+        log(f"[bench] mode {mode}: assemble+condense {ms_cond:.3f} ms")
+        results[mode] = dict(ms_step=ms_step, ms_condense=ms_cond, gmres_iters=iters[-1][0],
+                             relres=iters[-1][1], n_skel=plan.n_skel)
+        del plan
+        torch.cuda.synchronize()
+
+    ne = case.n_elements
+    main_mode = "mixed" if "mixed" in results else list(results)[0]
+    r = results[main_mode]
+    out = {
+        "metric": "condensed elements/s + skeleton DOF/s, mixed vs FP64 at 1e-10; p50/p99 latency",
+        "value": ne / (r["ms_step"] / 1e3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_mode == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "2-D Euler HDG, uniform p=3, 64x64 jittered unit square (8192 triangles), "
+                               "Mach 0.5, alpha 2 deg, perturbation 1e-2; one Newton step, GMRES(30) to 1e-10",
+                   "elements": ne, "skeleton_dofs": r["n_skel"], "precision": main_mode},
+        "modes": {m: {"ms_per_step": v["ms_step"], "elements_per_s": ne / (v["ms_step"] / 1e3),
+                      "skeleton_dof_per_s": v["n_skel"] / (v["ms_step"] / 1e3),
+                      "condense_ms": v["ms_condense"], "condensed_elements_per_s": ne / (v["ms_condense"] / 1e3),
+                      "gmres_iters": v["gmres_iters"], "relres": v["relres"]} for m, v in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cb = cpu_baseline()
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
