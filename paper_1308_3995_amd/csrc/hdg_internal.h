@@ -15,6 +15,7 @@ constexpr int kMaxDegree = 5;
 constexpr int kMaxFaceQ = 8;          // face Gauss points stored per rule (p_f + 2 <= 7 used)
 constexpr int kMinFaceQ = 2;
 constexpr int kNumFaceRules = kMaxFaceQ - kMinFaceQ + 1;
+constexpr int kMaxRestart = 32;       // GMRES restart length limit (Krylov basis kept in registers per element)
 
 __host__ __device__ constexpr int n_modes(int p) { return (p + 1) * (p + 2) / 2; }
 __host__ __device__ constexpr int n_vol_q(int p) { return (p + 2) * (p + 2); }
@@ -85,6 +86,11 @@ struct Plan {
     std::vector<int32_t> hat_col;
     std::vector<int64_t> hat_val_off;     // [nhat+1]; blocks of a row are contiguous (a row slab)
     std::vector<int64_t> hat_src;         // value offset of the corresponding block of K
+    // row slabs (values of a face row are contiguous, column-major with s_f rows)
+    std::vector<int64_t> k_rowbase, k_colbase, hat_rowbase, hat_colbase;
+    std::vector<int32_t> k_xidx, hat_xidx;    // skeleton index of every slab column
+    std::vector<int32_t> kb_rows;             // face-row partition over the Krylov kernel blocks
+    int kblocks = 1;
     TableIndex tix{};
     int64_t local_store_doubles = 0;
     int64_t bsr_values = 0;
@@ -103,6 +109,13 @@ struct Plan {
     int32_t* d_hat_col = nullptr;
     int64_t* d_hat_val_off = nullptr;
     int64_t* d_hat_src = nullptr;
+    int64_t* d_k_rowbase = nullptr;
+    int64_t* d_k_colbase = nullptr;
+    int32_t* d_k_xidx = nullptr;
+    int64_t* d_hat_rowbase = nullptr;
+    int64_t* d_hat_colbase = nullptr;
+    int32_t* d_hat_xidx = nullptr;
+    int32_t* d_kb_rows = nullptr;
 
     // workspace layout (offsets in bytes)
     int64_t ws_diag_part = 0, ws_g_part = 0, ws_status = 0, ws_solver = 0, ws_total = 0;

@@ -345,6 +345,36 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     }
     P.bsr_values = P.val_off.back();
     P.hat_values = P.hat_val_off.back();
+    // row slabs: value base of each row and the gather index of every slab column
+    auto slabs = [&](const std::vector<int64_t>& rp, const std::vector<int32_t>& cl, const std::vector<int64_t>& vo,
+                     std::vector<int64_t>& rowbase, std::vector<int64_t>& colbase, std::vector<int32_t>& xidx) {
+        rowbase.assign(P.nf + 1, 0);
+        colbase.assign(P.nf + 1, 0);
+        xidx.clear();
+        for (int f = 0; f < P.nf; ++f) {
+            rowbase[f] = rp[f] < rp[f + 1] ? vo[rp[f]] : (f > 0 ? rowbase[f - 1] : 0);
+            for (int64_t b = rp[f]; b < rp[f + 1]; ++b)
+                for (int64_t c = 0; c < fsize(cl[b]); ++c) xidx.push_back((int32_t)(P.face_off[cl[b]] + c));
+            colbase[f + 1] = (int64_t)xidx.size();
+        }
+        rowbase[P.nf] = vo.empty() ? 0 : vo.back();
+    };
+    slabs(P.row_ptr, P.col, P.val_off, P.k_rowbase, P.k_colbase, P.k_xidx);
+    slabs(P.hat_row_ptr, P.hat_col, P.hat_val_off, P.hat_rowbase, P.hat_colbase, P.hat_xidx);
+    // partition of the face rows over the blocks of the Krylov kernels (about equal dofs)
+    {
+        const int B = std::max(1, std::min(256, P.nf));
+        P.kb_rows.assign(B + 1, 0);
+        const int64_t tot = P.face_off[P.nf];
+        int f = 0;
+        for (int b = 1; b < B; ++b) {
+            const int64_t target = tot * b / B;
+            while (f < P.nf && P.face_off[f] < target) ++f;
+            P.kb_rows[b] = f;
+        }
+        P.kb_rows[B] = P.nf;
+        P.kblocks = B;
+    }
     auto block_offset = [&](int f, int g2) -> int64_t {
         for (int64_t b = P.row_ptr[f]; b < P.row_ptr[f + 1]; ++b)
             if (P.col[b] == g2) return P.val_off[b];
@@ -445,7 +475,7 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     build_tables(P, tab);
 
     // workspace: diagonal parts, rhs parts, status word, solver
-    P.solver_restart_max = 64;
+    P.solver_restart_max = kMaxRestart;
     int64_t off = 0;
     auto carve = [&](int64_t bytes) { int64_t o = off; off += (bytes + 255) / 256 * 256; return o; };
     P.ws_diag_part = carve(P.diag_off.back() * 8);
@@ -470,6 +500,13 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     if (err == hipSuccess) err = upload(&P.d_hat_col, P.hat_col);
     if (err == hipSuccess) err = upload(&P.d_hat_val_off, P.hat_val_off);
     if (err == hipSuccess) err = upload(&P.d_hat_src, P.hat_src);
+    if (err == hipSuccess) err = upload(&P.d_k_rowbase, P.k_rowbase);
+    if (err == hipSuccess) err = upload(&P.d_k_colbase, P.k_colbase);
+    if (err == hipSuccess) err = upload(&P.d_k_xidx, P.k_xidx);
+    if (err == hipSuccess) err = upload(&P.d_hat_rowbase, P.hat_rowbase);
+    if (err == hipSuccess) err = upload(&P.d_hat_colbase, P.hat_colbase);
+    if (err == hipSuccess) err = upload(&P.d_hat_xidx, P.hat_xidx);
+    if (err == hipSuccess) err = upload(&P.d_kb_rows, P.kb_rows);
     if (err != hipSuccess) {
         set_error(std::string("plan upload: ") + hipGetErrorString(err));
         return err == hipErrorOutOfMemory ? HDG_ERR_OOM : HDG_ERR_HIP;
@@ -479,7 +516,9 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
 
 void free_plan(Plan& P) {
     void* ptrs[] = {P.d_einfo, P.d_tab, P.d_bproj, P.d_face_off, P.d_face_deg, P.d_row_ptr, P.d_col,
-                    P.d_val_off, P.d_diag_off, P.d_hat_row_ptr, P.d_hat_col, P.d_hat_val_off, P.d_hat_src};
+                    P.d_val_off, P.d_diag_off, P.d_hat_row_ptr, P.d_hat_col, P.d_hat_val_off, P.d_hat_src,
+                    P.d_k_rowbase, P.d_k_colbase, P.d_k_xidx, P.d_hat_rowbase, P.d_hat_colbase, P.d_hat_xidx,
+                    P.d_kb_rows};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }

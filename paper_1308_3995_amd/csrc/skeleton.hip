@@ -23,32 +23,37 @@
 
 namespace hdg {
 
-constexpr int kVecBlocks = 256;     // blocks of the vector kernels
-constexpr int kVecThreads = 256;
+
+static int row_blocks(const Plan& p) { return std::max(1, (p.nf + 3) / 4); }
+static int vec_blocks(const Plan& p) {
+    const int64_t n = p.face_off.back();
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 511) / 512));
+}
 
 SolverLayout solver_layout(const Plan& p, int restart) {
     SolverLayout L{};
     const int64_t n = p.face_off.back();
+    const int64_t kmv = restart + 1;
+    const int64_t B1 = row_blocks(p), B2 = vec_blocks(p);
     int64_t off = 0;
     auto carve = [&](int64_t bytes) { int64_t o = off; off += (bytes + 255) / 256 * 256; return o; };
     L.minv = carve(p.diag_off.back() / 2 * 8);
     L.hat = carve(p.hat_values * 8);
     L.hat32 = carve(p.hat_values * 4);
-    L.V = carve((int64_t)(restart + 1) * n * 8);
+    L.V = carve(kmv * n * 8);
     L.w = carve(n * 8);
     L.w2 = carve(n * 8);
     L.x = carve(n * 8);
     L.y = carve(n * 8);
     L.r = carve(n * 8);
-    L.partial = carve((int64_t)kVecBlocks * (restart + 2) * 2 * 8);
-    L.hess = carve((int64_t)((restart + 1) * restart + 4 * (restart + 2)) * 8);
-    L.scal = carve(64 * 8);
+    L.partial = carve(((B1 + B2) * kmv + std::max(B1, B2) + kmv) * 8);
+    L.hess = carve((2 * restart * kmv + 4 * (kmv + 1)) * 8);
+    L.scal = carve(16 * 8);
     L.total = off;
     return L;
 }
 
-// scalar slots
-enum { SC_DONE = 0, SC_BETA0 = 1, SC_RES = 2, SC_SCALE = 3, SC_ITERS = 4, SC_TOL = 5, SC_SINGULAR = 6, SC_JDONE = 7 };
+enum { SC_SINGULAR = 4 };
 
 // ---------------------------------------------------------------------------
 // block Jacobi: invert every face-diagonal block (Gauss-Jordan, partial pivoting)
@@ -128,234 +133,404 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 }
 
 // ---------------------------------------------------------------------------
-// slab SpMV: y_f = [x_f] + sum_b K_fb x_b, x = scale * src. Optionally writes the
-// scaled own rows of src to vout (normalising the previous Krylov vector on the fly).
+// Krylov kernels. Per Arnoldi step j (cnt = j + 1 basis vectors):
+//   k_spmv_dots   y = Khat v_j, v_j = scale * src written on the fly (one wave per face
+//                 row, four rows per block), block partials of V^T y
+//   k_reduce_h    h = sum of the partials (one block per coefficient), H(:, j) = h
+//   k_update_dots w = y - V h, block partials of V^T w          (CGS, first pass)
+//   k_reduce_h    h2, H(:, j) += h2
+//   k_update_norm w = w - V h2, block partials of ||w||^2       (re-orthogonalisation)
+//   k_givens      ||w||, Givens rotation of column j, residual estimate, scale = 1/||w||
+// All sums are fixed-order, so every run gives the same bits.
 // ---------------------------------------------------------------------------
-template <typename VT, bool IDENT>
-__global__ __launch_bounds__(256) void k_spmv(int nf, const int64_t* face_off, const int64_t* rp, const int32_t* col,
-                                              const int64_t* voff, const VT* val, const double* src,
-                                              const double* scal, int scale_slot, double* vout, double* y) {
-    __shared__ double red[4][64];
-    if (scal && scal[SC_DONE] != 0.0) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int f = blockIdx.x * 4 + wave;
-    const double sc = scale_slot >= 0 ? scal[scale_slot] : 1.0;
-    double acc = 0.0;
-    int s = 1, r = 0;
-    int64_t fo = 0;
-    if (f < nf) {
-        fo = face_off[f];
-        s = (int)(face_off[f + 1] - fo);
-        const int nslots = 64 / s;
-        r = lane % s;
-        const int slot = lane / s;
-        if (slot < nslots) {
-            for (int64_t b = rp[f]; b < rp[f + 1]; ++b) {
-                const int g = col[b];
-                const int64_t go = face_off[g];
-                const int sg = (int)(face_off[g + 1] - go);
-                const VT* vb = val + voff[b];
-                for (int c = slot; c < sg; c += nslots) acc += (double)vb[(int64_t)c * s + r] * src[go + c];
-            }
-        }
-    }
-    red[wave][lane] = acc;
-    __syncthreads();
-    if (f < nf && lane < s) {
-        const int nslots = 64 / s;
-        double sum = 0.0;
-        for (int k = 0; k < nslots; ++k) sum += red[wave][k * s + lane];
-        const double xs = src[fo + lane];
-        double out = sc * sum;
-        if (IDENT) out += sc * xs;
-        y[fo + lane] = out;
-        if (vout) vout[fo + lane] = sc * xs;
-    }
-}
+constexpr int kMaxV = kMaxRestart + 1;   // Krylov vectors per cycle
+constexpr int kThreads = 256;
+constexpr int kVecBlocksMax = 1024;
+static_assert(kMaxRestart == 32, "the dot reductions assume 32 accumulators");
 
-// ---------------------------------------------------------------------------
-// vector kernels (grid = kVecBlocks x kVecThreads, each block a contiguous chunk)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum(double v, double* sh) {
+enum { SC_DONE = 0, SC_RES = 1, SC_JDONE = 2, SC_TOL = 3, SC_BETA = 5, SC_SCALE = 6 };
+
+struct GmArgs {
+    int nf;
+    int64_t n;
+    int B1;           // blocks of the row kernels (4 face rows each)
+    int B2;           // blocks of the vector kernels
+    int64_t chunk;    // vector entries per vector-kernel block
+    const int64_t* face_off;
+    const int64_t* rp;      // block pattern of the matrix (row pointers, columns, value offsets)
+    const int32_t* col;
+    const int64_t* voff;
+    double* V;        // (m+1) x n
+    double* y;        // SpMV output
+    double* w;        // orthogonalised vector
+    double* P1;       // [B1][kMaxV]
+    double* P2;       // [B2][kMaxV]
+    double* P3;       // [max(B1, B2)]
+    double* h;        // [kMaxV] last reduced coefficients
+    double* H;        // [m][kMaxV]
+    double* R;        // [m][kMaxV] rotated columns
+    double* cs;
+    double* sn;
+    double* ga;       // residual vector before the rotation of column j
+    double* gb;       // after it
+    double* scal;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum1(double v, double* sh) {
+    v = wave_sum(v);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
     if (lane == 0) sh[wave] = v;
     __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
-    return t;
+    return sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-__device__ __forceinline__ void chunk(int64_t n, int64_t& lo, int64_t& hi) {
-    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    lo = (int64_t)blockIdx.x * per;
-    hi = lo + per < n ? lo + per : n;
+// Recursive-halving wave reduction of NV values (NV a power of two <= 64): after it,
+// lane L holds the wave sum of value index (L >> log2(64 / NV)) -- one shuffle per value
+// and halving step instead of one full butterfly per value.
+template <int NV, int STEP>
+__device__ __forceinline__ void halving_step(double (&v)[NV], int lane) {
+    if constexpr ((NV >> STEP) > 1) {
+        constexpr int half = NV >> (STEP + 1);
+        constexpr int mask = 32 >> STEP;
+        const bool upper = (lane & mask) != 0;
+#pragma unroll
+        for (int t = 0; t < half; ++t) {
+            const double send = upper ? v[t] : v[t + half];
+            const double keep = upper ? v[t + half] : v[t];
+            v[t] = keep + __shfl_xor(send, mask, 64);
+        }
+        halving_step<NV, STEP + 1>(v, lane);
+    }
 }
 
-// Reduce the per-block partials of `cnt` quantities (fixed order).
-__device__ __forceinline__ void reduce_partials(const double* partial, int ld, int cnt, double* out, double* sh) {
-    for (int i = 0; i < cnt; ++i) {
-        double v = 0.0;
-        for (int g = threadIdx.x; g < kVecBlocks; g += blockDim.x) v += partial[(int64_t)g * ld + i];
-        const double t = block_sum(v, sh);
-        if (threadIdx.x == 0) out[i] = t;
+template <int NV>
+__device__ __forceinline__ double wave_reduce_many(double (&v)[NV]) {
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "power of two");
+    const int lane = threadIdx.x & 63;
+    halving_step<NV, 0>(v, lane);
+    // the lanes that share a value index still hold partial sums: finish with a butterfly
+    double r = v[0];
+#pragma unroll
+    for (int mask = 32 / NV; mask >= 1; mask >>= 1) r += __shfl_xor(r, mask, 64);
+    return r;
+}
+
+// One face row of y = src_scaled + Khat src_scaled (IDENT) or K src (no identity) by one wave.
+// Returns this lane's output (valid for lane < s).
+// One face row of y = src_scaled + Khat src_scaled (IDENT) or K src (no identity) by one wave.
+// Returns this lane's output (valid for lane < s).
+// Rows whose own size and every block width equal S (uniform degree) take a fully
+// unrolled path: each lane issues all its loads before the first use.
+template <typename VT, int S>
+__device__ __forceinline__ double row_sum_uniform(const GmArgs& a, const VT* val, const double* src, int f, int lane) {
+    constexpr int NS = 64 / S;                 // column slots
+    constexpr int PER = (S + NS - 1) / NS;     // columns per slot and block
+    const int r = lane % S, slot = lane / S;
+    double sum = 0.0;
+    if (slot < NS) {
+        const int64_t b0 = a.rp[f], nb = a.rp[f + 1] - b0;
+        double v[4 * PER], x[4 * PER];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int c = slot + k * NS;
+                const bool ok = b < nb && c < S;
+                const int64_t bb = b0 + (b < nb ? b : 0);
+                const VT* vb = val + a.voff[bb];
+                const int64_t go = a.face_off[a.col[bb]];
+                v[b * PER + k] = ok ? (double)vb[(int64_t)c * S + r] : 0.0;
+                x[b * PER + k] = ok ? src[go + c] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4 * PER; ++t) sum += v[t] * x[t];
+        for (int64_t b = b0 + 4; b < b0 + nb; ++b) {   // rows with more than four blocks
+            const VT* vb = val + a.voff[b];
+            const int64_t go = a.face_off[a.col[b]];
+            for (int c = slot; c < S; c += NS) sum += (double)vb[(int64_t)c * S + r] * src[go + c];
+        }
+    }
+    return sum;
+}
+
+// One face row of y = src_scaled + Khat src_scaled (IDENT) or K src (no identity) by one wave.
+// Returns this lane's output (valid for lane < s).
+template <typename VT, bool IDENT>
+__device__ __forceinline__ double row_spmv(const GmArgs& a, const VT* val, const double* src, double scale, int f,
+                                           int lane, double* red, double& xv) {
+    const int64_t fo = a.face_off[f];
+    const int s = (int)(a.face_off[f + 1] - fo);
+    const int nslots = 64 / s;
+    const int r = lane % s, slot = lane / s;
+    double sum = 0.0;
+    if (slot < nslots) {
+        for (int64_t b = a.rp[f]; b < a.rp[f + 1]; ++b) {
+            const int64_t go = a.face_off[a.col[b]];
+            const int sg = (int)(a.face_off[a.col[b] + 1] - go);
+            const VT* vb = val + a.voff[b] + r;
+#pragma unroll 4
+            for (int c = slot; c < sg; c += nslots) sum += (double)vb[(int64_t)c * s] * src[go + c];
+        }
+    }
+    red[lane] = sum;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double out = 0.0;
+    xv = 0.0;
+    if (lane < s) {
+        double t = 0.0;
+        for (int k = 0; k < nslots; ++k) t += red[k * s + lane];
+        xv = scale * src[fo + lane];
+        out = IDENT ? scale * t + xv : t;
+    }
+    return out;
+}
+
+template <typename VT, int CNT>
+__global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val, const double* src) {
+    constexpr int cnt = CNT;
+    constexpr int kPerWave = kMaxRestart / 4;   // Krylov vectors per wave in the dot phase
+    __shared__ double red[4][64];
+    __shared__ double yf[4 * 4 * (kMaxDegree + 1)];
+    __shared__ double xf[4 * 4 * (kMaxDegree + 1)];
+    if (a.scal[SC_DONE] != 0.0) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int f0 = blockIdx.x * 4;
+    const int f = f0 + wave;
+    const double scale = a.scal[SC_SCALE];
+    const int j = cnt - 1;
+    double* vj = a.V + (int64_t)j * a.n;
+    const int flast = f0 + 4 < a.nf ? f0 + 4 : a.nf;
+    const int64_t e0 = a.face_off[f0];
+    const int ne = (int)(a.face_off[flast] - e0);
+    if (f < a.nf) {
+        double xv;
+        const double out = row_spmv<VT, true>(a, val, src, scale, f, lane, red[wave], xv);
+        const int64_t fo = a.face_off[f];
+        const int s = (int)(a.face_off[f + 1] - fo);
+        if (lane < s) {
+            a.y[fo + lane] = out;
+            vj[fo + lane] = xv;
+            yf[fo - e0 + lane] = out;
+            xf[fo - e0 + lane] = xv;
+        }
     }
     __syncthreads();
+    // partials of V_i . y over this block's entries; wave w takes i = w + 4 k
+    double acc[kPerWave];
+#pragma unroll
+    for (int k = 0; k < kPerWave; ++k) acc[k] = 0.0;
+    for (int e = lane; e < ne; e += 64) {
+        const double ye = yf[e];
+#pragma unroll
+        for (int k = 0; k < kPerWave; ++k) {
+            const int i = wave + 4 * k;
+            if (i < cnt) acc[k] += ye * ((i == j) ? xf[e] : a.V[(int64_t)i * a.n + e0 + e]);
+        }
+    }
+    const double r = wave_reduce_many<kPerWave>(acc);
+    const int k = lane >> 3;              // 64 / kPerWave lanes share one value index
+    const int i = wave + 4 * k;
+    if ((lane & 7) == 0 && i < cnt) a.P1[(int64_t)i * a.B1 + blockIdx.x] = r;
 }
 
-// partial[g][i] = sum over block chunk of V_i . w, i < cnt
-__global__ __launch_bounds__(256) void k_mdot(int64_t n, const double* V, int cnt, const double* w, double* partial,
-                                              int ld, const double* scal) {
+// h_i = sum_b P[i * B + b] (block i); H(i, j) = h_i or += h_i
+__global__ __launch_bounds__(kThreads) void k_reduce_h(GmArgs a, const double* P, int B, int cnt, int j,
+                                                       int accumulate) {
     __shared__ double sh[8];
-    if (scal[SC_DONE] != 0.0) return;
-    int64_t lo, hi;
-    chunk(n, lo, hi);
-    for (int i = 0; i < cnt; ++i) {
-        const double* v = V + (int64_t)i * n;
-        double acc = 0.0;
-        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) acc += v[k] * w[k];
-        const double s = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ld + i] = s;
+    if (a.scal[SC_DONE] != 0.0) return;
+    const int i = blockIdx.x;
+    const double* Pi = P + (int64_t)i * B;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) v += Pi[b];
+    const double t = block_sum1(v, sh);
+    if (threadIdx.x == 0) {
+        a.h[i] = t;
+        double* hc = a.H + (int64_t)j * kMaxV;
+        hc[i] = accumulate ? hc[i] + t : t;
     }
 }
 
-// h = reduce(partial_in); w -= V h; then either partial_out[g][i] = V_i . w (dots) or
-// partial_out[g][0] = w . w (norm). Block 0 adds h into column j of the Hessenberg matrix.
-template <bool NORM>
-__global__ __launch_bounds__(256) void k_update(int64_t n, const double* V, int cnt, double* w, const double* partial_in,
-                                                double* partial_out, int ld, double* hcol, double* scal) {
+// acc[i], i < cnt <= kMaxRestart, summed over the block into out[i * ld]
+__device__ __forceinline__ void block_sum_vec(double (&acc)[kMaxRestart], int cnt, double* out, int64_t ld,
+                                              double* sh) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double r = wave_reduce_many<kMaxRestart>(acc);
+    if ((lane & 1) == 0) sh[wave * kMaxRestart + (lane >> 1)] = r;
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        const int i = threadIdx.x;
+        out[(int64_t)i * ld] = sh[i] + sh[kMaxRestart + i] + sh[2 * kMaxRestart + i] + sh[3 * kMaxRestart + i];
+    }
+}
+
+// w = y - V h, partials of V^T w (stored i-major: P2[i * B2 + block])
+template <int CNT>
+__global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
+    constexpr int cnt = CNT;
+    __shared__ double sh[4 * kMaxRestart];
+    __shared__ double h[kMaxRestart];
+    if (a.scal[SC_DONE] != 0.0) return;
+    if ((int)threadIdx.x < cnt) h[threadIdx.x] = a.h[threadIdx.x];
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+    const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+    double acc[kMaxRestart];
+#pragma unroll
+    for (int i = 0; i < kMaxRestart; ++i) acc[i] = 0.0;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        double wv = a.y[k];
+#pragma unroll
+        for (int i = 0; i < kMaxRestart; ++i)
+            if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
+        a.w[k] = wv;
+        // second sweep over the same entries (cache hits) for the dot products
+#pragma unroll
+        for (int i = 0; i < kMaxRestart; ++i)
+            if (i < cnt) acc[i] += a.V[(int64_t)i * a.n + k] * wv;
+    }
+    block_sum_vec(acc, cnt, a.P2 + blockIdx.x, a.B2, sh);
+}
+
+// w -= V h2, partials of ||w||^2
+template <int CNT>
+__global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a) {
+    constexpr int cnt = CNT;
     __shared__ double sh[8];
-    __shared__ double h[80];
-    if (scal[SC_DONE] != 0.0) return;
-    reduce_partials(partial_in, ld, cnt, h, sh);
-    if (blockIdx.x == 0)
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) hcol[i] += h[i];
-    int64_t lo, hi;
-    chunk(n, lo, hi);
+    __shared__ double h[kMaxV];
+    if (a.scal[SC_DONE] != 0.0) return;
+    if ((int)threadIdx.x < cnt) h[threadIdx.x] = a.h[threadIdx.x];
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+    const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     double nacc = 0.0;
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-        double v = w[k];
-        for (int i = 0; i < cnt; ++i) v -= h[i] * V[(int64_t)i * n + k];
-        w[k] = v;
-        nacc += v * v;
+        double wv = a.w[k];
+#pragma unroll
+        for (int i = 0; i < kMaxV; ++i)
+            if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
+        a.w[k] = wv;
+        nacc += wv * wv;
     }
-    if (NORM) {
-        const double s = block_sum(nacc, sh);
-        if (threadIdx.x == 0) partial_out[(int64_t)blockIdx.x * ld] = s;
-    } else {
-        for (int i = 0; i < cnt; ++i) {
-            const double* v = V + (int64_t)i * n;
-            double acc = 0.0;
-            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) acc += v[k] * w[k];
-            const double s = block_sum(acc, sh);
-            if (threadIdx.x == 0) partial_out[(int64_t)blockIdx.x * ld + i] = s;
-        }
-    }
+    const double t = block_sum1(nacc, sh);
+    if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
 }
 
-// Arnoldi step end: H[j+1][j] = ||w||, Givens rotation, residual estimate, convergence flag,
-// and the scale 1 / H[j+1][j] used by the next SpMV to normalise w into V_{j+1}.
-__global__ void k_givens(const double* partial, int ld, int j, int m, double* H, double* cs, double* sn, double* g,
-                         double* scal) {
+// ||w|| from the partials, Givens rotation of column j, residual estimate and flags (one block)
+__global__ __launch_bounds__(kThreads) void k_givens(GmArgs a, int j, int B) {
     __shared__ double sh[8];
-    __shared__ double nrm;
-    if (scal[SC_DONE] != 0.0) return;
+    __shared__ double col[kMaxV + 1];
+    __shared__ double rot[2 * kMaxV];
+    if (a.scal[SC_DONE] != 0.0) return;
     double v = 0.0;
-    for (int b = threadIdx.x; b < kVecBlocks; b += blockDim.x) v += partial[(int64_t)b * ld];
-    const double t = block_sum(v, sh);
-    if (threadIdx.x == 0) nrm = sqrt(t);
+    for (int b = threadIdx.x; b < B; b += blockDim.x) v += a.P3[b];
+    const double nrm = sqrt(block_sum1(v, sh));
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = a.H[(int64_t)j * kMaxV + i];
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        rot[2 * i] = a.cs[i];
+        rot[2 * i + 1] = a.sn[i];
+    }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    double* hc = H + (int64_t)j * (m + 1);     // column j, rows 0..j+1
-    hc[j + 1] = nrm;
+    col[j + 1] = nrm;
     for (int i = 0; i < j; ++i) {
-        const double a = hc[i], b = hc[i + 1];
-        hc[i] = cs[i] * a + sn[i] * b;
-        hc[i + 1] = -sn[i] * a + cs[i] * b;
+        const double c = rot[2 * i], s = rot[2 * i + 1];
+        const double x0 = col[i], x1 = col[i + 1];
+        col[i] = c * x0 + s * x1;
+        col[i + 1] = -s * x0 + c * x1;
     }
-    const double a = hc[j], b = hc[j + 1];
-    const double rr = hypot(a, b);
-    const double c = rr > 0.0 ? a / rr : 1.0, s = rr > 0.0 ? b / rr : 0.0;
-    cs[j] = c;
-    sn[j] = s;
-    hc[j] = rr;
-    hc[j + 1] = 0.0;
-    g[j + 1] = -s * g[j];
-    g[j] = c * g[j];
-    const double res = fabs(g[j + 1]);
-    scal[SC_RES] = res;
-    scal[SC_JDONE] = (double)(j + 1);
-    scal[SC_ITERS] += 1.0;
-    scal[SC_SCALE] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    if (res <= scal[SC_TOL] || !(nrm > 0.0) || !isfinite(res)) scal[SC_DONE] = 1.0;
+    const double x0 = col[j], x1 = col[j + 1];
+    const double r = hypot(x0, x1);
+    const double c = r > 0.0 ? x0 / r : 1.0, s = r > 0.0 ? x1 / r : 0.0;
+    col[j] = r;
+    for (int i = 0; i <= j; ++i) a.R[(int64_t)j * kMaxV + i] = col[i];
+    a.cs[j] = c;
+    a.sn[j] = s;
+    const double gj = a.ga[j];
+    a.gb[j] = c * gj;
+    a.ga[j + 1] = -s * gj;
+    const double res = fabs(s * gj);
+    a.scal[SC_RES] = res;
+    a.scal[SC_JDONE] = (double)(j + 1);
+    a.scal[SC_SCALE] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    if (res <= a.scal[SC_TOL] || !(nrm > 0.0) || !isfinite(res)) a.scal[SC_DONE] = 1.0;
 }
 
-// End of a cycle: solve the triangular system H y = g (first jdone columns) into coef.
-__global__ void k_cycle_solve(int m, const double* H, const double* g, double* coef, const double* scal) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int jd = (int)scal[SC_JDONE];
-    for (int i = jd - 1; i >= 0; --i) {
-        double v = g[i];
-        for (int k = i + 1; k < jd; ++k) v -= H[(int64_t)k * (m + 1) + i] * coef[k];
-        coef[i] = v / H[(int64_t)i * (m + 1) + i];
-    }
-    for (int i = jd; i < m + 1; ++i) coef[i] = 0.0;
-}
-
-// u += V coef (cnt vectors)
-__global__ __launch_bounds__(256) void k_combine(int64_t n, const double* V, const double* coef, int cnt, double* u) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    double v = u[k];
-    for (int i = 0; i < cnt; ++i) v += coef[i] * V[(int64_t)i * n + k];
-    u[k] = v;
-}
-
-// r = a - b ; partial norm of r
-__global__ __launch_bounds__(256) void k_sub_norm(int64_t n, const double* a, const double* b, double* r, double* partial,
-                                                  int ld) {
-    __shared__ double sh[8];
-    int64_t lo, hi;
-    chunk(n, lo, hi);
-    double acc = 0.0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-        const double v = a[k] - (b ? b[k] : 0.0);
-        r[k] = v;
-        acc += v * v;
-    }
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * ld] = s;
-}
-
-// start of a cycle: beta = ||r|| (from partials), V_0 = r / beta, g = beta e_1, H = 0.
-__global__ void k_cycle_start(int64_t n, const double* partial, int ld, int m, const double* r, double* V0, double* H,
-                              double* g, double* scal, int first) {
-    __shared__ double sh[8];
-    __shared__ double beta_s;
-    double v = 0.0;
-    for (int b = threadIdx.x; b < kVecBlocks; b += blockDim.x) v += partial[(int64_t)b * ld];
-    const double t = block_sum(v, sh);
-    if (threadIdx.x == 0) beta_s = sqrt(t);
+// End of a cycle: coef = R^-1 gb over the completed columns, u += V coef.
+__global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u) {
+    __shared__ double coef[kMaxV];
+    __shared__ double Rl[kMaxRestart * kMaxV];
+    const int jd = (int)a.scal[SC_JDONE];
+    for (int t = threadIdx.x; t < jd * kMaxV; t += blockDim.x) Rl[t] = a.R[t];
+    for (int t = threadIdx.x; t < jd; t += blockDim.x) coef[t] = a.gb[t];
     __syncthreads();
-    const double beta = beta_s;
-    const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-        V0[k] = r[k] * inv;
-    if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i < (m + 1) * m; i += blockDim.x) H[i] = 0.0;
-        for (int i = threadIdx.x; i < m + 1; i += blockDim.x) g[i] = i == 0 ? beta : 0.0;
-        if (threadIdx.x == 0) {
-            if (first) scal[SC_BETA0] = beta;
-            scal[SC_RES] = beta;
-            scal[SC_JDONE] = 0.0;
-            scal[SC_DONE] = (beta <= scal[SC_TOL]) ? 1.0 : 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = jd - 1; i >= 0; --i) {
+            double v = coef[i];
+            for (int k = i + 1; k < jd; ++k) v -= Rl[k * kMaxV + i] * coef[k];
+            coef[i] = v / Rl[i * kMaxV + i];
         }
     }
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+    const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        double v = u[k];
+        for (int i = 0; i < jd; ++i) v += coef[i] * a.V[(int64_t)i * a.n + k];
+        u[k] = v;
+    }
 }
 
-// x = M^-1 u (block diagonal), one block per face
+// r = r0 - (Khat u + u) [IDENT] or r = r0 - K u; norm partials per block (B1 blocks)
+template <typename VT, bool IDENT>
+__global__ __launch_bounds__(kThreads) void k_resid(GmArgs a, const VT* val, const double* r0, const double* u,
+                                                    double* r) {
+    __shared__ double sh[8];
+    __shared__ double red[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int f = blockIdx.x * 4 + wave;
+    double nacc = 0.0;
+    if (f < a.nf) {
+        double xv;
+        const double out = row_spmv<VT, IDENT>(a, val, u, 1.0, f, lane, red[wave], xv);
+        const int64_t fo = a.face_off[f];
+        const int s = (int)(a.face_off[f + 1] - fo);
+        if (lane < s) {
+            const double v = r0[fo + lane] - out;
+            r[fo + lane] = v;
+            nacc = v * v;
+        }
+    }
+    const double t = block_sum1(nacc, sh);
+    if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
+}
+
+// Start of a cycle: beta = ||r|| (one block); v_0 = r / beta is written by the first SpMV.
+__global__ __launch_bounds__(kThreads) void k_cycle_start(GmArgs a, int B) {
+    __shared__ double sh[8];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < B; b += blockDim.x) v += a.P3[b];
+    const double beta = sqrt(block_sum1(v, sh));
+    if (threadIdx.x == 0) {
+        a.ga[0] = beta;
+        a.scal[SC_RES] = beta;
+        a.scal[SC_BETA] = beta;
+        a.scal[SC_JDONE] = 0.0;
+        a.scal[SC_SCALE] = beta > 0.0 ? 1.0 / beta : 0.0;
+        a.scal[SC_DONE] = (beta <= a.scal[SC_TOL] || !(beta > 0.0)) ? 1.0 : 0.0;
+    }
+}
+
+// x = M^-1 u (block diagonal) or x += M^-1 u; one block per face
 __global__ void k_bj_apply(int nf, const int64_t* face_off, const int64_t* diag_off, const double* minv,
                            const double* u, double* x, int accumulate) {
     const int f = blockIdx.x;
@@ -377,7 +552,7 @@ __global__ void k_fill(int64_t n, double* x, double v) {
 
 __global__ void k_set_scalars(double* scal, double tol) {
     if (threadIdx.x == 0) {
-        for (int i = 0; i < 64; ++i) scal[i] = 0.0;
+        for (int i = 0; i < 16; ++i) scal[i] = 0.0;
         scal[SC_TOL] = tol;
     }
 }
@@ -385,89 +560,123 @@ __global__ void k_set_scalars(double* scal, double tol) {
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
-struct Vecs {
-    double *minv, *hat, *V, *w, *w2, *x, *u, *r, *partial, *H, *cs, *sn, *g, *coef, *scal;
+#define HIPCHK(x)                                                    \
+    do {                                                             \
+        hipError_t e_ = (x);                                         \
+        if (e_ != hipSuccess) {                                      \
+            set_error(std::string("HIP: ") + hipGetErrorString(e_)); \
+            return HDG_ERR_HIP;                                      \
+        }                                                            \
+    } while (0)
+
+// The Arnoldi kernels are instantiated for every basis size so that their loops over the
+// Krylov vectors are branch-free and all loads issue back to back.
+template <typename VT, int C>
+static void launch_step(const GmArgs& a, const VT* hat, const double* src, int cnt, hipStream_t s) {
+    if constexpr (C <= kMaxRestart) {
+        if (cnt != C) {
+            launch_step<VT, C + 1>(a, hat, src, cnt, s);
+            return;
+        }
+        const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
+        const int j = C - 1;
+        hipLaunchKernelGGL((k_spmv_dots<VT, C>), g1, blk, 0, s, a, hat, src);
+        hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P1, a.B1, C, j, 0);
+        hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
+        hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P2, a.B2, C, j, 1);
+        hipLaunchKernelGGL((k_update_norm<C>), g2, blk, 0, s, a);
+        hipLaunchKernelGGL(k_givens, dim3(1), blk, 0, s, a, j, a.B2);
+    }
+}
+
+struct Solver {
+    GmArgs ga;        // preconditioned matrix (identity diagonal not stored)
+    GmArgs gk;        // skeleton matrix K (true residual)
+    double *minv, *hat, *x, *u, *r;
     float* hat32;
 };
 
-#define HIPCHK(x)                                                   \
-    do {                                                            \
-        hipError_t e_ = (x);                                        \
-        if (e_ != hipSuccess) {                                     \
-            set_error(std::string("HIP: ") + hipGetErrorString(e_)); \
-            return HDG_ERR_HIP;                                     \
-        }                                                           \
-    } while (0)
+static Solver make_solver(Plan& p, char* ws) {
+    SolverLayout L = solver_layout(p, kMaxRestart);
+    char* base = ws + p.ws_solver;
+    Solver S{};
+    S.minv = (double*)(base + L.minv);
+    S.hat = (double*)(base + L.hat);
+    S.hat32 = (float*)(base + L.hat32);
+    S.x = (double*)(base + L.x);
+    S.u = (double*)(base + L.y);
+    S.r = (double*)(base + L.r);
+    GmArgs a{};
+    a.nf = p.nf;
+    a.n = p.face_off.back();
+    a.B1 = row_blocks(p);
+    a.B2 = vec_blocks(p);
+    a.chunk = (a.n + a.B2 - 1) / a.B2;
+    a.face_off = p.d_face_off;
+    a.V = (double*)(base + L.V);
+    a.y = (double*)(base + L.w);
+    a.w = (double*)(base + L.w2);
+    double* part = (double*)(base + L.partial);
+    a.P1 = part;
+    a.P2 = a.P1 + (int64_t)a.B1 * kMaxV;
+    a.P3 = a.P2 + (int64_t)a.B2 * kMaxV;
+    a.h = a.P3 + std::max(a.B1, a.B2);
+    double* hs = (double*)(base + L.hess);
+    a.H = hs;
+    a.R = hs + kMaxRestart * kMaxV;
+    a.cs = a.R + kMaxRestart * kMaxV;
+    a.sn = a.cs + (kMaxV + 1);
+    a.ga = a.sn + (kMaxV + 1);
+    a.gb = a.ga + (kMaxV + 1);
+    a.scal = (double*)(base + L.scal);
+    S.gk = a;
+    S.gk.rp = p.d_row_ptr;
+    S.gk.col = p.d_col;
+    S.gk.voff = p.d_val_off;
+    S.ga = a;
+    S.ga.rp = p.d_hat_row_ptr;
+    S.ga.col = p.d_hat_col;
+    S.ga.voff = p.d_hat_val_off;
+    return S;
+}
 
-// ||E - K x|| with the float64 skeleton matrix; result on the host (synchronises).
-static hdg_status true_residual(const Plan& p, const double* bsr, const double* rhs, const double* x, Vecs& v,
-                                int ld, hipStream_t s, double* out) {
-    const int64_t n = p.face_off.back();
-    hipLaunchKernelGGL((k_spmv<double, false>), dim3((p.nf + 3) / 4), dim3(256), 0, s, p.nf, p.d_face_off, p.d_row_ptr,
-                       p.d_col, p.d_val_off, bsr, x, (const double*)nullptr, -1, (double*)nullptr, v.w2);
-    hipLaunchKernelGGL(k_sub_norm, dim3(kVecBlocks), dim3(kVecThreads), 0, s, n, rhs, v.w2, v.r, v.partial, ld);
-    std::vector<double> part((size_t)kVecBlocks * ld);
-    HIPCHK(hipMemcpyAsync(part.data(), v.partial, part.size() * 8, hipMemcpyDeviceToHost, s));
+// ||E - K x|| with the float64 skeleton matrix (synchronises). The residual is left in S.r.
+static hdg_status true_residual(const Plan& p, Solver& S, const double* bsr, const double* rhs, const double* x,
+                                hipStream_t s, double* out) {
+    hipLaunchKernelGGL((k_resid<double, false>), dim3(S.gk.B1), dim3(kThreads), 0, s, S.gk, bsr, rhs, x, S.r);
+    std::vector<double> part(S.gk.B1);
+    HIPCHK(hipMemcpyAsync(part.data(), S.gk.P3, part.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     double t = 0.0;
-    for (int b = 0; b < kVecBlocks; ++b) t += part[(size_t)b * ld];
+    for (double v : part) t += v;
     *out = std::sqrt(t);
     return HDG_OK;
 }
 
-// Restarted GMRES on Khat u = r0 (Khat float64 or float32), accumulating into u.
-// Returns the number of inner iterations performed.
+// Restarted GMRES(m) on Khat u = r0, accumulating into u, until ||r0 - Khat u|| <= abs_tol
+// (recursive estimate) or max_iter inner iterations. One host synchronisation per cycle.
 template <typename VT>
-static hdg_status gmres_khat(const Plan& p, const VT* hat, const double* r0, double* u, int m, int max_iter,
-                             double abs_tol, Vecs& v, int ld, hipStream_t s, int* iters, double* est) {
-    const int64_t n = p.face_off.back();
-    const dim3 sg((p.nf + 3) / 4), sb(256), vg(kVecBlocks), vb(kVecThreads);
+static hdg_status gmres_khat(const Plan& p, Solver& S, const VT* hat, const double* r0, int m, int max_iter,
+                             double abs_tol, hipStream_t s, int* iters, double* est) {
+    GmArgs& a = S.ga;
+    const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
     int total = 0;
-    // r = r0 - Khat u
-    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, v.scal, abs_tol);
     double res = 0.0;
-    for (int cycle = 0; total < max_iter; ++cycle) {
-        hipLaunchKernelGGL((k_spmv<VT, true>), sg, sb, 0, s, p.nf, p.d_face_off, p.d_hat_row_ptr, p.d_hat_col,
-                           p.d_hat_val_off, hat, u, (const double*)nullptr, -1, (double*)nullptr, v.w2);
-        hipLaunchKernelGGL(k_sub_norm, vg, vb, 0, s, n, r0, v.w2, v.r, v.partial, ld);
-        hipLaunchKernelGGL(k_cycle_start, dim3(64), dim3(256), 0, s, n, v.partial, ld, m, v.r, v.V, v.H, v.g, v.scal,
-                           cycle == 0 ? 1 : 0);
+    while (total < max_iter) {
+        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, a.scal, abs_tol);
+        hipLaunchKernelGGL((k_resid<VT, true>), g1, blk, 0, s, a, hat, r0, S.u, S.r);
+        hipLaunchKernelGGL(k_cycle_start, dim3(1), blk, 0, s, a, a.B1);
         const int steps = std::min(m, max_iter - total);
-        for (int j = 0; j < steps; ++j) {
-            double* vj = v.V + (int64_t)j * n;
-            // w = Khat v_j ; v_j was normalised when it was produced
-            if (j == 0) {
-                hipLaunchKernelGGL((k_spmv<VT, true>), sg, sb, 0, s, p.nf, p.d_face_off, p.d_hat_row_ptr, p.d_hat_col,
-                                   p.d_hat_val_off, hat, vj, v.scal, -1, (double*)nullptr, v.w);
-            } else {
-                // previous w (unnormalised) in v.w2; normalise into V_j and multiply
-                hipLaunchKernelGGL((k_spmv<VT, true>), sg, sb, 0, s, p.nf, p.d_face_off, p.d_hat_row_ptr, p.d_hat_col,
-                                   p.d_hat_val_off, hat, v.w2, v.scal, (int)SC_SCALE, vj, v.w);
-            }
-            hipLaunchKernelGGL(k_mdot, vg, vb, 0, s, n, v.V, j + 1, v.w, v.partial, ld, v.scal);
-            double* hcol = v.H + (int64_t)j * (m + 1);
-            hipLaunchKernelGGL((k_update<false>), vg, vb, 0, s, n, v.V, j + 1, v.w, v.partial, v.partial + ld / 2, ld,
-                               hcol, v.scal);
-            hipLaunchKernelGGL((k_update<true>), vg, vb, 0, s, n, v.V, j + 1, v.w, v.partial + ld / 2, v.partial, ld,
-                               hcol, v.scal);
-            hipLaunchKernelGGL(k_givens, dim3(1), dim3(256), 0, s, v.partial, ld, j, m, v.H, v.cs, v.sn, v.g, v.scal);
-            // keep the unnormalised w for the next step's SpMV
-            std::swap(v.w, v.w2);
-        }
-        // the last w sits in v.w2 now; combine the basis into u
-        hipLaunchKernelGGL(k_cycle_solve, dim3(1), dim3(64), 0, s, m, v.H, v.g, v.coef, v.scal);
-        hipLaunchKernelGGL(k_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, v.V, v.coef, m, u);
+        for (int j = 0; j < steps; ++j) launch_step<VT, 1>(a, hat, j == 0 ? S.r : a.w, j + 1, s);
+        hipLaunchKernelGGL(k_cycle_end, g2, blk, 0, s, a, S.u);
+        HIPCHK(hipGetLastError());
         double sc[8];
-        HIPCHK(hipMemcpyAsync(sc, v.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(sc, a.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const int jd = (int)sc[SC_JDONE];
         total += jd;
         res = sc[SC_RES];
-        if (jd == 0) break;                 // converged at the cycle start
-        if (res <= abs_tol) break;
-        if (jd < steps) break;              // breakdown (w = 0): exact solution in the space
-        // reset the done flag for the next cycle
-        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, v.scal, abs_tol);
+        if (jd == 0 || res <= abs_tol || jd < steps) break;
     }
     *iters = total;
     *est = res;
@@ -476,8 +685,8 @@ static hdg_status gmres_khat(const Plan& p, const VT* hat, const double* r0, dou
 
 hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol, int restart,
                           int max_iter, char* ws, hipStream_t s, int* iters_out, double* relres_out) {
-    if (restart < 1 || restart > p.solver_restart_max) {
-        set_error("restart must be in 1.." + std::to_string(p.solver_restart_max));
+    if (restart < 1 || restart > kMaxRestart) {
+        set_error("restart must be in 1.." + std::to_string(kMaxRestart));
         return HDG_ERR_INVALID_ARG;
     }
     const int64_t n = p.face_off.back();
@@ -486,56 +695,27 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
         if (relres_out) *relres_out = 0.0;
         return HDG_OK;
     }
-    SolverLayout L = solver_layout(p, p.solver_restart_max);
-    char* base = ws + p.ws_solver;
-    Vecs v{};
-    v.minv = (double*)(base + L.minv);
-    v.hat = (double*)(base + L.hat);
-    v.hat32 = (float*)(base + L.hat32);
-    v.V = (double*)(base + L.V);
-    v.w = (double*)(base + L.w);
-    v.w2 = (double*)(base + L.w2);
-    v.x = (double*)(base + L.x);
-    v.u = (double*)(base + L.y);
-    v.r = (double*)(base + L.r);
-    v.partial = (double*)(base + L.partial);
-    const int m = restart;
-    double* hs = (double*)(base + L.hess);
-    v.H = hs;
-    v.cs = hs + (m + 1) * m;
-    v.sn = v.cs + (m + 2);
-    v.g = v.sn + (m + 2);
-    v.coef = v.g + (m + 2);
-    v.scal = (double*)(base + L.scal);
-    const int ld = 2 * (p.solver_restart_max + 2);
+    Solver S = make_solver(p, ws);
     const bool mixed = p.prm.precision == HDG_MIXED;
+    const unsigned vblocks = (unsigned)((n + 255) / 256);
 
-    // preconditioner setup
-    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, v.scal, 0.0);
+    // preconditioner: invert the face-diagonal blocks, form Khat = K M^-1
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, S.ga.scal, 0.0);
     hipLaunchKernelGGL(k_bj_invert, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_row_ptr, p.d_val_off,
-                       p.d_diag_off, bsr, v.minv, v.scal);
+                       p.d_diag_off, bsr, S.minv, S.ga.scal);
     hipLaunchKernelGGL(k_hat_build, dim3(p.nf), dim3(256), 0, s, p.nf, p.d_face_off, p.d_hat_row_ptr, p.d_hat_col,
-                       p.d_hat_val_off, p.d_hat_src, p.d_diag_off, bsr, v.minv, v.hat, mixed ? v.hat32 : nullptr);
+                       p.d_hat_val_off, p.d_hat_src, p.d_diag_off, bsr, S.minv, S.hat, mixed ? S.hat32 : nullptr);
     double sing = 0.0;
-    HIPCHK(hipMemcpyAsync(&sing, v.scal + SC_SINGULAR, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&sing, S.ga.scal + SC_SINGULAR, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (sing != 0.0) {
         set_error("singular face-diagonal block in the skeleton matrix");
         return HDG_ERR_SINGULAR_LOCAL;
     }
-    // ||E||
-    double enorm = 0.0;
-    {
-        hipLaunchKernelGGL(k_sub_norm, dim3(kVecBlocks), dim3(kVecThreads), 0, s, n, rhs, (const double*)nullptr, v.r,
-                           v.partial, ld);
-        std::vector<double> part((size_t)kVecBlocks * ld);
-        HIPCHK(hipMemcpyAsync(part.data(), v.partial, part.size() * 8, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int b = 0; b < kVecBlocks; ++b) enorm += part[(size_t)b * ld];
-        enorm = std::sqrt(enorm);
-    }
-    const unsigned vblocks = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, dlam, 0.0);
+    double enorm = 0.0;
+    hdg_status st = true_residual(p, S, bsr, rhs, dlam, s, &enorm);
+    if (st != HDG_OK) return st;
     if (enorm == 0.0) {
         if (iters_out) *iters_out = 0;
         if (relres_out) *relres_out = 0.0;
@@ -544,20 +724,19 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
     const double tol = rtol * enorm;
     int total = 0;
     double relres = 1.0;
-    hdg_status st = HDG_OK;
     if (!mixed) {
-        // GMRES on Khat u = E, dLambda = M^-1 u; restart until the true residual meets tol
-        hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, v.u, 0.0);
+        // GMRES on Khat u = E, dLambda = M^-1 u; continue until the true residual meets tol
+        hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, S.u, 0.0);
         for (int outer = 0; outer < 50 && total < max_iter; ++outer) {
             int it = 0;
             double est = 0.0;
-            st = gmres_khat<double>(p, v.hat, rhs, v.u, m, max_iter - total, tol, v, ld, s, &it, &est);
+            st = gmres_khat<double>(p, S, S.hat, rhs, restart, max_iter - total, tol, s, &it, &est);
             if (st != HDG_OK) return st;
             total += it;
-            hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, v.minv, v.u,
-                               dlam, 0);
+            hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv,
+                               S.u, dlam, 0);
             double tr = 0.0;
-            st = true_residual(p, bsr, rhs, dlam, v, ld, s, &tr);
+            st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
             if (st != HDG_OK) return st;
             relres = tr / enorm;
             if (tr <= tol || it == 0) break;
@@ -566,27 +745,26 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
         // iterative refinement: r = E - K x in float64, inner GMRES on the float32 Khat
         for (int outer = 0; outer < 50 && total < max_iter; ++outer) {
             double tr = 0.0;
-            st = true_residual(p, bsr, rhs, dlam, v, ld, s, &tr);
+            st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
             if (st != HDG_OK) return st;
             relres = tr / enorm;
             if (tr <= tol) break;
-            // v.r holds the residual; copy it aside as the inner right-hand side
-            HIPCHK(hipMemcpyAsync(v.x, v.r, n * 8, hipMemcpyDeviceToDevice, s));
-            hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, v.u, 0.0);
+            HIPCHK(hipMemcpyAsync(S.x, S.r, n * 8, hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, S.u, 0.0);
             int it = 0;
             double est = 0.0;
-            // float32 matrix limits the attainable inner reduction; ask for 1e-6 relative
+            // the float32 matrix bounds the attainable inner reduction near 1e-6
             const double inner_tol = std::max(tol, 1e-6 * tr);
-            st = gmres_khat<float>(p, v.hat32, v.x, v.u, m, max_iter - total, inner_tol, v, ld, s, &it, &est);
+            st = gmres_khat<float>(p, S, S.hat32, S.x, restart, max_iter - total, inner_tol, s, &it, &est);
             if (st != HDG_OK) return st;
             total += it;
-            hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, v.minv, v.u,
-                               dlam, 1);
+            hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv,
+                               S.u, dlam, 1);
             if (it == 0) break;
         }
         if (relres > rtol) {
             double tr = 0.0;
-            st = true_residual(p, bsr, rhs, dlam, v, ld, s, &tr);
+            st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
             if (st != HDG_OK) return st;
             relres = tr / enorm;
         }
