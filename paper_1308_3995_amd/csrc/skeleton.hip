@@ -224,45 +224,6 @@ __device__ __forceinline__ double wave_reduce_many(double (&v)[NV]) {
 
 // One face row of y = src_scaled + Khat src_scaled (IDENT) or K src (no identity) by one wave.
 // Returns this lane's output (valid for lane < s).
-// One face row of y = src_scaled + Khat src_scaled (IDENT) or K src (no identity) by one wave.
-// Returns this lane's output (valid for lane < s).
-// Rows whose own size and every block width equal S (uniform degree) take a fully
-// unrolled path: each lane issues all its loads before the first use.
-template <typename VT, int S>
-__device__ __forceinline__ double row_sum_uniform(const GmArgs& a, const VT* val, const double* src, int f, int lane) {
-    constexpr int NS = 64 / S;                 // column slots
-    constexpr int PER = (S + NS - 1) / NS;     // columns per slot and block
-    const int r = lane % S, slot = lane / S;
-    double sum = 0.0;
-    if (slot < NS) {
-        const int64_t b0 = a.rp[f], nb = a.rp[f + 1] - b0;
-        double v[4 * PER], x[4 * PER];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int c = slot + k * NS;
-                const bool ok = b < nb && c < S;
-                const int64_t bb = b0 + (b < nb ? b : 0);
-                const VT* vb = val + a.voff[bb];
-                const int64_t go = a.face_off[a.col[bb]];
-                v[b * PER + k] = ok ? (double)vb[(int64_t)c * S + r] : 0.0;
-                x[b * PER + k] = ok ? src[go + c] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 4 * PER; ++t) sum += v[t] * x[t];
-        for (int64_t b = b0 + 4; b < b0 + nb; ++b) {   // rows with more than four blocks
-            const VT* vb = val + a.voff[b];
-            const int64_t go = a.face_off[a.col[b]];
-            for (int c = slot; c < S; c += NS) sum += (double)vb[(int64_t)c * S + r] * src[go + c];
-        }
-    }
-    return sum;
-}
-
-// One face row of y = src_scaled + Khat src_scaled (IDENT) or K src (no identity) by one wave.
-// Returns this lane's output (valid for lane < s).
 template <typename VT, bool IDENT>
 __device__ __forceinline__ double row_spmv(const GmArgs& a, const VT* val, const double* src, double scale, int f,
                                            int lane, double* red, double& xv) {
