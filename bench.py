@@ -64,12 +64,23 @@ def main():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        n = (1 << 30) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
+        return
     import hdg_inputs as hi
     import paper_1308_3995_amd as hdg
 
@@ -105,6 +116,14 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms_step = e0.elapsed_time(e1) / args.steps
+        # the same step once more with every launch of the dominant kernel bracketed by HIP
+        # events on its stream (direct launches: events are not recorded inside graph replays)
+        plan.hdg_kernel_timing(reset=True)
+        plan.hdg_set_kernel_timing(True)
+        step()
+        torch.cuda.synchronize()
+        plan.hdg_set_kernel_timing(False)
+        k_launches, k_ms, k_bytes = plan.hdg_kernel_timing(reset=True)
         log(f"[bench] mode {mode}: {ms_step:.3f} ms/step, gmres iters {iters[-1][0]}, relres {iters[-1][1]:.2e}")
         # condensation alone
         reps = max(5, args.steps)
@@ -116,7 +135,10 @@ def main():
         ms_cond = e0.elapsed_time(e1) / reps
         log(f"[bench] mode {mode}: assemble+condense {ms_cond:.3f} ms")
         results[mode] = dict(ms_step=ms_step, ms_condense=ms_cond, gmres_iters=iters[-1][0],
-                             relres=iters[-1][1], n_skel=plan.n_skel)
+                             relres=iters[-1][1], n_skel=plan.n_skel, k_launches=k_launches, k_ms=k_ms,
+                             k_bytes=k_bytes)
+        log(f"[bench] mode {mode}: spmv+dots kernel {k_launches} launches, {k_ms / max(1, k_launches) * 1e3:.2f} us avg, "
+            f"{k_bytes / max(k_ms, 1e-12) / 1e6:.0f} GB/s algorithmic")
         del plan
         torch.cuda.synchronize()
 
@@ -144,6 +166,13 @@ def main():
                       "condense_ms": v["ms_condense"], "condensed_elements_per_s": ne / (v["ms_condense"] / 1e3),
                       "gmres_iters": v["gmres_iters"], "relres": v["relres"]} for m, v in results.items()},
     }
+    kl, kms, kb = r["k_launches"], r["k_ms"], r["k_bytes"]
+    achieved = kb / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    out["roofline"] = {"kernel": "k_spmv_dots (preconditioned skeleton SpMV fused with the first Gram-Schmidt dots)",
+                       "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "launches": kl, "avg_launch_us": kms / max(1, kl) * 1e3,
+                       "bytes_per_launch": kb / max(1, kl)}
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         cb = cpu_baseline()

@@ -181,6 +181,16 @@ hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const doubl
 hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev, int64_t element,
                                     double* X_host, double* y_host, int32_t* n_out, int32_t* f_out);
 
+/* Profiling hook for benchmarks: when enabled, hdg_skeleton_solve brackets every launch
+ * of its dominant kernel (the preconditioned SpMV fused with the first Gram-Schmidt dot
+ * products) with HIP events on the caller's stream and accumulates the launch count, the
+ * summed event time and the algorithmic bytes of those launches (matrix values, the
+ * source, output and new basis vector, and the basis vectors read by the dot products).
+ * hdg_kernel_timing returns and, if reset != 0, clears the totals. */
+hdg_status hdg_set_kernel_timing(hdg_plan* plan, int32_t enable);
+hdg_status hdg_kernel_timing(hdg_plan* plan, int64_t* launches, double* total_ms, double* total_bytes,
+                             int32_t reset);
+
 /* Thread-local description of the last error of the calling thread. */
 const char* hdg_last_error(void);
 

@@ -121,6 +121,15 @@ class HDGPlan:
         check(self.lib.hdg_back_substitute(self.handle, _vp(self.store), _vp(dlam), _vp(dw), _vp(dq), _vp(self.ws),
                                            _stream(stream)))
 
+    # ---- dominant-kernel timing (benchmarks)
+    def hdg_set_kernel_timing(self, enable: bool):
+        check(self.lib.hdg_set_kernel_timing(self.handle, 1 if enable else 0))
+
+    def hdg_kernel_timing(self, reset: bool = True):
+        n, ms, by = C.c_int64(0), C.c_double(0.0), C.c_double(0.0)
+        check(self.lib.hdg_kernel_timing(self.handle, C.byref(n), C.byref(ms), C.byref(by), 1 if reset else 0))
+        return n.value, ms.value, by.value
+
     # ---- inspection (tests)
     def debug_element_blocks(self, element: int, w, lam, q=None):
         n = self.sizes["n_fields"] * 21

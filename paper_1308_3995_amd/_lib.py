@@ -19,7 +19,7 @@ HDG_FP64, HDG_MIXED = 0, 1
 
 EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_pattern", "hdg_assemble_condense",
            "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
-           "hdg_last_error", "hdg_plan_destroy"]
+           "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_last_error", "hdg_plan_destroy"]
 
 
 class HdgParams(C.Structure):
@@ -62,6 +62,8 @@ def load(path: str = LIB_PATH):
     lib.hdg_back_substitute.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_debug_element_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32)]
     lib.hdg_debug_local_solution.argtypes = [vp, vp, i64, vp, vp, P(i32), P(i32)]
+    lib.hdg_set_kernel_timing.argtypes = [vp, i32]
+    lib.hdg_kernel_timing.argtypes = [vp, P(i64), P(dbl), P(dbl), i32]
     lib.hdg_last_error.argtypes = []
     lib.hdg_last_error.restype = C.c_char_p
     lib.hdg_plan_destroy.argtypes = [vp]

@@ -327,4 +327,31 @@ hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev,
     return HDG_OK;
 }
 
+hdg_status hdg_set_kernel_timing(hdg_plan* plan, int32_t enable) {
+    if (!plan) {
+        set_error("hdg_set_kernel_timing: null plan");
+        return HDG_ERR_INVALID_ARG;
+    }
+    plan->p.timing = enable != 0;
+    return HDG_OK;
+}
+
+hdg_status hdg_kernel_timing(hdg_plan* plan, int64_t* launches, double* total_ms, double* total_bytes,
+                             int32_t reset) {
+    if (!plan) {
+        set_error("hdg_kernel_timing: null plan");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (launches) *launches = p.t_launches;
+    if (total_ms) *total_ms = p.t_ms;
+    if (total_bytes) *total_bytes = p.t_bytes;
+    if (reset) {
+        p.t_launches = 0;
+        p.t_ms = 0.0;
+        p.t_bytes = 0.0;
+    }
+    return HDG_OK;
+}
+
 }  // extern "C"

@@ -121,7 +121,17 @@ struct Plan {
     int64_t ws_diag_part = 0, ws_g_part = 0, ws_status = 0, ws_solver = 0, ws_total = 0;
     int64_t hat_values = 0;
     int solver_restart_max = 0;
-    int gmres_groups = 0;
+    // dominant-kernel timing (benchmarks)
+    bool timing = false;
+    int64_t t_launches = 0;
+    double t_ms = 0.0, t_bytes = 0.0;
+    std::vector<hipEvent_t> t_events;
+    // captured GMRES restart cycles (one per matrix precision), replayed with hipGraphLaunch
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t cycle_exec[2] = {nullptr, nullptr};
+    hipGraph_t cycle_graph[2] = {nullptr, nullptr};
+    uint64_t cycle_key[2] = {0, 0};
+    bool use_graphs = true;
 };
 
 // Workspace carving for the skeleton solver (offsets in bytes from ws_solver).

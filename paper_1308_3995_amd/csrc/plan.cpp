@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -236,6 +237,10 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
                       const hdg_params& prm, int device) {
     P.device = device;
     P.prm = prm;
+    {
+        const char* g = std::getenv("HDG_DISABLE_GRAPHS");
+        P.use_graphs = !(g && g[0] && g[0] != '0');
+    }
     P.ns = prm.physics == HDG_NS;
     P.ne = ne;
     P.nv = nv;
@@ -515,6 +520,17 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
 }
 
 void free_plan(Plan& P) {
+    for (hipEvent_t e : P.t_events)
+        if (e) (void)hipEventDestroy(e);
+    P.t_events.clear();
+    for (int i = 0; i < 2; ++i) {
+        if (P.cycle_exec[i]) (void)hipGraphExecDestroy(P.cycle_exec[i]);
+        if (P.cycle_graph[i]) (void)hipGraphDestroy(P.cycle_graph[i]);
+        P.cycle_exec[i] = nullptr;
+        P.cycle_graph[i] = nullptr;
+    }
+    if (P.capture_stream) (void)hipStreamDestroy(P.capture_stream);
+    P.capture_stream = nullptr;
     void* ptrs[] = {P.d_einfo, P.d_tab, P.d_bproj, P.d_face_off, P.d_face_deg, P.d_row_ptr, P.d_col,
                     P.d_val_off, P.d_diag_off, P.d_hat_row_ptr, P.d_hat_col, P.d_hat_val_off, P.d_hat_src,
                     P.d_k_rowbase, P.d_k_colbase, P.d_k_xidx, P.d_hat_rowbase, P.d_hat_colbase, P.d_hat_xidx,

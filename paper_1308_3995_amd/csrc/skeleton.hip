@@ -17,6 +17,7 @@
 // are two-stage and fixed-order (per-block partials, then a redundant reduction by the
 // consumer blocks), so results are deterministic.
 #include <cmath>
+#include <functional>
 #include <vector>
 
 #include "hdg_internal.h"
@@ -533,15 +534,18 @@ __global__ void k_set_scalars(double* scal, double tol) {
 // The Arnoldi kernels are instantiated for every basis size so that their loops over the
 // Krylov vectors are branch-free and all loads issue back to back.
 template <typename VT, int C>
-static void launch_step(const GmArgs& a, const VT* hat, const double* src, int cnt, hipStream_t s) {
+static void launch_step(const GmArgs& a, const VT* hat, const double* src, int cnt, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
     if constexpr (C <= kMaxRestart) {
         if (cnt != C) {
-            launch_step<VT, C + 1>(a, hat, src, cnt, s);
+            launch_step<VT, C + 1>(a, hat, src, cnt, s, e0, e1);
             return;
         }
         const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
         const int j = C - 1;
+        if (e0) (void)hipEventRecord(e0, s);
         hipLaunchKernelGGL((k_spmv_dots<VT, C>), g1, blk, 0, s, a, hat, src);
+        if (e1) (void)hipEventRecord(e1, s);
         hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P1, a.B1, C, j, 0);
         hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
         hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P2, a.B2, C, j, 1);
@@ -617,19 +621,68 @@ static hdg_status true_residual(const Plan& p, Solver& S, const double* bsr, con
 // Restarted GMRES(m) on Khat u = r0, accumulating into u, until ||r0 - Khat u|| <= abs_tol
 // (recursive estimate) or max_iter inner iterations. One host synchronisation per cycle.
 template <typename VT>
-static hdg_status gmres_khat(const Plan& p, Solver& S, const VT* hat, const double* r0, int m, int max_iter,
+static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0, int m, int max_iter,
                              double abs_tol, hipStream_t s, int* iters, double* est) {
+    if (p.timing && (int)p.t_events.size() < 2 * kMaxRestart) {
+        p.t_events.resize(2 * kMaxRestart, nullptr);
+        for (auto& e : p.t_events)
+            if (!e) HIPCHK(hipEventCreate(&e));
+    }
     GmArgs& a = S.ga;
     const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
     int total = 0;
     double res = 0.0;
+    // one restart cycle: reset flags, r = r0 - Khat u, beta, m Arnoldi steps, u += V coef
+    auto enqueue_cycle = [&](hipStream_t q, int steps) {
+        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, q, a.scal, abs_tol);
+        hipLaunchKernelGGL((k_resid<VT, true>), g1, blk, 0, q, a, hat, r0, S.u, S.r);
+        hipLaunchKernelGGL(k_cycle_start, dim3(1), blk, 0, q, a, a.B1);
+        for (int j = 0; j < steps; ++j)
+            launch_step<VT, 1>(a, hat, j == 0 ? S.r : a.w, j + 1, q, p.timing ? p.t_events[2 * j] : nullptr,
+                               p.timing ? p.t_events[2 * j + 1] : nullptr);
+        hipLaunchKernelGGL(k_cycle_end, g2, blk, 0, q, a, S.u);
+    };
+    const int gi = sizeof(VT) == 8 ? 0 : 1;
     while (total < max_iter) {
-        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, a.scal, abs_tol);
-        hipLaunchKernelGGL((k_resid<VT, true>), g1, blk, 0, s, a, hat, r0, S.u, S.r);
-        hipLaunchKernelGGL(k_cycle_start, dim3(1), blk, 0, s, a, a.B1);
         const int steps = std::min(m, max_iter - total);
-        for (int j = 0; j < steps; ++j) launch_step<VT, 1>(a, hat, j == 0 ? S.r : a.w, j + 1, s);
-        hipLaunchKernelGGL(k_cycle_end, g2, blk, 0, s, a, S.u);
+        bool launched = false;
+        // per-launch event timing needs direct launches (events are not recorded inside replays)
+        if (p.use_graphs && !p.timing && steps == m) {
+            // key: every pointer and size baked into the captured kernels
+            uint64_t key = 1469598103934665603ull;
+            auto mix = [&](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+            mix((uint64_t)(uintptr_t)hat);
+            mix((uint64_t)(uintptr_t)r0);
+            mix((uint64_t)(uintptr_t)S.u);
+            mix((uint64_t)(uintptr_t)a.V);
+            mix((uint64_t)(uintptr_t)a.scal);
+            mix((uint64_t)m);
+            mix((uint64_t)std::hash<double>{}(abs_tol));
+            if (!p.cycle_exec[gi] || p.cycle_key[gi] != key) {
+                if (p.cycle_exec[gi]) (void)hipGraphExecDestroy(p.cycle_exec[gi]);
+                if (p.cycle_graph[gi]) (void)hipGraphDestroy(p.cycle_graph[gi]);
+                p.cycle_exec[gi] = nullptr;
+                p.cycle_graph[gi] = nullptr;
+                if (!p.capture_stream) HIPCHK(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
+                hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    enqueue_cycle(p.capture_stream, steps);
+                    e = hipStreamEndCapture(p.capture_stream, &p.cycle_graph[gi]);
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&p.cycle_exec[gi], p.cycle_graph[gi], nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    (void)hipGetLastError();
+                    p.use_graphs = false;          // fall back to direct launches from now on
+                } else {
+                    p.cycle_key[gi] = key;
+                }
+            }
+            if (p.use_graphs && p.cycle_exec[gi]) {
+                HIPCHK(hipGraphLaunch(p.cycle_exec[gi], s));
+                launched = true;
+            }
+        }
+        if (!launched) enqueue_cycle(s, steps);
         HIPCHK(hipGetLastError());
         double sc[8];
         HIPCHK(hipMemcpyAsync(sc, a.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
@@ -637,6 +690,18 @@ static hdg_status gmres_khat(const Plan& p, Solver& S, const VT* hat, const doub
         const int jd = (int)sc[SC_JDONE];
         total += jd;
         res = sc[SC_RES];
+        if (p.timing) {
+            // launches that did work: steps 0..jd-1 (later ones saw the converged flag)
+            const int worked = std::min(steps, jd);
+            for (int j = 0; j < worked; ++j) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, p.t_events[2 * j], p.t_events[2 * j + 1]));
+                p.t_ms += ms;
+                p.t_launches += 1;
+                const double nval = (double)p.hat_values, n = (double)a.n;
+                p.t_bytes += nval * sizeof(VT) + n * 8.0 * 3.0 + (double)(j + 1) * n * 8.0;
+            }
+        }
         if (jd == 0 || res <= abs_tol || jd < steps) break;
     }
     *iters = total;

@@ -280,3 +280,30 @@ def test_c2_full_size_sampled(hdg):
         d = O.elem_dofs(mesh, ob)
         ref = oc.y - oc.X @ x[d]
         assert rel(dwh[e, :, : ref.size // 4].reshape(-1), ref) < tol_resid(ob.A)
+
+
+def test_graph_replays_match_direct_launches(hdg, c1_oracle):
+    """The captured GMRES cycles, replayed across several solves with eager work in between,
+    give the same iterates as direct launches (deterministic kernels: identical bits)."""
+    import os
+    import torch
+    case, step = c1_oracle
+    _say("graph replays vs direct launches")
+    os.environ["HDG_DISABLE_GRAPHS"] = "1"
+    try:
+        eager = hdg.HDGPlan.from_case(case)
+    finally:
+        del os.environ["HDG_DISABLE_GRAPHS"]
+    graph = hdg.HDGPlan.from_case(case)
+    w, lam = _device_state(hdg, eager, case)
+    eager.hdg_assemble_condense(w, lam)
+    ref = torch.zeros(eager.n_skel, dtype=torch.float64, device=eager.device)
+    it_ref, rr_ref, _ = eager.hdg_skeleton_solve(ref, rtol=1e-12, restart=30)
+    for rep in range(3):
+        graph.hdg_assemble_condense(w, lam)
+        torch.cuda.synchronize()
+        got = torch.zeros_like(ref)
+        it, rr, _ = graph.hdg_skeleton_solve(got, rtol=1e-12, restart=30)
+        torch.cuda.synchronize()
+        assert it == it_ref and rr == rr_ref, (rep, it, it_ref, rr, rr_ref)
+        assert torch.equal(got, ref), rep
