@@ -148,7 +148,7 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
                                    (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag, nullptr, -1,
                                    stream);
     if (e == hipErrorInvalidValue) {
-        set_error("hdg_assemble_condense: element degree or face degree outside the built kernels (1..4)");
+        set_error("hdg_assemble_condense: element degree or face degree outside the built kernels (1..5)");
         return HDG_ERR_INVALID_ARG;
     }
     CHECK_HIP(e);

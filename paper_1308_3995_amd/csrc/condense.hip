@@ -87,41 +87,42 @@ __device__ __forceinline__ void wave_argmax(double& v, int& idx) {
     }
 }
 
-template <int P, int PF, bool DBG>
-__global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
+// Phases shared by both condensation kernels: the element state and face traces into LDS
+// (phase 0), weighted flux and flux Jacobian at the volume points (phase 1), and trace
+// fluxes, their Jacobians and the far-field boundary terms at the face points (phase 2).
+template <int P, int PF>
+struct ElemShared {
+    static constexpr int NP = n_modes(P), NPF = PF + 1, Q = n_vol_q(P), QF = PF + 2;
+    double sW[4 * NP];
+    double sLam[3][4][NPF];
+    double sK[Q][2][16];
+    double sF[Q][2][4];
+    double sJA[3][QF][16];
+    double sJB[3][QF][16];
+    double sFH[3][QF][4];
+};
+
+template <int P, int PF>
+__device__ __forceinline__ void point_data(const CondArgs& a, const ElemInfo* E, ElemShared<P, PF>& sh, int tid,
+                                           int nth) {
     constexpr int NP = n_modes(P);
-    constexpr int N = 4 * NP;
     constexpr int NPF = PF + 1;
-    constexpr int F = 12 * NPF;
-    constexpr int NC = N + F + 1;
     constexpr int Q = n_vol_q(P);
-    constexpr int QF = PF + 2;
-    static_assert(N <= 64, "one row per lane");
-    static_assert(Q <= 64, "one volume point per lane");
-
-    __shared__ double sW[4 * NP];
-    __shared__ double sLam[3][4][NPF];
-    __shared__ double sK[Q][2][16];
-    __shared__ double sF[Q][2][4];
-    __shared__ double sJA[3][QF][16];
-    __shared__ double sJB[3][QF][16];
-    __shared__ double sFH[3][QF][4];
-    __shared__ double sRow[2][NC];
-    __shared__ double sX[(F + 1) * N];
-
-    const int lane = threadIdx.x;
-    const int slot = a.start + blockIdx.x;
-    if (DBG && slot != a.debug_slot) return;
-    const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
     const double alpha = a.alpha, gm = a.gamma;
-
+    double* sW = sh.sW;
+    auto& sLam = sh.sLam;
+    auto& sK = sh.sK;
+    auto& sF = sh.sF;
+    auto& sJA = sh.sJA;
+    auto& sJB = sh.sJB;
+    auto& sFH = sh.sFH;
     // ---- phase 0: element state and face traces into LDS
-    for (int t = lane; t < 4 * NP; t += 64) {
+    for (int t = tid; t < 4 * NP; t += nth) {
         const int fa = t / NP, i = t % NP;
         sW[t] = a.w[((int64_t)e * 4 + fa) * a.npmax + i];
     }
-    for (int t = lane; t < 12 * NPF; t += 64) {
+    for (int t = tid; t < 12 * NPF; t += nth) {
         const int lf = t / (4 * NPF), r = t % (4 * NPF), fa = r / NPF, k = r % NPF;
         const int f = E->face[lf];
         double v = 0.0;
@@ -130,8 +131,8 @@ __global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
     }
     __syncthreads();
 
-    // ---- phase 1: volume points (one per lane)
-    if (lane < Q) {
+    // ---- phase 1: volume points
+    for (int lane = tid; lane < Q; lane += nth) {
         double wq[4];
 #pragma unroll
         for (int fa = 0; fa < 4; ++fa) {
@@ -152,8 +153,8 @@ __global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
             for (int c = 0; c < 16; ++c) sK[lane][r][c] = j0 * Ax[c] + j1 * Ay[c];
         }
     }
-    // ---- phase 2: face points (lane = 8 lf + g)
-    if (lane < 24) {
+    // ---- phase 2: face points (t = 8 lf + g)
+    for (int lane = tid; lane < 24; lane += nth) {
         const int lf = lane >> 3, g = lane & 7;
         const int pe = E->pe[lf], nq = pe + 2, o = E->orient[lf];
         if (g < nq) {
@@ -218,6 +219,115 @@ __global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
         }
     }
     __syncthreads();
+
+}
+
+// Phase 6 of both kernels: skeleton rows (local face, field, mode) of
+//   S_K = D_K - C_K X_K,   g_K = r_lam,K - C_K y_K.
+// sX holds [X_K | y_K] column-major with N rows. With DBG the rows of C_K, D_K and r_lam,K
+// are written to the debug buffer instead.
+template <int P, int PF, bool DBG>
+__device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
+                                           const double* sX, int tid, int nth) {
+    constexpr int NP = n_modes(P);
+    constexpr int N = 4 * NP;
+    constexpr int NPF = PF + 1;
+    constexpr int F = 12 * NPF;
+    constexpr int NC = N + F + 1;
+    const double alpha = a.alpha;
+    const auto& sFH = sh.sFH;
+    const auto& sJB = sh.sJB;
+    for (int r = tid; r < F; r += nth) {
+        const int lf = r / (4 * NPF), b = (r / NPF) % 4, k = r % NPF;
+        const int f = E->face[lf], pe = E->pe[lf];
+        if (!DBG && (f < 0 || k > pe)) continue;
+        const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+        const bool valid = f >= 0 && k <= pe;
+        const double hl = 0.5 * E->len[lf];
+        // trace mass T[j] = int_e psi_k phi_j
+        double T[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) T[j] = 0.0;
+        double rl = 0.0;
+        if (valid) {
+            for (int g = 0; g < nq; ++g) {
+                const double pk = a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
+                const double wpk = a.gw[rule * kMaxFaceQ + g] * hl * pk;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) T[j] += wpk * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
+                rl -= pk * sFH[lf][g][b];
+            }
+        }
+        const int se = 4 * (pe + 1);
+        const int row = b * (pe + 1) + k;
+        if (DBG) {
+            // C_K row (field-diagonal trace mass), D_K row, r_lam
+#pragma unroll
+            for (int c2 = 0; c2 < N; ++c2) a.debug[(int64_t)NC * N + (int64_t)c2 * F + r] = (c2 / NP == b) ? alpha * T[c2 % NP] : 0.0;
+        } else {
+            double gy = rl;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) gy -= alpha * T[j] * sX[F * N + b * NP + j];
+            a.g_part[2 * a.face_off[f] + E->side[lf] * se + row] = gy;
+        }
+#pragma unroll
+        for (int c2 = 0; c2 < F; ++c2) {
+            const int lf2 = c2 / (4 * NPF), b2 = (c2 / NPF) % 4, l = c2 % NPF;
+            double dv = 0.0;
+            if (lf2 == lf && valid && l <= pe) {
+                for (int g = 0; g < nq; ++g) {
+                    const double* lg = a.leg + (rule * kMaxFaceQ + g) * (kMaxDegree + 1);
+                    dv += lg[k] * lg[l] * sJB[lf][g][b * 4 + b2];
+                }
+            }
+            if (DBG) {
+                a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)c2 * F + r] = dv;
+                continue;
+            }
+            const int f2 = E->face[lf2], pe2 = E->pe[lf2];
+            if (f2 < 0 || l > pe2) continue;
+            double cx = 0.0;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) cx += T[j] * sX[c2 * N + b * NP + j];
+            const double sv = dv - alpha * cx;
+            const int colc = b2 * (pe2 + 1) + l;
+            if (lf2 == lf) {
+                a.diag_part[a.diag_off[f] + (int64_t)E->side[lf] * se * se + (int64_t)colc * se + row] = sv;
+            } else {
+                a.bsr[E->boff[lf][lf2] + (int64_t)colc * se + row] = sv;
+            }
+        }
+        if (DBG) a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)F * F + r] = rl;
+    }
+}
+
+template <int P, int PF, bool DBG>
+__global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
+    constexpr int NP = n_modes(P);
+    constexpr int N = 4 * NP;
+    constexpr int NPF = PF + 1;
+    constexpr int F = 12 * NPF;
+    constexpr int NC = N + F + 1;
+    constexpr int Q = n_vol_q(P);
+    static_assert(N <= 64, "one row per lane");
+    static_assert(Q <= 64, "one volume point per lane");
+
+    __shared__ ElemShared<P, PF> sh;
+    __shared__ double sRow[2][NC];
+    __shared__ double sX[(F + 1) * N];
+
+    const int lane = threadIdx.x;
+    const int slot = a.start + blockIdx.x;
+    if (DBG && slot != a.debug_slot) return;
+    const ElemInfo* E = a.einfo + slot;
+    const int e = E->elem;
+    point_data<P, PF>(a, E, sh, lane, 64);
+    __syncthreads();
+    const auto& sK = sh.sK;
+    const auto& sF = sh.sF;
+    const auto& sJA = sh.sJA;
+    const auto& sJB = sh.sJB;
+    const auto& sFH = sh.sFH;
 
     // ---- phase 3: row assembly, lane r = fa * NP + i
     double m[NC];
@@ -326,69 +436,144 @@ __global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
         __syncthreads();
     }
 
-    // ---- phase 6: skeleton rows (lf, field, mode): S_K = D_K - C_K X_K, g_K = r_lam - C_K y_K
-    for (int r = lane; r < F; r += 64) {
-        const int lf = r / (4 * NPF), b = (r / NPF) % 4, k = r % NPF;
-        const int f = E->face[lf], pe = E->pe[lf];
-        if (!DBG && (f < 0 || k > pe)) continue;
-        const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
-        const bool valid = f >= 0 && k <= pe;
-        const double hl = 0.5 * E->len[lf];
-        // trace mass T[j] = int_e psi_k phi_j
-        double T[NP];
-#pragma unroll
-        for (int j = 0; j < NP; ++j) T[j] = 0.0;
-        double rl = 0.0;
-        if (valid) {
-            for (int g = 0; g < nq; ++g) {
-                const double pk = a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
-                const double wpk = a.gw[rule * kMaxFaceQ + g] * hl * pk;
-#pragma unroll
-                for (int j = 0; j < NP; ++j) T[j] += wpk * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
-                rl -= pk * sFH[lf][g][b];
+    schur_rows<P, PF, DBG>(a, E, sh, sX, lane, 64);
+}
+
+// Variant for large local blocks (degree 4 and 5: N = 60 or 84 rows, more than one
+// wavefront holds in registers): 256 threads per element, the augmented system
+// [A_K | B_K | r_K] resident in LDS (column-major), assembled entry by entry and eliminated
+// by Gauss-Jordan with partial pivoting (one wave searches the pivot, all threads update).
+template <int P, int PF, bool DBG>
+__global__ __launch_bounds__(256) void k_condense_euler_lds(CondArgs a) {
+    constexpr int NP = n_modes(P);
+    constexpr int N = 4 * NP;
+    constexpr int NPF = PF + 1;
+    constexpr int F = 12 * NPF;
+    constexpr int NC = N + F + 1;
+    constexpr int Q = n_vol_q(P);
+    constexpr int LDM = N + 1;                       // odd leading dimension
+    constexpr bool REUSE = (F + 1) * N <= N * LDM;   // X_K overwrites the dead A_K columns
+    constexpr int NTH = 256;
+
+    __shared__ ElemShared<P, PF> sh;
+    __shared__ double sM[NC * LDM];
+    __shared__ double sXsep[REUSE ? 1 : (F + 1) * N];
+    __shared__ double fmul[N];
+    __shared__ double pvk[N];
+    __shared__ int perm[N];
+    __shared__ int used[N];
+    __shared__ int piv_s;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int slot = a.start + blockIdx.x;
+    if (DBG && slot != a.debug_slot) return;
+    const ElemInfo* E = a.einfo + slot;
+    const int e = E->elem;
+    point_data<P, PF>(a, E, sh, tid, NTH);
+    for (int r = tid; r < N; r += NTH) used[r] = 0;
+    __syncthreads();
+    const auto& sK = sh.sK;
+    const auto& sF = sh.sF;
+    const auto& sJA = sh.sJA;
+    const auto& sJB = sh.sJB;
+    const auto& sFH = sh.sFH;
+
+    // ---- assembly, one entry per thread iteration (consecutive threads: consecutive rows)
+    for (int t = tid; t < NC * N; t += NTH) {
+        const int c = t / N, r = t % N;
+        const int fa = r / NP, ii = r % NP;
+        double v = 0.0;
+        if (c < N) {
+            const int b = c / NP, j = c % NP;
+            for (int q = 0; q < Q; ++q) {
+                const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
+                v -= (g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]) * a.vphi[q * NP + j];
+            }
+            for (int lf = 0; lf < 3; ++lf) {
+                const int nq = E->pe[lf] + 2, o = E->orient[lf];
+                for (int g = 0; g < nq; ++g)
+                    v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJA[lf][g][fa * 4 + b] *
+                         a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
+            }
+        } else if (c < N + F) {
+            const int cf = c - N, lf = cf / (4 * NPF), b = (cf / NPF) % 4, k = cf % NPF;
+            const int pe = E->pe[lf];
+            if (E->face[lf] >= 0 && k <= pe) {
+                const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+                for (int g = 0; g < nq; ++g)
+                    v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJB[lf][g][fa * 4 + b] *
+                         a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
+            }
+        } else {
+            for (int q = 0; q < Q; ++q) {
+                const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
+                v += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
+            }
+            for (int lf = 0; lf < 3; ++lf) {
+                const int nq = E->pe[lf] + 2, o = E->orient[lf];
+                for (int g = 0; g < nq; ++g) v -= a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sFH[lf][g][fa];
             }
         }
-        const int se = 4 * (pe + 1);
-        const int row = b * (pe + 1) + k;
-        if (DBG) {
-            // C_K row (field-diagonal trace mass), D_K row, r_lam
-#pragma unroll
-            for (int c2 = 0; c2 < N; ++c2) a.debug[(int64_t)NC * N + (int64_t)c2 * F + r] = (c2 / NP == b) ? alpha * T[c2 % NP] : 0.0;
-        } else {
-            double gy = rl;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) gy -= alpha * T[j] * sX[F * N + b * NP + j];
-            a.g_part[2 * a.face_off[f] + E->side[lf] * se + row] = gy;
-        }
-#pragma unroll
-        for (int c2 = 0; c2 < F; ++c2) {
-            const int lf2 = c2 / (4 * NPF), b2 = (c2 / NPF) % 4, l = c2 % NPF;
-            double dv = 0.0;
-            if (lf2 == lf && valid && l <= pe) {
-                for (int g = 0; g < nq; ++g) {
-                    const double* lg = a.leg + (rule * kMaxFaceQ + g) * (kMaxDegree + 1);
-                    dv += lg[k] * lg[l] * sJB[lf][g][b * 4 + b2];
+        sM[c * LDM + r] = v;
+        if (DBG) a.debug[(int64_t)c * N + r] = v;
+    }
+    __syncthreads();
+
+    double* sX = REUSE ? sM : sXsep;
+    if (!DBG) {
+        // ---- Gauss-Jordan with partial pivoting (first largest |a| in row order)
+        for (int k = 0; k < N; ++k) {
+            if (wave == 0) {
+                double best = -1.0;
+                int idx = N;
+                for (int r = lane; r < N; r += 64) {
+                    const double v = used[r] ? -1.0 : fabs(sM[k * LDM + r]);
+                    if (v > best) {
+                        best = v;
+                        idx = r;
+                    }
+                }
+                wave_argmax(best, idx);
+                if (lane == 0) {
+                    piv_s = idx;
+                    used[idx] = 1;
+                    perm[k] = idx;
+                    pvk[k] = sM[k * LDM + idx];
                 }
             }
-            if (DBG) {
-                a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)c2 * F + r] = dv;
-                continue;
+            __syncthreads();
+            const int pv_r = piv_s;
+            const double pv = pvk[k];
+            for (int r = tid; r < N; r += NTH) fmul[r] = (r == pv_r) ? 0.0 : sM[k * LDM + r] / pv;
+            __syncthreads();
+            const int ncols = NC - k - 1;
+            for (int t = tid; t < ncols * N; t += NTH) {
+                const int c = k + 1 + t / N, r = t % N;
+                if (r != pv_r) sM[c * LDM + r] -= fmul[r] * sM[c * LDM + pv_r];
             }
-            const int f2 = E->face[lf2], pe2 = E->pe[lf2];
-            if (f2 < 0 || l > pe2) continue;
-            double cx = 0.0;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) cx += T[j] * sX[c2 * N + b * NP + j];
-            const double sv = dv - alpha * cx;
-            const int colc = b2 * (pe2 + 1) + l;
-            if (lf2 == lf) {
-                a.diag_part[a.diag_off[f] + (int64_t)E->side[lf] * se * se + (int64_t)colc * se + row] = sv;
-            } else {
-                a.bsr[E->boff[lf][lf2] + (int64_t)colc * se + row] = sv;
-            }
+            __syncthreads();
         }
-        if (DBG) a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)F * F + r] = rl;
+        // ---- X_K, y_K (row k of the solution sits in row perm[k], scaled by its pivot)
+        const int bslot = slot - a.start;
+        double* st = a.store + (int64_t)bslot * ((F + 1) * N);
+        bool bad = false, singular = false;
+        for (int t = tid; t < (F + 1) * N; t += NTH) {
+            // sX (inside the dead A_K columns when REUSE) and the B/r columns read here are disjoint
+            const int c = t / N, k = t % N;
+            const double pv = pvk[k];
+            const double x = sM[(N + c) * LDM + perm[k]] / pv;
+            singular |= !(fabs(pv) > 0.0);
+            bad |= !isfinite(x);
+            st[c * N + k] = x;
+            sX[c * N + k] = x;
+        }
+        if (bad || singular) {
+            a.status[e] = singular ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+            a.flag[0] = 1;
+        }
+        __syncthreads();
     }
+    schur_rows<P, PF, DBG>(a, E, sh, sX, tid, NTH);
 }
 
 // Sum the two diagonal contributions of every face in a fixed order and the two halves
@@ -423,10 +608,10 @@ __global__ __launch_bounds__(64) void k_backsub_euler(const ElemInfo* einfo, int
     }
     __syncthreads();
     const double* st = store + (int64_t)blockIdx.x * ((F + 1) * N);
-    if (lane < N) {
-        double v = st[F * N + lane];
-        for (int c = 0; c < F; ++c) v -= st[c * N + lane] * sL[c];
-        sD[lane] = v;
+    for (int r = lane; r < N; r += 64) {
+        double v = st[F * N + r];
+        for (int c = 0; c < F; ++c) v -= st[c * N + r] * sL[c];
+        sD[r] = v;
     }
     __syncthreads();
     const int e = E->elem;
@@ -436,6 +621,8 @@ __global__ __launch_bounds__(64) void k_backsub_euler(const ElemInfo* einfo, int
     }
 }
 
+// Degrees up to 3 take the register kernel (one wavefront per element); degrees 4 and 5
+// take the LDS-resident kernel.
 template <int P, int PF>
 static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, hipStream_t s) {
     a.vphi = p.d_tab + p.tix.vol_phi[P];
@@ -443,25 +630,36 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.vw = p.d_tab + p.tix.vol_w[P];
     a.fphi = p.d_tab + p.tix.face_phi[P];
     a.start = bk.start;
-    if (dbg)
-        hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(64), 0, s, a);
+    if constexpr (P <= 3) {
+        if (dbg)
+            hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(64), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(64), 0, s, a);
+    } else {
+        if (dbg)
+            hipLaunchKernelGGL((k_condense_euler_lds<P, PF, true>), dim3(bk.count), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_condense_euler_lds<P, PF, false>), dim3(bk.count), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
+
+#define HDG_BUCKETS(X)                                          \
+    X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(1, 5)                     \
+    X(2, 2) X(2, 3) X(2, 4) X(2, 5)                             \
+    X(3, 3) X(3, 4) X(3, 5)                                     \
+    X(4, 4) X(4, 5)                                             \
+    X(5, 5)
 
 static hipError_t dispatch_condense(const Plan& p, const Bucket& bk, const CondArgs& a, bool dbg, hipStream_t s) {
 #define HDG_CASE(PP, FF) \
     if (bk.p == PP && bk.pf == FF) return launch_bucket<PP, FF>(p, bk, a, dbg, s);
-    HDG_CASE(1, 1) HDG_CASE(1, 2) HDG_CASE(1, 3) HDG_CASE(1, 4)
-    HDG_CASE(2, 2) HDG_CASE(2, 3) HDG_CASE(2, 4)
-    HDG_CASE(3, 3) HDG_CASE(3, 4)
-    HDG_CASE(4, 4)
+    HDG_BUCKETS(HDG_CASE)
 #undef HDG_CASE
     return hipErrorInvalidValue;
 }
 
-static bool bucket_supported(const Bucket& bk) { return bk.p >= 1 && bk.p <= 4 && bk.pf >= bk.p && bk.pf <= 4; }
+static bool bucket_supported(const Bucket& bk) { return bk.p >= 1 && bk.p <= 5 && bk.pf >= bk.p && bk.pf <= 5; }
 
 hipError_t launch_condense(const Plan& p, const double* w, const double* q, const double* lam, double* bsr,
                            double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag,
@@ -517,10 +715,7 @@ hipError_t launch_back_substitute(const Plan& p, const double* store, const doub
                            store + bk.store_off, p.d_face_off, dlam, dw, p.npmax);                          \
         continue;                                                                                           \
     }
-        HDG_CASE(1, 1) HDG_CASE(1, 2) HDG_CASE(1, 3) HDG_CASE(1, 4)
-        HDG_CASE(2, 2) HDG_CASE(2, 3) HDG_CASE(2, 4)
-        HDG_CASE(3, 3) HDG_CASE(3, 4)
-        HDG_CASE(4, 4)
+        HDG_BUCKETS(HDG_CASE)
 #undef HDG_CASE
     }
     return hipGetLastError();

@@ -45,9 +45,20 @@ def _tiny_hp(seed=3):
     return hi.make_case("euler", 4, [1, 2, 3, 4], 0.6, 1.5, 2e-2, seed=seed)
 
 
-@pytest.mark.parametrize("which", ["c1", "hp"])
+def _tiny_hp5(seed=4):
+    """Degrees 3..5: exercises the LDS-resident kernel (degree 4, 5) and face degree 5."""
+    return hi.make_case("euler", 3, [3, 4, 5], 0.8, 1.25, 5e-2, seed=seed)
+
+
+def _case(which):
+    if which == "c1":
+        return hi.config_case("c1")
+    return _tiny_hp() if which == "hp" else _tiny_hp5()
+
+
+@pytest.mark.parametrize("which", ["c1", "hp", "hp5"])
 def test_plan_faces_match_oracle(hdg, which):
-    case = hi.config_case("c1") if which == "c1" else _tiny_hp()
+    case = _case(which)
     _say(f"plan faces {which}")
     plan = hdg.HDGPlan.from_case(case)
     mesh = O.Mesh(case, O.make_physics(case))
@@ -57,9 +68,9 @@ def test_plan_faces_match_oracle(hdg, which):
     assert plan.sizes["n_boundary_faces"] == int((mesh.elem_faces < 0).sum())
 
 
-@pytest.mark.parametrize("which", ["c1", "hp"])
+@pytest.mark.parametrize("which", ["c1", "hp", "hp5"])
 def test_element_blocks_match_oracle(hdg, which):
-    case = hi.config_case("c1") if which == "c1" else _tiny_hp()
+    case = _case(which)
     _say(f"element blocks {which}")
     plan = hdg.HDGPlan.from_case(case)
     w, lam = _device_state(hdg, plan, case)
@@ -81,12 +92,12 @@ def c1_oracle():
     return case, O.newton_step(case)
 
 
-@pytest.mark.parametrize("which", ["c1", "hp"])
+@pytest.mark.parametrize("which", ["c1", "hp", "hp5"])
 def test_condensation_matches_oracle(hdg, which, c1_oracle):
     if which == "c1":
         case, step = c1_oracle
     else:
-        case = _tiny_hp()
+        case = _case(which)
         step = O.newton_step(case)
     _say(f"condense {which}")
     plan = hdg.HDGPlan.from_case(case)
@@ -106,13 +117,13 @@ def test_condensation_matches_oracle(hdg, which, c1_oracle):
     assert rel(plan.rhs.cpu().numpy(), step.E) < TOL
 
 
-@pytest.mark.parametrize("which", ["c1", "hp"])
+@pytest.mark.parametrize("which", ["c1", "hp", "hp5"])
 def test_skeleton_solve_meets_fp64_gate(hdg, which, c1_oracle):
     import torch
     if which == "c1":
         case, step = c1_oracle
     else:
-        case = _tiny_hp()
+        case = _case(which)
         step = O.newton_step(case)
     _say(f"skeleton solve {which}")
     plan = hdg.HDGPlan.from_case(case)
@@ -128,14 +139,14 @@ def test_skeleton_solve_meets_fp64_gate(hdg, which, c1_oracle):
     assert rel(x, step.dlam) < 1e-9
 
 
-@pytest.mark.parametrize("which", ["c1", "hp"])
+@pytest.mark.parametrize("which", ["c1", "hp", "hp5"])
 def test_back_substitution_matches_oracle(hdg, which, c1_oracle):
     """Given the oracle's dLambda, the reconstruction agrees to 1e-12."""
     import torch
     if which == "c1":
         case, step = c1_oracle
     else:
-        case = _tiny_hp()
+        case = _case(which)
         step = O.newton_step(case)
     _say(f"back substitute {which}")
     plan = hdg.HDGPlan.from_case(case)
@@ -307,3 +318,49 @@ def test_graph_replays_match_direct_launches(hdg, c1_oracle):
         torch.cuda.synchronize()
         assert it == it_ref and rr == rr_ref, (rep, it, it_ref, rr, rr_ref)
         assert torch.equal(got, ref), rep
+
+
+def test_c3_hp_full_size_sampled(hdg):
+    """The 128x128 hp workload (degrees 1..5, 32768 elements): sampled local solutions against
+    the oracle for every degree, and the skeleton solve's residual recomputed on the CPU."""
+    import scipy.sparse as sp
+    import torch
+    case = hi.config_case("c3")
+    _say("c3 full size")
+    plan = hdg.HDGPlan.from_case(case)
+    assert plan.sizes["n_buckets"] >= 10
+    w, lam = _device_state(hdg, plan, case)
+    plan.hdg_assemble_condense(w, lam)
+    torch.cuda.synchronize()
+    mesh = O.Mesh(case, O.make_physics(case))
+    st = O.State(mesh, case.W, case.lam)
+    rng = np.random.default_rng(1)
+    sample = []
+    for p in range(1, 6):
+        idx = np.flatnonzero(case.degree == p)
+        sample += rng.choice(idx, 3, replace=False).tolist()
+    for e in sample:
+        ob = O.element_blocks(st, e)
+        oc = O.condense(ob)
+        X, y = plan.debug_local_solution(e)
+        assert rel(X, oc.X) < TOL, (e, case.degree[e], rel(X, oc.X))
+        assert rel(y, oc.y) < tol_resid(ob.A), (e, case.degree[e], rel(y, oc.y))
+    dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=plan.device)
+    it, relres, _ = plan.hdg_skeleton_solve(dlam, rtol=1e-10, restart=30)
+    _say(f"  c3 gmres iters {it} relres {relres:.3e}")
+    rp, col, voff = plan.pattern()
+    vals = plan.bsr.cpu().numpy()
+    n = plan.n_skel
+    rows, cols, data = [], [], []
+    for f in range(len(plan.face_degree)):
+        f0, f1 = plan.face_offset[f], plan.face_offset[f + 1]
+        for k in range(rp[f], rp[f + 1]):
+            g = col[k]
+            g0, g1 = plan.face_offset[g], plan.face_offset[g + 1]
+            blk = vals[voff[k]: voff[k] + (f1 - f0) * (g1 - g0)].reshape(g1 - g0, f1 - f0).T
+            rr, cc = np.meshgrid(np.arange(f0, f1), np.arange(g0, g1), indexing="ij")
+            rows.append(rr.ravel()); cols.append(cc.ravel()); data.append(blk.ravel())
+    K = sp.csr_matrix((np.concatenate(data), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    E = plan.rhs.cpu().numpy()
+    x = dlam.cpu().numpy()
+    assert relres <= 1e-10 and np.linalg.norm(E - K @ x) / np.linalg.norm(E) <= 2e-10
