@@ -30,6 +30,74 @@ struct hdg_plan {
         }                                                                   \
     } while (0)
 
+
+// Navier-Stokes inspection: run the assembly kernel for one element and rebuild the
+// uncondensed blocks (gradient unknowns first) from Z, L = [A_wq; C_q], R = [G_qw | B_q | r_q].
+static hdg_status debug_blocks_ns(Plan& p, int64_t element, const double* w, const double* q, const double* lam,
+                                  double* A_host, double* B_host, double* C_host, double* D_host, double* r_host,
+                                  double* rl_host, int32_t* n_out, int32_t* f_out) {
+    const int slot = p.slot_of_elem[element];
+    const ElemInfo& ei = p.einfo[slot];
+    int bi = 0;
+    while (!(slot >= p.buckets[bi].start && slot < p.buckets[bi].start + p.buckets[bi].count)) ++bi;
+    const Bucket& bk = p.buckets[bi];
+    const int np = n_modes(bk.p), N = 4 * np, NQ = 8 * np, NPF = bk.pf + 1, F = 12 * NPF;
+    const int NR = N + F, NCZ = N + F + 1;
+    const int64_t per = ns_workspace_per_element(bk.p, bk.pf);
+    CHECK_HIP(hipSetDevice(p.device));
+    double* buf = nullptr;
+    CHECK_HIP(hipMalloc((void**)&buf, per * 8));
+    hipError_t e = launch_ns(p, w, q, lam, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, buf, per, slot, 0);
+    std::vector<double> h(per);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(h.data(), buf, per * 8, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (e != hipSuccess) {
+        set_error(std::string("debug launch: ") + hipGetErrorString(e));
+        return HDG_ERR_HIP;
+    }
+    const double* Z = h.data();
+    const double* L = Z + (int64_t)NR * NCZ;
+    const double* R = L + (int64_t)NR * NQ;
+    auto z = [&](int r, int c) { return Z[(int64_t)c * NR + r]; };
+    auto l = [&](int r, int c) { return L[(int64_t)c * NR + r]; };
+    auto rr = [&](int r, int c) { return R[(int64_t)c * NQ + r]; };
+    std::vector<int> fmap;
+    for (int lf = 0; lf < 3; ++lf) {
+        if (ei.face[lf] < 0) continue;
+        for (int b = 0; b < 4; ++b)
+            for (int k = 0; k <= ei.pe[lf]; ++k) fmap.push_back((lf * 4 + b) * NPF + k);
+    }
+    const int f = (int)fmap.size(), n = NQ + N;
+    if (n_out) *n_out = n;
+    if (f_out) *f_out = f;
+    // element unknowns: q rows/columns 0..NQ-1, then w
+    if (A_host)
+        for (int c = 0; c < n; ++c)
+            for (int r = 0; r < n; ++r) {
+                double v;
+                if (r < NQ && c < NQ) v = r == c ? ei.detj : 0.0;
+                else if (r < NQ) v = rr(r, c - NQ);
+                else if (c < NQ) v = l(r - NQ, c);
+                else v = z(r - NQ, c - NQ);
+                A_host[(int64_t)c * n + r] = v;
+            }
+    if (B_host)
+        for (int c = 0; c < f; ++c)
+            for (int r = 0; r < n; ++r) B_host[(int64_t)c * n + r] = r < NQ ? rr(r, N + fmap[c]) : z(r - NQ, N + fmap[c]);
+    if (C_host)
+        for (int c = 0; c < n; ++c)
+            for (int r = 0; r < f; ++r) C_host[(int64_t)c * f + r] = c < NQ ? l(N + fmap[r], c) : z(N + fmap[r], c - NQ);
+    if (D_host)
+        for (int c = 0; c < f; ++c)
+            for (int r = 0; r < f; ++r) D_host[(int64_t)c * f + r] = z(N + fmap[r], N + fmap[c]);
+    if (r_host)
+        for (int r = 0; r < n; ++r) r_host[r] = r < NQ ? rr(r, NCZ - 1) : z(r - NQ, NCZ - 1);
+    if (rl_host)
+        for (int r = 0; r < f; ++r) rl_host[r] = z(N + fmap[r], NCZ - 1);
+    return HDG_OK;
+}
+
 extern "C" {
 
 const char* hdg_last_error(void) { return g_err.c_str(); }
@@ -134,19 +202,18 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
         set_error("hdg_assemble_condense: Navier-Stokes needs the gradient unknowns q");
         return HDG_ERR_INVALID_ARG;
     }
-    if (p.ns) {
-        set_error("hdg_assemble_condense: Navier-Stokes condensation is not built in this library");
-        return HDG_ERR_INVALID_ARG;
-    }
     char* ws = (char*)workspace_dev;
     int32_t* status = elem_status_dev ? elem_status_dev : (int32_t*)(ws + p.ws_status);
     int32_t* flag = (int32_t*)(ws + p.ws_status) + p.ne;
     CHECK_HIP(hipSetDevice(p.device));
     CHECK_HIP(hipMemsetAsync(status, 0, (size_t)p.ne * 4, stream));
     CHECK_HIP(hipMemsetAsync(flag, 0, 4, stream));
-    hipError_t e = launch_condense(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
-                                   (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag, nullptr, -1,
-                                   stream);
+    hipError_t e = p.ns ? launch_ns(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
+                                    (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag,
+                                    (double*)(ws + p.ws_ns), p.ns_zcap, -1, stream)
+                        : launch_condense(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
+                                          (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag,
+                                          nullptr, -1, stream);
     if (e == hipErrorInvalidValue) {
         set_error("hdg_assemble_condense: element degree or face degree outside the built kernels (1..5)");
         return HDG_ERR_INVALID_ARG;
@@ -230,10 +297,12 @@ hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const doubl
         set_error("element out of range");
         return HDG_ERR_INVALID_ARG;
     }
-    if (p.ns) {
-        set_error("hdg_debug_element_blocks: Navier-Stokes is not built in this library");
+    if (p.ns && !q_dev) {
+        set_error("hdg_debug_element_blocks: Navier-Stokes needs q");
         return HDG_ERR_INVALID_ARG;
     }
+    if (p.ns) return debug_blocks_ns(p, element, w_dev, q_dev, lam_dev, A_host, B_host, C_host, D_host, r_host,
+                                     rl_host, n_out, f_out);
     const int slot = p.slot_of_elem[element];
     const ElemInfo& ei = p.einfo[slot];
     int bi = 0;
@@ -304,7 +373,7 @@ hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev,
     int bi = 0;
     while (!(slot >= p.buckets[bi].start && slot < p.buckets[bi].start + p.buckets[bi].count)) ++bi;
     const Bucket& bk = p.buckets[bi];
-    const int np = n_modes(bk.p), N = 4 * np, NPF = bk.pf + 1, F = 12 * NPF;
+    const int np = n_modes(bk.p), N = (p.ns ? 12 : 4) * np, NPF = bk.pf + 1, F = 12 * NPF;
     const int64_t per = (int64_t)(F + 1) * N;
     std::vector<double> h(per);
     CHECK_HIP(hipSetDevice(p.device));

@@ -590,14 +590,16 @@ __global__ void k_diag_sum(int nf, const int64_t* face_off, const int64_t* diag_
     for (int64_t t = threadIdx.x; t < s; t += blockDim.x) rhs[face_off[f] + t] = g0[t] + g0[s + t];
 }
 
-// Reconstruction dU_K = y_K - X_K dLambda_K (Sec. 3.4), one wave per element.
-template <int P, int PF>
-__global__ __launch_bounds__(64) void k_backsub_euler(const ElemInfo* einfo, int start, const double* store,
-                                                      const int64_t* face_off, const double* dlam, double* dw,
-                                                      int npmax) {
-    constexpr int NP = n_modes(P), N = 4 * NP, NPF = PF + 1, F = 12 * NPF;
+// Reconstruction dU_K = y_K - X_K dLambda_K (Sec. 3.4), one wave per element. The store
+// holds [X_K | y_K] column-major with MLOC Np rows (Navier-Stokes: the 8 gradient fields
+// first, then the 4 conserved fields).
+template <int P, int PF, int MLOC>
+__global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start, const double* store,
+                                                const int64_t* face_off, const double* dlam, double* dw, double* dq,
+                                                int npmax) {
+    constexpr int NP = n_modes(P), NALL = MLOC * NP, NPF = PF + 1, F = 12 * NPF;
     __shared__ double sL[F];
-    __shared__ double sD[N];
+    __shared__ double sD[NALL];
     const int lane = threadIdx.x;
     const int slot = start + blockIdx.x;
     const ElemInfo* E = einfo + slot;
@@ -607,18 +609,24 @@ __global__ __launch_bounds__(64) void k_backsub_euler(const ElemInfo* einfo, int
         sL[c] = (f >= 0 && k <= E->pe[lf]) ? dlam[face_off[f] + b * (E->pe[lf] + 1) + k] : 0.0;
     }
     __syncthreads();
-    const double* st = store + (int64_t)blockIdx.x * ((F + 1) * N);
-    for (int r = lane; r < N; r += 64) {
-        double v = st[F * N + r];
-        for (int c = 0; c < F; ++c) v -= st[c * N + r] * sL[c];
+    const double* st = store + (int64_t)blockIdx.x * ((F + 1) * NALL);
+    for (int r = lane; r < NALL; r += 64) {
+        double v = st[(int64_t)F * NALL + r];
+        for (int c = 0; c < F; ++c) v -= st[(int64_t)c * NALL + r] * sL[c];
         sD[r] = v;
     }
     __syncthreads();
     const int e = E->elem;
+    constexpr int WOFF = (MLOC - 4) * NP;   // first conserved-field row
     for (int t = lane; t < 4 * npmax; t += 64) {
         const int fa = t / npmax, i = t % npmax;
-        dw[(int64_t)e * 4 * npmax + t] = i < NP ? sD[fa * NP + i] : 0.0;
+        dw[(int64_t)e * 4 * npmax + t] = i < NP ? sD[WOFF + fa * NP + i] : 0.0;
     }
+    if (MLOC == 12)
+        for (int t = lane; t < 8 * npmax; t += 64) {
+            const int fa = t / npmax, i = t % npmax;
+            dq[(int64_t)e * 8 * npmax + t] = i < NP ? sD[fa * NP + i] : 0.0;
+        }
 }
 
 // Degrees up to 3 take the register kernel (one wavefront per element); degrees 4 and 5
@@ -706,14 +714,19 @@ hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double*
 
 hipError_t launch_back_substitute(const Plan& p, const double* store, const double* dlam, double* dw, double* dq,
                                   hipStream_t s) {
-    (void)dq;
     for (const Bucket& bk : p.buckets) {
         if (!bucket_supported(bk)) return hipErrorInvalidValue;
-#define HDG_CASE(PP, FF)                                                                                    \
-    if (bk.p == PP && bk.pf == FF) {                                                                        \
-        hipLaunchKernelGGL((k_backsub_euler<PP, FF>), dim3(bk.count), dim3(64), 0, s, p.d_einfo, bk.start, \
-                           store + bk.store_off, p.d_face_off, dlam, dw, p.npmax);                          \
-        continue;                                                                                           \
+#define HDG_CASE(PP, FF)                                                                                        \
+    if (bk.p == PP && bk.pf == FF) {                                                                            \
+        if (p.ns) {                                                                                             \
+            if constexpr (PP <= 4 && FF <= 4)                                                                   \
+                hipLaunchKernelGGL((k_backsub<PP, FF, 12>), dim3(bk.count), dim3(64), 0, s, p.d_einfo, bk.start, \
+                                   store + bk.store_off, p.d_face_off, dlam, dw, dq, p.npmax);                  \
+        } else {                                                                                                \
+            hipLaunchKernelGGL((k_backsub<PP, FF, 4>), dim3(bk.count), dim3(64), 0, s, p.d_einfo, bk.start,      \
+                               store + bk.store_off, p.d_face_off, dlam, dw, dq, p.npmax);                      \
+        }                                                                                                       \
+        continue;                                                                                               \
     }
         HDG_BUCKETS(HDG_CASE)
 #undef HDG_CASE

@@ -119,6 +119,7 @@ struct Plan {
 
     // workspace layout (offsets in bytes)
     int64_t ws_diag_part = 0, ws_g_part = 0, ws_status = 0, ws_solver = 0, ws_total = 0;
+    int64_t ws_ns = 0, ns_zcap = 0;       // Navier-Stokes assembly chunk workspace (doubles)
     int64_t hat_values = 0;
     int solver_restart_max = 0;
     // dominant-kernel timing (benchmarks)
@@ -148,6 +149,10 @@ hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double*
                            double* rhs, hipStream_t s);
 hipError_t launch_back_substitute(const Plan& p, const double* store, const double* dlam, double* dw,
                                   double* dq, hipStream_t s);
+hipError_t launch_ns(const Plan& p, const double* w, const double* q, const double* lam, double* bsr,
+                     double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag, double* zbuf,
+                     int64_t zcap_doubles, int only_slot, hipStream_t s);
+int64_t ns_workspace_per_element(int p, int pf);
 hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol,
                           int restart, int max_iter, char* ws, hipStream_t s, int* iters, double* relres);
 

@@ -486,6 +486,22 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     P.ws_diag_part = carve(P.diag_off.back() * 8);
     P.ws_g_part = carve(2 * P.face_off.back() * 8);
     P.ws_status = carve(((int64_t)ne + 64) * 4);
+    if (P.ns) {
+        for (const Bucket& b : P.buckets)
+            if (b.p > 4 || b.pf > 4) {
+                set_error("Navier-Stokes supports element and face degrees up to 4");
+                return HDG_ERR_INVALID_ARG;
+            }
+        int64_t need = 0, per_max = 0;
+        for (const Bucket& b : P.buckets) {
+            const int64_t per = ns_workspace_per_element(b.p, b.pf);
+            need = std::max(need, per * b.count);
+            per_max = std::max(per_max, per);
+        }
+        const int64_t cap = std::max<int64_t>(per_max, (int64_t)1 << 28);   // 2 GiB of chunk workspace
+        P.ns_zcap = std::min(need, cap);
+        P.ws_ns = carve(P.ns_zcap * 8);
+    }
     P.ws_solver = off;
     off += solver_layout(P, P.solver_restart_max).total;
     P.ws_total = off;

@@ -1,0 +1,140 @@
+"""GPU parity of the Navier-Stokes path (gradient unknowns eliminated on the device) against
+the CPU oracle, which builds the full (q, w) local system by complex-step differentiation."""
+import sys
+
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+from oracle import hdg_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+RESID_ROUNDING = 1e-13   # float64 rounding of a smooth-state residual, amplified by kappa(A_K)
+
+
+def tol_resid(A) -> float:
+    return TOL + np.linalg.cond(A) * RESID_ROUNDING
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return O.relative_error(a, b)
+
+
+CASES = {
+    "ns23": dict(physics="ns", ng=3, degrees=[2, 3], mach=0.5, aoa_deg=1.0, amp=2e-2, seed=21, reynolds=200.0),
+    "ns14": dict(physics="ns", ng=3, degrees=[1, 2, 3, 4], mach=0.6, aoa_deg=-2.0, amp=2e-2, seed=22,
+                 reynolds=500.0),
+}
+
+
+def _case(which):
+    kw = dict(CASES[which])
+    return hi.make_case(kw.pop("physics"), kw.pop("ng"), kw.pop("degrees"), kw.pop("mach"), kw.pop("aoa_deg"),
+                        kw.pop("amp"), **kw)
+
+
+def _state(plan, case):
+    import torch
+    w = torch.tensor(case.W, dtype=torch.float64, device=plan.device)
+    q = torch.tensor(case.Q, dtype=torch.float64, device=plan.device)
+    lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=plan.device)
+    return w, q, lam
+
+
+@pytest.mark.parametrize("which", list(CASES))
+def test_ns_element_blocks_match_oracle(hdg, which):
+    case = _case(which)
+    _say(f"ns blocks {which}")
+    plan = hdg.HDGPlan.from_case(case)
+    w, q, lam = _state(plan, case)
+    mesh = O.Mesh(case, O.make_physics(case))
+    st = O.State(mesh, case.W, case.lam, case.Q)
+    for e in range(case.n_elements):
+        ob = O.element_blocks(st, e)
+        gb = plan.debug_element_blocks(e, w, lam, q)
+        for k, ref in (("A", ob.A), ("B", ob.B), ("C", ob.C), ("D", ob.D), ("r", ob.r), ("rl", ob.rl)):
+            assert gb[k].shape == ref.shape, (e, k)
+            if ref.size:
+                assert rel(gb[k], ref) < TOL, (e, k, rel(gb[k], ref))
+
+
+@pytest.mark.parametrize("which", list(CASES))
+def test_ns_newton_step_matches_oracle(hdg, which):
+    import torch
+    case = _case(which)
+    _say(f"ns newton step {which}")
+    step = O.newton_step(case)
+    plan = hdg.HDGPlan.from_case(case)
+    w, q, lam = _state(plan, case)
+    plan.hdg_assemble_condense(w, lam, q=q)
+    torch.cuda.synchronize()
+    for e in range(case.n_elements):
+        X, y = plan.debug_local_solution(e)
+        c = step.cond[e]
+        assert rel(X, c.X) < TOL, (e, rel(X, c.X))
+        assert rel(y, c.y) < tol_resid(step.blocks[e].A), (e, rel(y, c.y))
+    K = plan.skeleton_matrix_dense()
+    assert rel(K, step.K.toarray()) < TOL
+    assert rel(plan.rhs.cpu().numpy(), step.E) < TOL
+    dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=plan.device)
+    it, relres, _ = plan.hdg_skeleton_solve(dlam, rtol=1e-12, restart=30)
+    x = dlam.cpu().numpy()
+    _say(f"  gmres iters {it} relres {relres:.2e}")
+    assert relres <= 1e-12
+    assert np.linalg.norm(step.E - step.K @ x) / np.linalg.norm(step.E) <= 2e-12
+    # back-substitution with the oracle's dLambda: both the gradient and the state updates
+    dl = torch.tensor(step.dlam, dtype=torch.float64, device=plan.device)
+    dw = torch.zeros_like(w)
+    dq = torch.zeros_like(q)
+    plan.hdg_back_substitute(dl, dw, dq)
+    gw, gq = dw.cpu().numpy(), dq.cpu().numpy()
+    rw, rq = np.zeros_like(gw), np.zeros_like(gq)
+    for e in range(case.n_elements):
+        rw[e], rq[e] = O.unpack_local(step.mesh, e, step.du[e], case.W.shape[2])
+    assert rel(gw, rw) < 1e-11
+    assert rel(gq, rq) < 1e-11
+
+
+def test_ns_free_stream_gives_zero_rhs(hdg):
+    case = hi.make_case("ns", 4, [1, 2, 3, 4], 0.5, 1.0, 0.0, seed=23, reynolds=100.0, free_stream_only=True)
+    _say("ns free stream")
+    plan = hdg.HDGPlan.from_case(case)
+    w, q, lam = _state(plan, case)
+    nrm = plan.hdg_assemble_condense(w, lam, q=q, want_norm=True)
+    assert nrm < 1e-13
+
+
+def test_c4_recipe_reduced_size_sampled(hdg):
+    """The Navier-Stokes workload recipe (p in {2,3,4}, Re 5000, Pr 0.72) on a 24x24 mesh:
+    sampled local solutions and the skeleton residual recomputed on the CPU."""
+    import scipy.sparse as sp
+    import torch
+    case = hi.config_case("c4", ng=24)
+    _say("c4 recipe 24x24")
+    plan = hdg.HDGPlan.from_case(case)
+    w, q, lam = _state(plan, case)
+    plan.hdg_assemble_condense(w, lam, q=q)
+    torch.cuda.synchronize()
+    mesh = O.Mesh(case, O.make_physics(case))
+    st = O.State(mesh, case.W, case.lam, case.Q)
+    rng = np.random.default_rng(2)
+    for e in rng.choice(case.n_elements, 9, replace=False):
+        ob = O.element_blocks(st, int(e))
+        oc = O.condense(ob)
+        X, y = plan.debug_local_solution(int(e))
+        assert rel(X, oc.X) < TOL
+        assert rel(y, oc.y) < tol_resid(ob.A)
+    dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=plan.device)
+    it, relres, _ = plan.hdg_skeleton_solve(dlam, rtol=1e-10, restart=30)
+    _say(f"  c4-recipe gmres iters {it} relres {relres:.2e}")
+    K = sp.csr_matrix(plan.skeleton_matrix_dense())
+    E = plan.rhs.cpu().numpy()
+    x = dlam.cpu().numpy()
+    assert relres <= 1e-10 and np.linalg.norm(E - K @ x) / np.linalg.norm(E) <= 2e-10
