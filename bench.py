@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--serving-requests", type=int, default=24,
+                    help="requests of the Poisson serving stream to run (0 = skip; 512 = the full stream)")
+    ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -173,6 +176,22 @@ def main():
                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                        "launches": kl, "avg_launch_us": kms / max(1, kl) * 1e3,
                        "bytes_per_launch": kb / max(1, kl)}
+    if args.serving_requests > 0:
+        from paper_1308_3995_amd.serving import ServingEngine, stream_requests
+        log(f"[bench] serving: generating {args.serving_requests} requests")
+        reqs = stream_requests(512, 200.0, rtol=args.rtol)[: args.serving_requests]
+        eng = ServingEngine(max_slots=args.serving_slots, precision="mixed", restart=args.restart)
+        st = eng.run(reqs, on_result=lambda r: log(f"[bench] serving: request {r.index} done, "
+                                                   f"latency {r.latency_s:.3f} s, {r.elements} elements, "
+                                                   f"{r.gmres_iters} GMRES iterations"))
+        sm = st.summary()
+        sm["workload"] = (f"first {args.serving_requests} of 512 Poisson requests at 200/s (seed 1313): "
+                          f"2k-64k triangles log-uniform, p in 1..4, Euler or NS, Mach U(0.3,0.9), "
+                          f"alpha U(-3,3) deg; mixed precision, GMRES({args.restart}) to {args.rtol:g}; "
+                          f"{args.serving_slots} slots")
+        out["serving"] = sm
+        log(f"[bench] serving: p50 {sm['p50_latency_s']:.3f} s, p99 {sm['p99_latency_s']:.3f} s, "
+            f"{sm['elements_per_s']:.0f} elements/s")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         cb = cpu_baseline()

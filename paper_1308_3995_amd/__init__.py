@@ -37,7 +37,7 @@ class HDGPlan:
 
     def __init__(self, xy, tri, degree, physics: str = "euler", mach: float = 0.5, aoa_deg: float = 0.0,
                  reynolds: float = 0.0, prandtl: float = 0.72, gamma: float = 1.4, precision: str = "fp64",
-                 alpha: float = 0.0, device: int = 0):
+                 alpha: float = 0.0, device: int = 0, allocate: bool = True):
         import torch
         self.lib = load()
         self.device = torch.device("cuda", device)
@@ -64,17 +64,28 @@ class HDGPlan:
         self.n_skel = int(sz.n_skel_dof)
         self.npmax = int(sz.np_max)
         self.ne = int(sz.n_elements)
+        self.bsr = self.rhs = self.store = self.ws = None
+        if allocate:
+            self.allocate()
+
+    def allocate(self):
+        """Device buffers of one Newton step (skeleton matrix, right-hand side, local store, workspace)."""
+        import torch
+        if self.bsr is not None:
+            return
+        sz = self.sizes
         f64 = dict(dtype=torch.float64, device=self.device)
-        self.bsr = torch.empty(max(1, sz.bsr_values), **f64)
+        self.bsr = torch.empty(max(1, sz["bsr_values"]), **f64)
         self.rhs = torch.empty(max(1, self.n_skel), **f64)
-        self.store = torch.empty(max(1, (sz.local_store_bytes + 7) // 8), **f64)
-        self.ws = torch.empty(max(1, sz.workspace_bytes), dtype=torch.uint8, device=self.device)
+        self.store = torch.empty(max(1, (sz["local_store_bytes"] + 7) // 8), **f64)
+        self.ws = torch.empty(max(1, sz["workspace_bytes"]), dtype=torch.uint8, device=self.device)
 
     @classmethod
-    def from_case(cls, case, precision: str = "fp64", device: int = 0, alpha: float = 0.0) -> "HDGPlan":
+    def from_case(cls, case, precision: str = "fp64", device: int = 0, alpha: float = 0.0,
+                  allocate: bool = True) -> "HDGPlan":
         return cls(case.xy, case.tri, case.degree, physics=case.physics, mach=case.mach, aoa_deg=case.aoa_deg,
                    reynolds=case.reynolds, prandtl=case.prandtl, gamma=case.gamma, precision=precision,
-                   alpha=alpha, device=device)
+                   alpha=alpha, device=device, allocate=allocate)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -157,5 +158,9 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
                           int restart, int max_iter, char* ws, hipStream_t s, int* iters, double* relres);
 
 void set_error(const std::string& msg);
+
+// Serialises graph captures against plan creation and destruction (device allocation,
+// uploads and frees), so that several host threads may drive different plans.
+std::mutex& device_mutex();
 
 }  // namespace hdg

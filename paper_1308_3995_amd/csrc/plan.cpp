@@ -224,12 +224,19 @@ static void farfield_projector(const double* winf, double gamma, double nx, doub
 // Plan construction
 // ---------------------------------------------------------------------------
 
+std::mutex& device_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+// Uploads go through a private non-blocking stream (never the legacy stream, which would
+// synchronise with streams that other threads may be capturing).
 template <typename T>
-static hipError_t upload(T** dst, const std::vector<T>& src) {
+static hipError_t upload(T** dst, const std::vector<T>& src, hipStream_t st) {
     size_t n = std::max<size_t>(src.size(), 1);
     hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
     if (e != hipSuccess) return e;
-    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (!src.empty()) e = hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
     return e;
 }
 
@@ -507,27 +514,34 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     P.ws_total = off;
 
     // device uploads
+    std::lock_guard<std::mutex> lock(device_mutex());
     hipError_t err = hipSetDevice(device);
-    if (err == hipSuccess) err = upload(&P.d_einfo, P.einfo);
-    if (err == hipSuccess) err = upload(&P.d_tab, tab);
-    if (err == hipSuccess) err = upload(&P.d_bproj, bproj);
-    if (err == hipSuccess) err = upload(&P.d_face_off, P.face_off);
-    if (err == hipSuccess) err = upload(&P.d_face_deg, P.face_deg);
-    if (err == hipSuccess) err = upload(&P.d_row_ptr, P.row_ptr);
-    if (err == hipSuccess) err = upload(&P.d_col, P.col);
-    if (err == hipSuccess) err = upload(&P.d_val_off, P.val_off);
-    if (err == hipSuccess) err = upload(&P.d_diag_off, P.diag_off);
-    if (err == hipSuccess) err = upload(&P.d_hat_row_ptr, P.hat_row_ptr);
-    if (err == hipSuccess) err = upload(&P.d_hat_col, P.hat_col);
-    if (err == hipSuccess) err = upload(&P.d_hat_val_off, P.hat_val_off);
-    if (err == hipSuccess) err = upload(&P.d_hat_src, P.hat_src);
-    if (err == hipSuccess) err = upload(&P.d_k_rowbase, P.k_rowbase);
-    if (err == hipSuccess) err = upload(&P.d_k_colbase, P.k_colbase);
-    if (err == hipSuccess) err = upload(&P.d_k_xidx, P.k_xidx);
-    if (err == hipSuccess) err = upload(&P.d_hat_rowbase, P.hat_rowbase);
-    if (err == hipSuccess) err = upload(&P.d_hat_colbase, P.hat_colbase);
-    if (err == hipSuccess) err = upload(&P.d_hat_xidx, P.hat_xidx);
-    if (err == hipSuccess) err = upload(&P.d_kb_rows, P.kb_rows);
+    hipStream_t up = nullptr;
+    if (err == hipSuccess) err = hipStreamCreateWithFlags(&up, hipStreamNonBlocking);
+    if (err == hipSuccess) err = upload(&P.d_einfo, P.einfo, up);
+    if (err == hipSuccess) err = upload(&P.d_tab, tab, up);
+    if (err == hipSuccess) err = upload(&P.d_bproj, bproj, up);
+    if (err == hipSuccess) err = upload(&P.d_face_off, P.face_off, up);
+    if (err == hipSuccess) err = upload(&P.d_face_deg, P.face_deg, up);
+    if (err == hipSuccess) err = upload(&P.d_row_ptr, P.row_ptr, up);
+    if (err == hipSuccess) err = upload(&P.d_col, P.col, up);
+    if (err == hipSuccess) err = upload(&P.d_val_off, P.val_off, up);
+    if (err == hipSuccess) err = upload(&P.d_diag_off, P.diag_off, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_row_ptr, P.hat_row_ptr, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_col, P.hat_col, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_val_off, P.hat_val_off, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_src, P.hat_src, up);
+    if (err == hipSuccess) err = upload(&P.d_k_rowbase, P.k_rowbase, up);
+    if (err == hipSuccess) err = upload(&P.d_k_colbase, P.k_colbase, up);
+    if (err == hipSuccess) err = upload(&P.d_k_xidx, P.k_xidx, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_rowbase, P.hat_rowbase, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_colbase, P.hat_colbase, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_xidx, P.hat_xidx, up);
+    if (err == hipSuccess) err = upload(&P.d_kb_rows, P.kb_rows, up);
+    if (up) {
+        if (err == hipSuccess) err = hipStreamSynchronize(up);
+        (void)hipStreamDestroy(up);
+    }
     if (err != hipSuccess) {
         set_error(std::string("plan upload: ") + hipGetErrorString(err));
         return err == hipErrorOutOfMemory ? HDG_ERR_OOM : HDG_ERR_HIP;
@@ -536,6 +550,7 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
 }
 
 void free_plan(Plan& P) {
+    std::lock_guard<std::mutex> lock(device_mutex());
     for (hipEvent_t e : P.t_events)
         if (e) (void)hipEventDestroy(e);
     P.t_events.clear();

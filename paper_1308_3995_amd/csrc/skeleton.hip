@@ -663,8 +663,9 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
                 if (p.cycle_graph[gi]) (void)hipGraphDestroy(p.cycle_graph[gi]);
                 p.cycle_exec[gi] = nullptr;
                 p.cycle_graph[gi] = nullptr;
+                std::lock_guard<std::mutex> lock(device_mutex());
                 if (!p.capture_stream) HIPCHK(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
-                hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal);
+                hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeRelaxed);
                 if (e == hipSuccess) {
                     enqueue_cycle(p.capture_stream, steps);
                     e = hipStreamEndCapture(p.capture_stream, &p.cycle_graph[gi]);
@@ -768,20 +769,30 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
             if (tr <= tol || it == 0) break;
         }
     } else {
-        // iterative refinement: r = E - K x in float64, inner GMRES on the float32 Khat
-        for (int outer = 0; outer < 50 && total < max_iter; ++outer) {
+        // iterative refinement: r = E - K x in float64, inner GMRES on the float32 Khat. When an
+        // outer step fails to halve the float64 residual (kappa(Khat) u_32 too close to 1 for
+        // refinement to contract), the rest of the solve runs on the float64 Khat.
+        double prev = HUGE_VAL;
+        bool fp64_inner = false;
+        for (int outer = 0; outer < 200 && total < max_iter; ++outer) {
             double tr = 0.0;
             st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
             if (st != HDG_OK) return st;
             relres = tr / enorm;
             if (tr <= tol) break;
+            if (tr > 0.5 * prev) fp64_inner = true;
+            prev = tr;
             HIPCHK(hipMemcpyAsync(S.x, S.r, n * 8, hipMemcpyDeviceToDevice, s));
             hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, S.u, 0.0);
             int it = 0;
             double est = 0.0;
-            // the float32 matrix bounds the attainable inner reduction near 1e-6
-            const double inner_tol = std::max(tol, 1e-6 * tr);
-            st = gmres_khat<float>(p, S, S.hat32, S.x, restart, max_iter - total, inner_tol, s, &it, &est);
+            if (fp64_inner) {
+                st = gmres_khat<double>(p, S, S.hat, S.x, restart, max_iter - total, tol, s, &it, &est);
+            } else {
+                // the float32 matrix bounds what one refinement step can gain; ask for 1e-6
+                const double inner_tol = std::max(tol, 1e-6 * tr);
+                st = gmres_khat<float>(p, S, S.hat32, S.x, restart, max_iter - total, inner_tol, s, &it, &est);
+            }
             if (st != HDG_OK) return st;
             total += it;
             hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv,

@@ -1,0 +1,188 @@
+"""Continuous-batching request loop for Newton-step solves of independent HDG cases.
+
+Requests arrive on their own clock (seconds after the start of `run`). A request is
+admitted as soon as it has arrived, a slot is free and its device footprint (skeleton
+matrix, local store, workspace and state, from hdg_plan_sizes) fits in the HBM budget
+next to the cases already on the device. Each admitted case keeps its plan, state and
+matrices resident and runs one full Newton step (hdg_assemble_condense,
+hdg_skeleton_solve, hdg_back_substitute) on its own HIP stream from its own host thread,
+so the kernels of concurrent cases overlap on the GPU. When a case finishes, its slot and
+memory are released and waiting requests are admitted. Latency is completion minus
+arrival. All device work is deterministic (fixed-order reductions), so a case's result
+does not depend on what else is running.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional
+
+import numpy as np
+
+
+@dataclass
+class ServeRequest:
+    index: int
+    arrival_s: float
+    case: object                      # hdg_inputs.Case (or anything HDGPlan.from_case accepts)
+    rtol: float = 1e-10
+
+
+@dataclass
+class ServeResult:
+    index: int
+    arrival_s: float
+    admitted_s: float
+    done_s: float
+    elements: int
+    skel_dofs: int
+    gmres_iters: int
+    relres: float
+    status: int
+    footprint_bytes: int
+    dw: Optional[np.ndarray] = None
+    dlam: Optional[np.ndarray] = None
+
+    @property
+    def latency_s(self) -> float:
+        return self.done_s - self.arrival_s
+
+
+@dataclass
+class ServeStats:
+    results: List[ServeResult] = field(default_factory=list)
+    wall_s: float = 0.0
+    max_concurrent: int = 0
+    max_bytes_in_use: int = 0
+
+    def summary(self) -> dict:
+        ok = [r for r in self.results if r.status == 0]
+        lat = np.array([r.latency_s for r in ok]) if ok else np.zeros(1)
+        ne = sum(r.elements for r in ok)
+        nd = sum(r.skel_dofs for r in ok)
+        return {"requests": len(self.results), "completed": len(ok),
+                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "elements_per_s": ne / self.wall_s if self.wall_s > 0 else 0.0,
+                "skeleton_dof_per_s": nd / self.wall_s if self.wall_s > 0 else 0.0,
+                "wall_s": self.wall_s, "max_concurrent": self.max_concurrent,
+                "max_bytes_in_use": self.max_bytes_in_use}
+
+
+class ServingEngine:
+    def __init__(self, max_slots: int = 8, hbm_budget_bytes: Optional[int] = None, precision: str = "mixed",
+                 restart: int = 30, keep_results: bool = False, device: int = 0):
+        import torch
+        self.max_slots = max_slots
+        if hbm_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            hbm_budget_bytes = int(free * 0.8)
+        self.budget = int(hbm_budget_bytes)
+        self.precision = precision
+        self.restart = restart
+        self.keep = keep_results
+        self.device = device
+        self._lock = threading.Lock()
+        self._cv = threading.Condition(self._lock)
+        self._in_use = 0
+        self._active = 0
+
+    @staticmethod
+    def footprint(sizes: dict, npmax: int, n_elements: int, ns: bool) -> int:
+        state = n_elements * npmax * 8 * (12 if ns else 4) * 2      # state + update
+        return int(sizes["bsr_values"] * 8 + sizes["local_store_bytes"] + sizes["workspace_bytes"]
+                   + sizes["n_skel_dof"] * 8 * 3 + state)
+
+    def _solve(self, req: ServeRequest, plan, t0: float, admitted: float, fp: int) -> ServeResult:
+        import torch
+        from . import _lib
+        case = req.case
+        stream = torch.cuda.Stream(device=self.device)
+        dev = plan.device
+        plan.allocate()
+        status = 0
+        it, rr = 0, float("nan")
+        dw_h = dl_h = None
+        try:
+            with torch.cuda.stream(stream):
+                w = torch.tensor(case.W, dtype=torch.float64, device=dev)
+                q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
+                lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
+                dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=dev)
+                dw = torch.zeros_like(w)
+                dq = torch.zeros_like(q) if q is not None else None
+                plan.hdg_assemble_condense(w, lam, q=q, stream=stream)
+                it, rr, status = plan.hdg_skeleton_solve(dlam, rtol=req.rtol, restart=self.restart, stream=stream,
+                                                         raise_on_fail=False)
+                plan.hdg_back_substitute(dlam, dw, dq, stream=stream)
+                stream.synchronize()
+                if self.keep:
+                    dw_h = dw.cpu().numpy()
+                    dl_h = dlam.cpu().numpy()
+        except _lib.HdgError as e:      # a failed request is isolated: its slot is freed
+            status = e.status
+        done = time.perf_counter() - t0
+        return ServeResult(req.index, req.arrival_s, admitted, done, plan.ne, plan.n_skel, it, rr, status, fp,
+                           dw_h, dl_h)
+
+    def run(self, requests: List[ServeRequest], on_result: Optional[Callable[[ServeResult], None]] = None
+            ) -> ServeStats:
+        from . import HDGPlan
+        pending = sorted(requests, key=lambda r: r.arrival_s)
+        stats = ServeStats()
+        t0 = time.perf_counter()
+        futures = []
+
+        def finish(res: ServeResult, fp: int, plan):
+            with self._cv:
+                self._in_use -= fp
+                self._active -= 1
+                stats.results.append(res)
+                self._cv.notify_all()
+            del plan
+            if on_result:
+                on_result(res)
+
+        with ThreadPoolExecutor(max_workers=self.max_slots) as pool:
+            i = 0
+            while i < len(pending):
+                req = pending[i]
+                now = time.perf_counter() - t0
+                if req.arrival_s > now:
+                    time.sleep(min(req.arrival_s - now, 0.01))
+                    continue
+                plan = HDGPlan.from_case(req.case, precision=self.precision, device=self.device, allocate=False)
+                fp = self.footprint(plan.sizes, plan.npmax, plan.ne, plan.physics == "ns")
+                with self._cv:
+                    while self._active >= self.max_slots or (self._active > 0 and self._in_use + fp > self.budget):
+                        self._cv.wait(timeout=0.05)
+                    self._in_use += fp
+                    self._active += 1
+                    stats.max_concurrent = max(stats.max_concurrent, self._active)
+                    stats.max_bytes_in_use = max(stats.max_bytes_in_use, self._in_use)
+                admitted = time.perf_counter() - t0
+
+                def job(req=req, plan=plan, admitted=admitted, fp=fp):
+                    res = self._solve(req, plan, t0, admitted, fp)
+                    finish(res, fp, plan)
+                    return res
+
+                futures.append(pool.submit(job))
+                i += 1
+            for f in futures:
+                f.result()
+        stats.wall_s = time.perf_counter() - t0
+        stats.results.sort(key=lambda r: r.index)
+        return stats
+
+
+def stream_requests(n_requests: int, rate_per_s: float, seed: int = 1313, ne_range=(2000, 64000),
+                    degrees=(1, 2, 3, 4), rtol: float = 1e-10) -> List[ServeRequest]:
+    """The serving workload: Poisson arrivals, log-uniform mesh sizes, Euler or NS with
+    probability 1/2, p uniform in `degrees`, Mach ~ U(0.3, 0.9), alpha ~ U(-3, 3) deg."""
+    import hdg_inputs as hi
+    out = []
+    for r in hi.serving_stream(n_requests, rate_per_s, seed, ne_range, degrees):
+        out.append(ServeRequest(r.index, r.arrival_s, r.case(), rtol))
+    return out
