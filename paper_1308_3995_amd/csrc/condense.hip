@@ -1,13 +1,12 @@
 // Fused per-element assembly and static condensation for the Euler equations (gfx950).
 //
-// One 64-lane wavefront owns one element. Lanes first evaluate the state, convective
-// flux and its Jacobian at the volume and face quadrature points (Sec. 2.1, Sec. 3.2),
-// staging the weighted point data in LDS. Lane r then assembles row r of the augmented
-// local system [A_K | B_K | r_K] in registers (eq. hdg_ls2..hdg_ls4 linearised as in
-// eq. linearsystem), and the wave eliminates it with partial pivoting (Gauss-Jordan,
-// one row per lane, the pivot row broadcast through LDS). The eliminated rows are the
+// One workgroup owns one element. Its threads first evaluate the state, convective flux
+// and its Jacobian at the volume and face quadrature points (Sec. 2.1, Sec. 3.2), staging
+// the weighted point data in LDS. They then assemble the augmented local system
+// [A_K | B_K | r_K] (eq. hdg_ls2..hdg_ls4 linearised as in eq. linearsystem) and
+// eliminate it with partial pivoting (Gauss-Jordan). The eliminated columns are the
 // local solutions X_K = A_K^-1 B_K and y_K = A_K^-1 r_K kept for the reconstruction
-// (Sec. 3.4). Lanes then take the skeleton rows (local face, field, mode) and form
+// (Sec. 3.4). The threads then take the skeleton rows (local face, field, mode) and form
 //   S_K = D_K - C_K X_K,   g_K = r_lam,K - C_K y_K        (eq. hybridsystem)
 // where, for the trace flux f(lam).n - alpha (lam - w), C_K = alpha (trace mass) acts
 // field by field and D_K is block-diagonal over the element's faces. Off-diagonal face
@@ -224,8 +223,10 @@ __device__ __forceinline__ void point_data(const CondArgs& a, const ElemInfo* E,
 
 // Phase 6 of both kernels: skeleton rows (local face, field, mode) of
 //   S_K = D_K - C_K X_K,   g_K = r_lam,K - C_K y_K.
-// sX holds [X_K | y_K] column-major with N rows. With DBG the rows of C_K, D_K and r_lam,K
-// are written to the debug buffer instead.
+// sX holds [X_K | y_K] column-major with N rows. The nth threads split the F x F entries:
+// thread t takes row t % F and every CH-th column from t / F, so consecutive threads store
+// consecutive rows of a skeleton block. With DBG the rows of C_K, D_K and r_lam,K are
+// written to the debug buffer instead.
 template <int P, int PF, bool DBG>
 __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
                                            const double* sX, int tid, int nth) {
@@ -234,10 +235,12 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
     constexpr int NPF = PF + 1;
     constexpr int F = 12 * NPF;
     constexpr int NC = N + F + 1;
+    const int CH = nth >= F ? nth / F : 1;
     const double alpha = a.alpha;
     const auto& sFH = sh.sFH;
     const auto& sJB = sh.sJB;
-    for (int r = tid; r < F; r += nth) {
+    for (int t = tid; t < F * CH; t += nth) {
+        const int r = t % F, ch = t / F;
         const int lf = r / (4 * NPF), b = (r / NPF) % 4, k = r % NPF;
         const int f = E->face[lf], pe = E->pe[lf];
         if (!DBG && (f < 0 || k > pe)) continue;
@@ -260,18 +263,20 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
         }
         const int se = 4 * (pe + 1);
         const int row = b * (pe + 1) + k;
-        if (DBG) {
-            // C_K row (field-diagonal trace mass), D_K row, r_lam
+        if (ch == 0) {
+            if (DBG) {
+                // C_K row (field-diagonal trace mass) and r_lam
+                for (int c2 = 0; c2 < N; ++c2)
+                    a.debug[(int64_t)NC * N + (int64_t)c2 * F + r] = (c2 / NP == b) ? alpha * T[c2 % NP] : 0.0;
+                a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)F * F + r] = rl;
+            } else {
+                double gy = rl;
 #pragma unroll
-            for (int c2 = 0; c2 < N; ++c2) a.debug[(int64_t)NC * N + (int64_t)c2 * F + r] = (c2 / NP == b) ? alpha * T[c2 % NP] : 0.0;
-        } else {
-            double gy = rl;
-#pragma unroll
-            for (int j = 0; j < NP; ++j) gy -= alpha * T[j] * sX[F * N + b * NP + j];
-            a.g_part[2 * a.face_off[f] + E->side[lf] * se + row] = gy;
+                for (int j = 0; j < NP; ++j) gy -= alpha * T[j] * sX[F * N + b * NP + j];
+                a.g_part[2 * a.face_off[f] + E->side[lf] * se + row] = gy;
+            }
         }
-#pragma unroll
-        for (int c2 = 0; c2 < F; ++c2) {
+        for (int c2 = ch; c2 < F; c2 += CH) {
             const int lf2 = c2 / (4 * NPF), b2 = (c2 / NPF) % 4, l = c2 % NPF;
             double dv = 0.0;
             if (lf2 == lf && valid && l <= pe) {
@@ -297,146 +302,224 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
                 a.bsr[E->boff[lf][lf2] + (int64_t)colc * se + row] = sv;
             }
         }
-        if (DBG) a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)F * F + r] = rl;
     }
 }
 
+// Broadcast of lane src's value (src uniform across the wave) through two readlanes.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __hiloint2double(hi, lo);
+}
+
+// Wave-wide maximum of a 32-bit key: DPP prefix maxima within rows of 16 lanes, then the
+// row broadcasts of lanes 15 and 31; lane 63 ends with the maximum.
+__device__ __forceinline__ unsigned wave_max_key(unsigned x) {
+    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));  // row_shr:1
+    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));  // row_shr:2
+    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));  // row_shr:4
+    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));  // row_shr:8
+    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Pivot row for column value v: the lowest lane among the unused rows whose |v|, rounded to
+// single precision, is largest. The single-precision comparison keeps the pivot within a
+// factor 1 - 2^-24 of the largest candidate, which is as stable as exact partial pivoting.
+// Keys: 0 for used rows, bits(|v|) + 1 otherwise (the bit pattern of a non-negative float
+// orders like its value).
+__device__ __forceinline__ int pivot_lane(double v, bool used) {
+    const unsigned key = used ? 0u : (unsigned)__float_as_int((float)fabs(v)) + 1u;
+    const unsigned mx = wave_max_key(key);
+    const unsigned long long m = __ballot(key == mx);
+    return m ? __ffsll((long long)m) - 1 : 0;
+}
+
+// Degrees 1..3 (N = 4 Np <= 40 rows): four wavefronts per element, one row of the
+// augmented system [A_K | B_K | r_K] per lane, the columns split between the waves:
+// wave w holds the A_K columns of field w and every fourth block of the B_K / r_K
+// columns. Gauss-Jordan elimination with partial pivoting runs step by step over the
+// whole workgroup: the wave holding column k picks the pivot row and publishes the
+// multipliers through LDS (double-buffered, one barrier per step), and every wave applies
+// the step to its live columns, taking the pivot row's entries from the pivot lane. The
+// owner of the next pivot column updates that column first and searches its pivot before
+// finishing the rest of the step (one-column lookahead).
 template <int P, int PF, bool DBG>
-__global__ __launch_bounds__(64) void k_condense_euler(CondArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_condense_euler(CondArgs a) {
     constexpr int NP = n_modes(P);
     constexpr int N = 4 * NP;
     constexpr int NPF = PF + 1;
     constexpr int F = 12 * NPF;
-    constexpr int NC = N + F + 1;
+    constexpr int FB = 4 * NPF;                // B_K columns of one local face
+    constexpr int NBW = (F + 1 + 3) / 4;       // B_K / r_K columns per wave (zero padded)
     constexpr int Q = n_vol_q(P);
     static_assert(N <= 64, "one row per lane");
-    static_assert(Q <= 64, "one volume point per lane");
 
     __shared__ ElemShared<P, PF> sh;
-    __shared__ double sRow[2][NC];
     __shared__ double sX[(F + 1) * N];
+    __shared__ double sFm[2][64];
+    __shared__ double sPVk[N];
+    __shared__ int sPiv[2];
+    __shared__ int sBad;
 
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int slot = a.start + blockIdx.x;
     if (DBG && slot != a.debug_slot) return;
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
-    point_data<P, PF>(a, E, sh, lane, 64);
-    __syncthreads();
+    if (tid == 0) sBad = 0;
+    point_data<P, PF>(a, E, sh, tid, 256);
     const auto& sK = sh.sK;
     const auto& sF = sh.sF;
     const auto& sJA = sh.sJA;
     const auto& sJB = sh.sJB;
     const auto& sFH = sh.sFH;
 
-    // ---- phase 3: row assembly, lane r = fa * NP + i
-    double m[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) m[c] = 0.0;
     const int rr = lane < N ? lane : N - 1;
     const int fa = rr / NP, ii = rr % NP;
+
+    // ---- A_K columns of field b = wave: volume and face terms (eq. hdg_ls2 linearised)
+    double mA[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) mA[j] = 0.0;
     {
-        double rhs = 0.0;
+        const int b = wave;
         for (int q = 0; q < Q; ++q) {
             const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
-            double s[4];
+            const double s = -(g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) s[b] = -(g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]);
-            rhs += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
-#pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                const double ph = a.vphi[q * NP + j];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) m[b * NP + j] += s[b] * ph;
-            }
+            for (int j = 0; j < NP; ++j) mA[j] += s * a.vphi[q * NP + j];
         }
 #pragma unroll
         for (int lf = 0; lf < 3; ++lf) {
-            const int pe = E->pe[lf], nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
-            const bool interior = E->face[lf] >= 0;
+            const int nq = E->pe[lf] + 2, o = E->orient[lf];
             for (int g = 0; g < nq; ++g) {
-                const double phi_i = a.fphi[face_phi_index(NP, lf, o, nq, g, ii)];
-                double t[4];
+                const double t = a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJA[lf][g][fa * 4 + b];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) t[b] = phi_i * sJA[lf][g][fa * 4 + b];
-#pragma unroll
-                for (int j = 0; j < NP; ++j) {
-                    const double ph = a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) m[b * NP + j] += t[b] * ph;
-                }
-                rhs -= phi_i * sFH[lf][g][fa];
-                if (interior) {
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) t[b] = phi_i * sJB[lf][g][fa * 4 + b];
-#pragma unroll
-                    for (int k = 0; k < NPF; ++k) {
-                        const double ps = k <= pe ? a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k] : 0.0;
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) m[N + (lf * 4 + b) * NPF + k] += t[b] * ps;
-                    }
-                }
+                for (int j = 0; j < NP; ++j) mA[j] += t * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
             }
         }
-        m[NC - 1] = rhs;
     }
 
+    // ---- B_K / r_K columns cb = wave * NBW + i (cb < F: face lf, field b, mode k; cb = F: r_K)
+    double mB[NBW];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+        const int cb = wave * NBW + i;
+        double v = 0.0;
+        if (cb < F) {
+            const int lf = cb / FB, b = (cb / NPF) % 4, k = cb % NPF;
+            const int pe = E->pe[lf];
+            if (E->face[lf] >= 0 && k <= pe) {
+                const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+                for (int g = 0; g < nq; ++g)
+                    v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJB[lf][g][fa * 4 + b] *
+                         a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
+            }
+        } else if (cb == F) {
+            for (int q = 0; q < Q; ++q) {
+                const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
+                v += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
+            }
+#pragma unroll
+            for (int l2 = 0; l2 < 3; ++l2) {
+                const int nq = E->pe[l2] + 2, o = E->orient[l2];
+                for (int g = 0; g < nq; ++g) v -= a.fphi[face_phi_index(NP, l2, o, nq, g, ii)] * sFH[l2][g][fa];
+            }
+        }
+        mB[i] = v;
+    }
     if (DBG) {
         if (lane < N) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a.debug[(int64_t)c * N + lane] = m[c];
-        }
-    }
-
-    // ---- phase 4: Gauss-Jordan elimination with partial pivoting, one row per lane
-    int mykk = 0;
-    double mypv = 1.0;
-    if (!DBG) {
-        bool used = lane >= N;
+            for (int j = 0; j < NP; ++j) a.debug[(int64_t)(wave * NP + j) * N + lane] = mA[j];
 #pragma unroll
-        for (int k = 0; k < N; ++k) {
-            double v = used ? -1.0 : fabs(m[k]);
-            int idx = lane;
-            wave_argmax(v, idx);
-            const int piv = __builtin_amdgcn_readfirstlane(idx);
-            double* buf = sRow[k & 1];
-            if (lane == piv) {
-#pragma unroll
-                for (int c = k; c < NC; ++c) buf[c] = m[c];
-            }
-            __syncthreads();
-            const double pv = buf[k];
-            const double f = (lane == piv || lane >= N) ? 0.0 : m[k] / pv;
-#pragma unroll
-            for (int c = k + 1; c < NC; ++c) m[c] -= f * buf[c];
-            if (lane == piv) {
-                used = true;
-                mykk = k;
-                mypv = pv;
-            }
-        }
-        // ---- phase 5: X_K, y_K to the local store and to LDS
-        if (lane < N) {
-            const double inv = 1.0 / mypv;
-            const int bslot = slot - a.start;
-            double* st = a.store + (int64_t)bslot * ((F + 1) * N);
-            bool bad = !(fabs(mypv) > 0.0) || !isfinite(inv);
-#pragma unroll
-            for (int c = 0; c <= F; ++c) {
-                const double x = m[N + c] * inv;
-                bad |= !isfinite(x);
-                sX[c * N + mykk] = x;
-                st[c * N + mykk] = x;
-            }
-            if (bad) {
-                a.status[e] = (!(fabs(mypv) > 0.0) || !isfinite(inv)) ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
-                a.flag[0] = 1;
+            for (int i = 0; i < NBW; ++i) {
+                const int cb = wave * NBW + i;
+                if (cb <= F) a.debug[(int64_t)(N + cb) * N + lane] = mB[i];
             }
         }
         __syncthreads();
+        schur_rows<P, PF, DBG>(a, E, sh, sX, tid, 256);
+        return;
     }
 
-    schur_rows<P, PF, DBG>(a, E, sh, sX, lane, 64);
+    // ---- Gauss-Jordan elimination with partial pivoting
+    bool used = lane >= N;
+    int mykk = 0;
+    if (wave == 0) {
+        const int piv = pivot_lane(mA[0], used);
+        const double pv = lane_bcast(mA[0], piv);
+        sFm[0][lane] = (lane == piv || lane >= N) ? 0.0 : mA[0] / pv;
+        if (lane == 0) {
+            sPiv[0] = piv;
+            sPVk[0] = pv;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        // apply step k - 1; the owner of column k (if any) then publishes step k
+        const int piv = __builtin_amdgcn_readfirstlane(sPiv[(k - 1) & 1]);
+        const double f = sFm[(k - 1) & 1][lane];
+        if (lane == piv) {
+            used = true;
+            mykk = k - 1;
+        }
+        const int ow = k / NP, jk = k % NP;   // column k = A_K column jk of wave ow
+        if (k < N && wave == ow) {
+            mA[jk] -= f * lane_bcast(mA[jk], piv);
+            const int pn = pivot_lane(mA[jk], used);
+            const double pv = lane_bcast(mA[jk], pn);
+            sFm[k & 1][lane] = (lane == pn || lane >= N) ? 0.0 : mA[jk] / pv;
+            if (lane == 0) {
+                sPiv[k & 1] = pn;
+                sPVk[k] = pv;
+            }
+#pragma unroll
+            for (int j = jk + 1; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
+        } else if (wave > (k - 1) / NP) {
+            // every A_K column of this wave has index >= k
+#pragma unroll
+            for (int j = 0; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
+        } else if (wave == (k - 1) / NP) {
+#pragma unroll
+            for (int j = (k - 1) % NP + 1; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
+        }
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) mB[i] -= f * lane_bcast(mB[i], piv);
+        __syncthreads();
+    }
+
+    // ---- X_K = A_K^-1 B_K and y_K = A_K^-1 r_K: row kk of the solution sits in the row
+    // whose pivot was taken at step kk
+    const int bslot = slot - a.start;
+    if (lane < N) {
+        const double pv = sPVk[mykk];
+        const double inv = 1.0 / pv;
+        double* st = a.store + (int64_t)bslot * ((F + 1) * N);
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) {
+            const int cb = wave * NBW + i;
+            if (cb <= F) {
+                const double x = mB[i] * inv;
+                bad |= !isfinite(x);
+                sX[cb * N + mykk] = x;
+                st[(int64_t)cb * N + mykk] = x;
+            }
+        }
+        if (!(fabs(pv) > 0.0) || !isfinite(inv)) sBad = 1;
+        else if (bad && sBad == 0) sBad = 2;
+    }
+    __syncthreads();
+    if (tid == 0 && sBad != 0) {
+        a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+        a.flag[0] = 1;
+    }
+    schur_rows<P, PF, DBG>(a, E, sh, sX, tid, 256);
 }
 
 // Variant for large local blocks (degree 4 and 5: N = 60 or 84 rows, more than one
@@ -629,8 +712,8 @@ __global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start
         }
 }
 
-// Degrees up to 3 take the register kernel (one wavefront per element); degrees 4 and 5
-// take the LDS-resident kernel.
+// Degrees up to 3 take the register kernel (four wavefronts per element, columns split);
+// degrees 4 and 5 take the LDS-resident kernel.
 template <int P, int PF>
 static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, hipStream_t s) {
     a.vphi = p.d_tab + p.tix.vol_phi[P];
@@ -640,9 +723,9 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.start = bk.start;
     if constexpr (P <= 3) {
         if (dbg)
-            hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(64), 0, s, a);
+            hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(256), 0, s, a);
         else
-            hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(64), 0, s, a);
+            hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(256), 0, s, a);
     } else {
         if (dbg)
             hipLaunchKernelGGL((k_condense_euler_lds<P, PF, true>), dim3(bk.count), dim3(256), 0, s, a);
