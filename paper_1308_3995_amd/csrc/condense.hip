@@ -721,7 +721,7 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.vw = p.d_tab + p.tix.vol_w[P];
     a.fphi = p.d_tab + p.tix.face_phi[P];
     a.start = bk.start;
-    if constexpr (P <= 3) {
+    if constexpr (P <= 4) {
         if (dbg)
             hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(256), 0, s, a);
         else
