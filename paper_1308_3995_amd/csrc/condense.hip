@@ -13,6 +13,7 @@
 // blocks of S_K have one owner element and are stored straight into the skeleton
 // matrix; the diagonal blocks and g_K go to per-face slots summed by k_diag_sum in a
 // fixed order, so the assembly is deterministic and atomic-free.
+#include "gj.h"
 #include "hdg_internal.h"
 
 namespace hdg {
@@ -305,47 +306,10 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
     }
 }
 
-// Broadcast of lane src's value (src uniform across the wave) through two readlanes.
-__device__ __forceinline__ double lane_bcast(double v, int src) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, src);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-    return __hiloint2double(hi, lo);
-}
-
-// Wave-wide maximum of a 32-bit key: DPP prefix maxima within rows of 16 lanes, then the
-// row broadcasts of lanes 15 and 31; lane 63 ends with the maximum.
-__device__ __forceinline__ unsigned wave_max_key(unsigned x) {
-    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));  // row_shr:1
-    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));  // row_shr:2
-    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));  // row_shr:4
-    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));  // row_shr:8
-    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));  // row_bcast:15
-    x = max(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));  // row_bcast:31
-    return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
-}
-
-// Pivot row for column value v: the lowest lane among the unused rows whose |v|, rounded to
-// single precision, is largest. The single-precision comparison keeps the pivot within a
-// factor 1 - 2^-24 of the largest candidate, which is as stable as exact partial pivoting.
-// Keys: 0 for used rows, bits(|v|) + 1 otherwise (the bit pattern of a non-negative float
-// orders like its value).
-__device__ __forceinline__ int pivot_lane(double v, bool used) {
-    const unsigned key = used ? 0u : (unsigned)__float_as_int((float)fabs(v)) + 1u;
-    const unsigned mx = wave_max_key(key);
-    const unsigned long long m = __ballot(key == mx);
-    return m ? __ffsll((long long)m) - 1 : 0;
-}
-
-// Degrees 1..3 (N = 4 Np <= 40 rows): four wavefronts per element, one row of the
+// Degrees 1..4 (N = 4 Np <= 60 rows): four wavefronts per element, one row of the
 // augmented system [A_K | B_K | r_K] per lane, the columns split between the waves:
 // wave w holds the A_K columns of field w and every fourth block of the B_K / r_K
-// columns. Gauss-Jordan elimination with partial pivoting runs step by step over the
-// whole workgroup: the wave holding column k picks the pivot row and publishes the
-// multipliers through LDS (double-buffered, one barrier per step), and every wave applies
-// the step to its live columns, taking the pivot row's entries from the pivot lane. The
-// owner of the next pivot column updates that column first and searches its pivot before
-// finishing the rest of the step (one-column lookahead).
+// columns; the elimination is gj_eliminate.
 template <int P, int PF, bool DBG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_condense_euler(CondArgs a) {
     constexpr int NP = n_modes(P);
@@ -447,51 +411,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
 
     // ---- Gauss-Jordan elimination with partial pivoting
-    bool used = lane >= N;
     int mykk = 0;
-    if (wave == 0) {
-        const int piv = pivot_lane(mA[0], used);
-        const double pv = lane_bcast(mA[0], piv);
-        sFm[0][lane] = (lane == piv || lane >= N) ? 0.0 : mA[0] / pv;
-        if (lane == 0) {
-            sPiv[0] = piv;
-            sPVk[0] = pv;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 1; k <= N; ++k) {
-        // apply step k - 1; the owner of column k (if any) then publishes step k
-        const int piv = __builtin_amdgcn_readfirstlane(sPiv[(k - 1) & 1]);
-        const double f = sFm[(k - 1) & 1][lane];
-        if (lane == piv) {
-            used = true;
-            mykk = k - 1;
-        }
-        const int ow = k / NP, jk = k % NP;   // column k = A_K column jk of wave ow
-        if (k < N && wave == ow) {
-            mA[jk] -= f * lane_bcast(mA[jk], piv);
-            const int pn = pivot_lane(mA[jk], used);
-            const double pv = lane_bcast(mA[jk], pn);
-            sFm[k & 1][lane] = (lane == pn || lane >= N) ? 0.0 : mA[jk] / pv;
-            if (lane == 0) {
-                sPiv[k & 1] = pn;
-                sPVk[k] = pv;
-            }
-#pragma unroll
-            for (int j = jk + 1; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
-        } else if (wave > (k - 1) / NP) {
-            // every A_K column of this wave has index >= k
-#pragma unroll
-            for (int j = 0; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
-        } else if (wave == (k - 1) / NP) {
-#pragma unroll
-            for (int j = (k - 1) % NP + 1; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
-        }
-#pragma unroll
-        for (int i = 0; i < NBW; ++i) mB[i] -= f * lane_bcast(mB[i], piv);
-        __syncthreads();
-    }
+    gj_eliminate<NP, NBW>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
 
     // ---- X_K = A_K^-1 B_K and y_K = A_K^-1 r_K: row kk of the solution sits in the row
     // whose pivot was taken at step kk

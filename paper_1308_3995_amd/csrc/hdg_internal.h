@@ -153,7 +153,8 @@ hipError_t launch_back_substitute(const Plan& p, const double* store, const doub
 hipError_t launch_ns(const Plan& p, const double* w, const double* q, const double* lam, double* bsr,
                      double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag, double* zbuf,
                      int64_t zcap_doubles, int only_slot, hipStream_t s);
-int64_t ns_workspace_per_element(int p, int pf);
+int64_t ns_workspace_per_element(int p, int pf);   // Z, L, R of one element (block inspection)
+int64_t ns_chunk_per_element(int p, int pf);       // reduced system and factors (product path)
 hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol,
                           int restart, int max_iter, char* ws, hipStream_t s, int* iters, double* relres);
 

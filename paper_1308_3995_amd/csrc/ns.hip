@@ -12,13 +12,19 @@
 // rows [Chat | Dhat | rhat_lam]; it is condensed like the Euler system, and the gradient
 // part of the local solutions follows as X_q = (B_q - G_qw X_w)/|J|, y_q = (r_q - G_qw y_w)/|J|.
 //
-// Three kernels per bucket chunk:
-//   k_ns_assemble  point data (fluxes and Jacobians by forward-mode dual numbers), Z, the
-//                  left factor L = [A_wq ; C_q] and the right factor R = [G_qw | B_q | r_q]
-//                  written to a workspace chunk (256 threads per element);
-//   k_ns_reduce    Zhat = Z - L R / |J| (batched dense product, LDS tiles);
-//   k_ns_condense  Gauss-Jordan on [Ahat | Bhat | rhat] in LDS, X_q and y_q, the local store,
-//                  S_K = Dhat - Chat X_w, g_K = rhat_lam - Chat y_w and the scatter.
+// Product path, three kernels per bucket chunk:
+//   k_ns_points     point data: fluxes and Jacobians by forward-mode dual numbers at the
+//                   volume and face quadrature points (one wave per element);
+//   k_ns_zhat       the reduced system Zhat without forming L or R: the gradient rows are
+//                   linear in (w, lambda) with structured coefficients G_d, Bf, Mb, r_q,
+//                   so every thread accumulates its row fragment of L over the quadrature
+//                   points and applies those small factors;
+//   k_ns_condense2  Gauss-Jordan on [Ahat | Bhat | rhat] (gj_eliminate), X_q and y_q, the
+//                   local store, S_K = Dhat - Chat X_w, g_K = rhat_lam - Chat y_w and the
+//                   scatter.
+// Block inspection (one element) runs k_ns_assemble, which writes Z, L = [A_wq ; C_q] and
+// R = [G_qw | B_q | r_q] as dense matrices.
+#include "gj.h"
 #include "hdg_internal.h"
 
 namespace hdg {
@@ -419,148 +425,603 @@ __global__ __launch_bounds__(256) void k_ns_assemble(NsArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Zhat = Z - (1/|J|) L R, one element per block, 16 x 16 output tiles
+// Product path: the reduced system without the factors L and R.
+//
+// The gradient rows are linear in (w, lambda) with the element mass matrix |J| I, so
+// (L R)[row, col] = sum_{d,c,m} l_row[d][c][m] R[(d,c,m), col] with the structured factor
+//   R[(d,c,m), (b,j)]      = delta_cb G_d[m][j] - sum_{boundary lf} n_d P+_lf[c][b] Mb_lf[m][j]
+//   R[(d,c,m), (lf,b,k)]   = -delta_cb n_d Bf_lf[m][k]                       (interior lf)
+//   R[(d,c,m), rhs]        = rq[4 d + c][m]
+// where G_d[m][j] = int d_d phi_m phi_j, Mb_lf[m][j] = int_lf phi_m phi_j (boundary faces),
+// Bf_lf[m][k] = int_lf phi_m psi_k (interior faces) and rq is the gradient residual. The
+// row fragment l_row[d][c][.] is a sum over quadrature points of (dF/dq contraction) x phi,
+// accumulated in registers by the thread that owns (row, c); it never leaves the thread.
 // ---------------------------------------------------------------------------
+// Point data of one element: volume points with the weights |J| w_q folded in, face points
+// with the edge weights w_g |e|/2 folded in (interior faces: trace flux F.n - alpha (lam - w)
+// and its derivatives; far-field faces: F(w_b).n with w_b = P+ w + (I - P+) w_inf).
 template <int P, int PF>
-__global__ __launch_bounds__(256) void k_ns_reduce(NsArgs a) {
+struct NsPoints {
+    static constexpr int Q = n_vol_q(P), QF = PF + 2;
+    double vw_[Q];          // |J| w_q
+    double vwv[Q][4];       // w
+    double vqv[Q][8];       // q
+    double vF[Q][2][4];     // |J| w_q F_d
+    double vJw[Q][2][16];   // |J| w_q dF_d/dw
+    double vJq[Q][2][32];   // |J| w_q dF_d/dq
+    double fwl[3][QF];
+    double fFH[3][QF][4];
+    double fJA[3][QF][16];
+    double fJB[3][QF][16];
+    double fJQ[3][QF][32];
+    double fTr[3][QF][4];   // the state entering the gradient equation: lam or w_b
+};
+
+template <int P, int PF>
+struct NsLayout {
     using D = NsDims<P, PF>;
-    constexpr int NR = D::NR, NQ = D::NQ, NCZ = D::NCZ;
-    constexpr int TK = 16;
-    __shared__ double Lt[16][TK + 1];
-    __shared__ double Rt[TK][16 + 1];
+    static constexpr int NP = D::NP, NPF = D::NPF;
+    static constexpr int64_t ZH = (int64_t)D::NR * D::NCZ;     // Zhat, column-major with NR rows
+    static constexpr int64_t G = ZH;                           // G_d    [2][NP][NP]
+    static constexpr int64_t BF = G + 2 * NP * NP;             // Bf_lf  [3][NP][NPF]
+    static constexpr int64_t MB = BF + 3 * NP * NPF;           // Mb_lf  [3][NP][NP]
+    static constexpr int64_t RQ = MB + 3 * NP * NP;            // rq     [8][NP]
+    static constexpr int64_t PT = RQ + 8 * NP;                 // NsPoints image
+    static constexpr int64_t PER = PT + sizeof(NsPoints<P, PF>) / 8;
+};
+
+// Point data of the chunk's elements: one wave per element, one lane per volume point
+// and one per face point; fluxes and Jacobians by forward-mode dual numbers.
+template <int P, int PF>
+__global__ __launch_bounds__(64) void k_ns_points(NsArgs a) {
+    using D = NsDims<P, PF>;
+    using LY = NsLayout<P, PF>;
+    constexpr int NP = D::NP, NPF = D::NPF, Q = D::Q, QF = D::QF;
+    static_assert(Q + 24 <= 128, "two passes of one wave");
+    __shared__ double sW[4 * NP];
+    __shared__ double sQ[8 * NP];
+    __shared__ double sLam[3][4][NPF];
+    __shared__ NsPoints<P, PF> pt;
+    const int tid = threadIdx.x;
     const int slot = a.start + blockIdx.x;
-    const double inv = 1.0 / a.einfo[slot].detj;
-    double* Z = a.zbuf + (int64_t)blockIdx.x * D::PER;
-    const double* L = Z + D::ZSZ;
-    const double* R = L + D::LSZ;
-    const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
-    for (int r0 = 0; r0 < NR; r0 += 16)
-        for (int c0 = 0; c0 < NCZ; c0 += 16) {
-            double acc = 0.0;
-            for (int k0 = 0; k0 < NQ; k0 += TK) {
-                __syncthreads();
-                {
-                    const int r = r0 + tr, k = k0 + tc;
-                    Lt[tr][tc] = (r < NR && k < NQ) ? L[(int64_t)k * NR + r] : 0.0;
-                    const int kk = k0 + tr, c = c0 + tc;
-                    Rt[tr][tc] = (kk < NQ && c < NCZ) ? R[(int64_t)c * NQ + kk] : 0.0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < TK; ++k) acc += Lt[tr][k] * Rt[k][tc];
+    const ElemInfo* E = a.einfo + slot;
+    const int e = E->elem;
+    const double alpha = a.alpha, gm = a.gamma, mu = a.mu, pr = a.prandtl, detj = E->detj;
+    for (int t = tid; t < 4 * NP; t += 64) sW[t] = a.w[((int64_t)e * 4 + t / NP) * a.npmax + t % NP];
+    for (int t = tid; t < 8 * NP; t += 64) sQ[t] = a.q[((int64_t)e * 8 + t / NP) * a.npmax + t % NP];
+    for (int t = tid; t < 12 * NPF; t += 64) {
+        const int lf = t / (4 * NPF), r = t % (4 * NPF), fa = r / NPF, k = r % NPF;
+        const int f = E->face[lf];
+        sLam[lf][fa][k] = (f >= 0 && k <= E->pe[lf]) ? a.lam[a.face_off[f] + fa * (E->pe[lf] + 1) + k] : 0.0;
+    }
+    __syncthreads();
+    for (int t = tid; t < Q + 24; t += 64) {
+        if (t < Q) {
+            const int qp = t;
+            double w[4], q[8];
+            for (int c = 0; c < 4; ++c) {
+                double s = 0.0;
+                for (int i = 0; i < NP; ++i) s += a.vphi[qp * NP + i] * sW[c * NP + i];
+                w[c] = s;
             }
-            const int r = r0 + tr, c = c0 + tc;
-            if (r < NR && c < NCZ) Z[(int64_t)c * NR + r] -= inv * acc;
+            for (int c = 0; c < 8; ++c) {
+                double s = 0.0;
+                for (int i = 0; i < NP; ++i) s += a.vphi[qp * NP + i] * sQ[c * NP + i];
+                q[c] = s;
+            }
+            double Fv[2][4], Jw[2][4][4], Jq[2][4][8];
+            ns_flux_jac(w, q, gm, mu, pr, Fv, Jw, Jq);
+            const double sc = a.vw[qp] * detj;
+            pt.vw_[qp] = sc;
+            for (int c = 0; c < 4; ++c) pt.vwv[qp][c] = w[c];
+            for (int c = 0; c < 8; ++c) pt.vqv[qp][c] = q[c];
+            for (int d = 0; d < 2; ++d)
+                for (int r = 0; r < 4; ++r) {
+                    pt.vF[qp][d][r] = sc * Fv[d][r];
+                    for (int c = 0; c < 4; ++c) pt.vJw[qp][d][r * 4 + c] = sc * Jw[d][r][c];
+                    for (int c = 0; c < 8; ++c) pt.vJq[qp][d][r * 8 + c] = sc * Jq[d][r][c];
+                }
+        } else {
+            const int lf = (t - Q) >> 3, g = (t - Q) & 7;
+            const int pe = E->pe[lf], nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+            if (g < QF) {
+                if (g >= nq) {
+                    // unused point of a lower-degree face: zero weights keep every sum exact
+                    pt.fwl[lf][g] = 0.0;
+                    for (int r = 0; r < 4; ++r) pt.fFH[lf][g][r] = pt.fTr[lf][g][r] = 0.0;
+                    for (int c = 0; c < 16; ++c) pt.fJA[lf][g][c] = pt.fJB[lf][g][c] = 0.0;
+                    for (int c = 0; c < 32; ++c) pt.fJQ[lf][g][c] = 0.0;
+                } else {
+                    const double wl = a.gw[rule * kMaxFaceQ + g] * 0.5 * E->len[lf];
+                    const double nx = E->nrm[lf][0], ny = E->nrm[lf][1];
+                    double wt[4], qt[8];
+                    for (int c = 0; c < 4; ++c) {
+                        double s = 0.0;
+                        for (int i = 0; i < NP; ++i) s += a.fphi[face_phi_index(NP, lf, o, nq, g, i)] * sW[c * NP + i];
+                        wt[c] = s;
+                    }
+                    for (int c = 0; c < 8; ++c) {
+                        double s = 0.0;
+                        for (int i = 0; i < NP; ++i) s += a.fphi[face_phi_index(NP, lf, o, nq, g, i)] * sQ[c * NP + i];
+                        qt[c] = s;
+                    }
+                    double st[4];
+                    const bool interior = E->face[lf] >= 0;
+                    const double* Pp = interior ? nullptr : a.bproj + 16 * E->bproj[lf];
+                    if (interior) {
+                        for (int c = 0; c < 4; ++c) {
+                            double s = 0.0;
+                            for (int k = 0; k <= pe; ++k)
+                                s += a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k] * sLam[lf][c][k];
+                            st[c] = s;
+                        }
+                    } else {
+                        for (int r = 0; r < 4; ++r) {
+                            double s = 0.0;
+                            for (int c = 0; c < 4; ++c) s += Pp[r * 4 + c] * (wt[c] - a.winf[c]);
+                            st[r] = a.winf[r] + s;
+                        }
+                    }
+                    double Fv[2][4], Jw[2][4][4], Jq[2][4][8];
+                    ns_flux_jac(st, qt, gm, mu, pr, Fv, Jw, Jq);
+                    pt.fwl[lf][g] = wl;
+                    for (int r = 0; r < 4; ++r) {
+                        const double fn = nx * Fv[0][r] + ny * Fv[1][r];
+                        pt.fTr[lf][g][r] = st[r];
+                        pt.fFH[lf][g][r] = wl * (interior ? fn - alpha * (st[r] - wt[r]) : fn);
+                        for (int c = 0; c < 8; ++c) pt.fJQ[lf][g][r * 8 + c] = wl * (nx * Jq[0][r][c] + ny * Jq[1][r][c]);
+                        for (int c = 0; c < 4; ++c) {
+                            const double jn = nx * Jw[0][r][c] + ny * Jw[1][r][c];
+                            if (interior) {
+                                pt.fJB[lf][g][r * 4 + c] = wl * (jn - (r == c ? alpha : 0.0));
+                                pt.fJA[lf][g][r * 4 + c] = wl * (r == c ? alpha : 0.0);
+                            } else {
+                                double s = 0.0;
+                                for (int k = 0; k < 4; ++k) s += (nx * Jw[0][r][k] + ny * Jw[1][r][k]) * Pp[k * 4 + c];
+                                pt.fJA[lf][g][r * 4 + c] = wl * s;
+                                pt.fJB[lf][g][r * 4 + c] = 0.0;
+                            }
+                        }
+                    }
+                }
+            }
         }
+    }
+    __syncthreads();
+    double* out = a.zbuf + (int64_t)blockIdx.x * LY::PER + LY::PT;
+    const double* src = reinterpret_cast<const double*>(&pt);
+    for (int t = tid; t < (int)(sizeof(pt) / 8); t += 64) out[t] = src[t];
 }
 
-// ---------------------------------------------------------------------------
-// condensation of the reduced system
-// ---------------------------------------------------------------------------
+// Reduced rows Zhat = Z - L R / |J| of the chunk's elements (256 threads per element):
+// thread (row, c) accumulates the row's entries in the columns of field c and its factor
+// fragment l_row[.][c][.] over the quadrature points, then applies the structured factors.
 template <int P, int PF>
-__global__ __launch_bounds__(256) void k_ns_condense(NsArgs a) {
+__global__ __launch_bounds__(256) void k_ns_zhat(NsArgs a) {
     using D = NsDims<P, PF>;
-    constexpr int NP = D::NP, N = D::N, NQ = D::NQ, NPF = D::NPF, F = D::F, NR = D::NR;
-    constexpr int NC = N + F + 1;
-    constexpr int LDM = N + 1;
+    using LY = NsLayout<P, PF>;
+    constexpr int NP = D::NP, N = D::N, NPF = D::NPF, F = D::F, NR = D::NR, Q = D::Q, QF = D::QF;
     constexpr int NTH = 256;
-    __shared__ double sM[NC * LDM];
+    __shared__ NsPoints<P, PF> pt;
+    // element tables: physical basis gradients, basis and face traces at the points
+    __shared__ double sGp[Q][2][NP];
+    __shared__ double sPh[Q][NP];
+    __shared__ double sFp[3][QF][NP];
+    __shared__ double sPs[3][QF][NPF];   // psi_k at the face points, zero for k > p_e
+    __shared__ double sG[2][NP][NP];
+    __shared__ double sBf[3][NP][NPF];
+    __shared__ double sMb[3][NP][NP];
+    __shared__ double sRq[8][NP];
+    __shared__ double sZr[NR];
+    __shared__ double sPr[4][NR];
+    const auto& vw_ = pt.vw_;
+    const auto& vwv = pt.vwv;
+    const auto& vqv = pt.vqv;
+    const auto& vF = pt.vF;
+    const auto& vJw = pt.vJw;
+    const auto& vJq = pt.vJq;
+    const auto& fwl = pt.fwl;
+    const auto& fFH = pt.fFH;
+    const auto& fJA = pt.fJA;
+    const auto& fJB = pt.fJB;
+    const auto& fJQ = pt.fJQ;
+    const auto& fTr = pt.fTr;
+
+    const int tid = threadIdx.x;
+    const int slot = a.start + blockIdx.x;
+    const ElemInfo* E = a.einfo + slot;
+    const double alpha = a.alpha, detj = E->detj;
+    const double invJ = 1.0 / detj;
+    double* ws = a.zbuf + (int64_t)blockIdx.x * LY::PER;
+    {
+        const double* src = ws + LY::PT;
+        double* dst = reinterpret_cast<double*>(&pt);
+        for (int t = tid; t < (int)(sizeof(pt) / 8); t += NTH) dst[t] = src[t];
+    }
+    for (int t = tid; t < Q * NP; t += NTH) {
+        const int qp = t / NP, i = t % NP;
+        const double r0 = a.vgrad[qp * NP + i], r1 = a.vgrad[(Q + qp) * NP + i];
+        sGp[qp][0][i] = r0 * E->jinv[0] + r1 * E->jinv[2];
+        sGp[qp][1][i] = r0 * E->jinv[1] + r1 * E->jinv[3];
+        sPh[qp][i] = a.vphi[qp * NP + i];
+    }
+    for (int t = tid; t < 3 * QF * NP; t += NTH) {
+        const int lf = t / (QF * NP), g = (t / NP) % QF, i = t % NP;
+        const int nq = E->pe[lf] + 2;
+        sFp[lf][g][i] = g < nq ? a.fphi[face_phi_index(NP, lf, E->orient[lf], nq, g, i)] : 0.0;
+    }
+    for (int t = tid; t < 3 * QF * NPF; t += NTH) {
+        const int lf = t / (QF * NPF), g = (t / NPF) % QF, k = t % NPF;
+        const int pe = E->pe[lf], nq = pe + 2;
+        sPs[lf][g][k] = (g < nq && k <= pe) ? a.leg[((nq - kMinFaceQ) * kMaxFaceQ + g) * (kMaxDegree + 1) + k] : 0.0;
+    }
+    __syncthreads();
+    // ---- the structured factors of R
+    for (int t = tid; t < 2 * NP * NP; t += NTH) {
+        const int d = t / (NP * NP), i = (t / NP) % NP, j = t % NP;
+        double v = 0.0;
+#pragma unroll 4
+        for (int qp = 0; qp < Q; ++qp) v += vw_[qp] * sGp[qp][d][i] * sPh[qp][j];
+        sG[d][i][j] = v;
+        ws[LY::G + t] = v;
+    }
+    for (int t = tid; t < 3 * NP * NPF; t += NTH) {
+        const int lf = t / (NP * NPF), i = (t / NPF) % NP, k = t % NPF;
+        double v = 0.0;
+        if (E->face[lf] >= 0)
+            for (int g = 0; g < E->pe[lf] + 2; ++g) v += fwl[lf][g] * sFp[lf][g][i] * sPs[lf][g][k];
+        sBf[lf][i][k] = v;
+        ws[LY::BF + t] = v;
+    }
+    for (int t = tid; t < 3 * NP * NP; t += NTH) {
+        const int lf = t / (NP * NP), i = (t / NP) % NP, j = t % NP;
+        double v = 0.0;
+        if (E->face[lf] < 0)
+            for (int g = 0; g < E->pe[lf] + 2; ++g) v += fwl[lf][g] * sFp[lf][g][i] * sFp[lf][g][j];
+        sMb[lf][i][j] = v;
+        ws[LY::MB + t] = v;
+    }
+    for (int t = tid; t < 8 * NP; t += NTH) {
+        // r_q = -[(tau, q) + (div tau, w) - <tau.n, lam or w_b>] for tau = phi_i e_(d, a)
+        const int da = t / NP, ii = t % NP, d = da / 4, fa = da % 4;
+        double s = 0.0;
+#pragma unroll 4
+        for (int qp = 0; qp < Q; ++qp) s += vw_[qp] * (sPh[qp][ii] * vqv[qp][da] + sGp[qp][d][ii] * vwv[qp][fa]);
+        for (int lf = 0; lf < 3; ++lf) {
+            const double nd = E->nrm[lf][d];
+            for (int g = 0; g < E->pe[lf] + 2; ++g) s -= fwl[lf][g] * sFp[lf][g][ii] * nd * fTr[lf][g][fa];
+        }
+        sRq[da][ii] = -s;
+        ws[LY::RQ + t] = -s;
+    }
+    __syncthreads();
+
+    // ---- reduced rows: task (row slot, field c); slots 0..63 are w rows, 64..127 skeleton rows
+    bool has_bnd = false;
+#pragma unroll
+    for (int lf = 0; lf < 3; ++lf) has_bnd |= E->face[lf] < 0;
+    double* Zh = ws;
+#pragma unroll 1
+    for (int it = 0; it < 2; ++it) {
+        // the barrier also keeps the compiler from holding the factor tables in registers
+        // across iterations
+        __syncthreads();
+        const int t = it * NTH + tid;
+        const int c = t >> 7, sl = t & 127;
+        const bool wrow = sl < 64;
+        const int r = wrow ? sl : N + (sl - 64);
+        const bool active = wrow ? sl < N : (sl - 64) < F;
+        if (!active) continue;
+        double zA[NP], zB[3][NPF], ell[2][NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) zA[j] = ell[0][j] = ell[1][j] = 0.0;
+#pragma unroll
+        for (int lf = 0; lf < 3; ++lf)
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) zB[lf][k] = 0.0;
+        double zr = 0.0;
+        double zD[NPF];   // skeleton rows: Lambda columns of the row's own face
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) zD[k] = 0.0;
+        if (wrow) {
+            const int fa = r / NP, ii = r % NP;
+#pragma unroll 1
+            for (int qp = 0; qp < Q; ++qp) {
+                const double g0 = sGp[qp][0][ii], g1 = sGp[qp][1][ii];
+                const double s = -(g0 * vJw[qp][0][fa * 4 + c] + g1 * vJw[qp][1][fa * 4 + c]);
+                const double t0 = -(g0 * vJq[qp][0][fa * 8 + c] + g1 * vJq[qp][1][fa * 8 + c]);
+                const double t1 = -(g0 * vJq[qp][0][fa * 8 + 4 + c] + g1 * vJq[qp][1][fa * 8 + 4 + c]);
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const double ph = sPh[qp][j];
+                    zA[j] += s * ph;
+                    ell[0][j] += t0 * ph;
+                    ell[1][j] += t1 * ph;
+                }
+                if (c == 0) zr += g0 * vF[qp][0][fa] + g1 * vF[qp][1][fa];
+            }
+#pragma unroll 1
+            for (int lf = 0; lf < 3; ++lf) {
+                const bool interior = E->face[lf] >= 0;
+                const int nq = E->pe[lf] + 2;
+#pragma unroll 1
+                for (int g = 0; g < nq; ++g) {
+                    const double phi_i = sFp[lf][g][ii];
+                    const double av = phi_i * fJA[lf][g][fa * 4 + c];
+                    const double u0 = phi_i * fJQ[lf][g][fa * 8 + c];
+                    const double u1 = phi_i * fJQ[lf][g][fa * 8 + 4 + c];
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        const double ph = sFp[lf][g][j];
+                        zA[j] += av * ph;
+                        ell[0][j] += u0 * ph;
+                        ell[1][j] += u1 * ph;
+                    }
+                    if (interior) {
+                        const double bv = phi_i * fJB[lf][g][fa * 4 + c];
+#pragma unroll
+                        for (int k = 0; k < NPF; ++k) zB[lf][k] += bv * sPs[lf][g][k];
+                    }
+                    if (c == 0) zr -= phi_i * fFH[lf][g][fa];
+                }
+            }
+        } else {
+            const int rf = r - N, lf = rf / (4 * NPF), fa = (rf / NPF) % 4, k = rf % NPF;
+            if (E->face[lf] >= 0 && k <= E->pe[lf]) {
+                const int nq = E->pe[lf] + 2;
+#pragma unroll 1
+                for (int g = 0; g < nq; ++g) {
+                    const double pk = sPs[lf][g][k];
+                    const double av = (c == fa) ? pk * fwl[lf][g] * alpha : 0.0;
+                    const double bv = pk * fJB[lf][g][fa * 4 + c];
+                    const double u0 = pk * fJQ[lf][g][fa * 8 + c];
+                    const double u1 = pk * fJQ[lf][g][fa * 8 + 4 + c];
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        const double ph = sFp[lf][g][j];
+                        zA[j] += av * ph;
+                        ell[0][j] += u0 * ph;
+                        ell[1][j] += u1 * ph;
+                    }
+#pragma unroll
+                    for (int l = 0; l < NPF; ++l) zD[l] += bv * sPs[lf][g][l];   // own face only
+                    if (c == 0) zr -= pk * fFH[lf][g][fa];
+                }
+            }
+#pragma unroll
+            for (int l2 = 0; l2 < 3; ++l2)
+                if (l2 == lf)
+#pragma unroll
+                    for (int k2 = 0; k2 < NPF; ++k2) zB[l2][k2] = zD[k2];
+        }
+        // Z part of the row's entries in the columns of field c
+#pragma unroll
+        for (int j = 0; j < NP; ++j) Zh[(int64_t)(c * NP + j) * NR + r] = zA[j];
+#pragma unroll
+        for (int lf = 0; lf < 3; ++lf)
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) Zh[(int64_t)(N + (lf * 4 + c) * NPF + k) * NR + r] = zB[lf][k];
+        // q elimination, one output column at a time: W columns (c, j), Lambda columns (lf, c, k),
+        // right-hand side part
+#pragma unroll 1
+        for (int j = 0; j < NP; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) v += ell[0][m] * sG[0][m][j] + ell[1][m] * sG[1][m][j];
+            Zh[(int64_t)(c * NP + j) * NR + r] -= invJ * v;
+        }
+#pragma unroll 1
+        for (int lk = 0; lk < 3 * NPF; ++lk) {
+            const int lf = lk / NPF, k = lk % NPF;
+            const double n0 = E->nrm[lf][0], n1 = E->nrm[lf][1];
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) v += (n0 * ell[0][m] + n1 * ell[1][m]) * sBf[lf][m][k];
+            Zh[(int64_t)(N + (lf * 4 + c) * NPF + k) * NR + r] += invJ * v;
+        }
+        {
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < NP; ++m) v += ell[0][m] * sRq[c][m] + ell[1][m] * sRq[4 + c][m];
+            sPr[c][r] = v;
+            if (c == 0) sZr[r] = zr;
+        }
+        // far-field faces: the gradient rows couple the fields through P+ (second pass)
+        if (has_bnd) {
+#pragma unroll 1
+            for (int lf = 0; lf < 3; ++lf) {
+                if (E->face[lf] >= 0) continue;
+                const double* Pp = a.bproj + 16 * E->bproj[lf];
+                double pc[4];
+#pragma unroll
+                for (int c2 = 0; c2 < 4; ++c2) pc[c2] = Pp[c2 * 4 + c];   // P+[c2][c]
+#pragma unroll
+                for (int m = 0; m < NP; ++m) ell[0][m] = ell[1][m] = 0.0;
+                if (wrow) {
+                    const int fa = r / NP, ii = r % NP;
+        #pragma unroll 1
+            for (int qp = 0; qp < Q; ++qp) {
+                        const double g0 = sGp[qp][0][ii], g1 = sGp[qp][1][ii];
+                        double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+                        for (int c2 = 0; c2 < 4; ++c2) {
+                            t0 -= pc[c2] * (g0 * vJq[qp][0][fa * 8 + c2] + g1 * vJq[qp][1][fa * 8 + c2]);
+                            t1 -= pc[c2] * (g0 * vJq[qp][0][fa * 8 + 4 + c2] + g1 * vJq[qp][1][fa * 8 + 4 + c2]);
+                        }
+#pragma unroll
+                        for (int m = 0; m < NP; ++m) {
+                            ell[0][m] += t0 * sPh[qp][m];
+                            ell[1][m] += t1 * sPh[qp][m];
+                        }
+                    }
+#pragma unroll 1
+                    for (int l2 = 0; l2 < 3; ++l2) {
+                        const int nq = E->pe[l2] + 2;
+        #pragma unroll 1
+                for (int g = 0; g < nq; ++g) {
+                            const double phi_i = sFp[l2][g][ii];
+                            double u0 = 0.0, u1 = 0.0;
+#pragma unroll
+                            for (int c2 = 0; c2 < 4; ++c2) {
+                                u0 += pc[c2] * fJQ[l2][g][fa * 8 + c2];
+                                u1 += pc[c2] * fJQ[l2][g][fa * 8 + 4 + c2];
+                            }
+#pragma unroll
+                            for (int m = 0; m < NP; ++m) {
+                                ell[0][m] += phi_i * u0 * sFp[l2][g][m];
+                                ell[1][m] += phi_i * u1 * sFp[l2][g][m];
+                            }
+                        }
+                    }
+                } else {
+                    const int rf = r - N, l2 = rf / (4 * NPF), fa = (rf / NPF) % 4, k = rf % NPF;
+                    if (E->face[l2] >= 0 && k <= E->pe[l2]) {
+                        const int nq = E->pe[l2] + 2;
+        #pragma unroll 1
+                for (int g = 0; g < nq; ++g) {
+                            const double pk = sPs[l2][g][k];
+                            double u0 = 0.0, u1 = 0.0;
+#pragma unroll
+                            for (int c2 = 0; c2 < 4; ++c2) {
+                                u0 += pc[c2] * fJQ[l2][g][fa * 8 + c2];
+                                u1 += pc[c2] * fJQ[l2][g][fa * 8 + 4 + c2];
+                            }
+#pragma unroll
+                            for (int m = 0; m < NP; ++m) {
+                                ell[0][m] += pk * u0 * sFp[l2][g][m];
+                                ell[1][m] += pk * u1 * sFp[l2][g][m];
+                            }
+                        }
+                    }
+                }
+                const double n0 = E->nrm[lf][0], n1 = E->nrm[lf][1];
+#pragma unroll 1
+                for (int j = 0; j < NP; ++j) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int m = 0; m < NP; ++m) v += (n0 * ell[0][m] + n1 * ell[1][m]) * sMb[lf][m][j];
+                    Zh[(int64_t)(c * NP + j) * NR + r] += invJ * v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = tid; r < NR; r += NTH)
+        Zh[(int64_t)(N + F) * NR + r] = sZr[r] - invJ * (((sPr[0][r] + sPr[1][r]) + sPr[2][r]) + sPr[3][r]);
+}
+
+// Condensation of the reduced system: Gauss-Jordan on [Ahat | Bhat | rhat] (gj_eliminate),
+// the gradient part of the local solutions X_q = (B_q - G_qw X_w)/|J|, y_q likewise, the
+// local store, S_K = Dhat - Chat X_w, g_K = rhat_lam - Chat y_w and the scatter.
+template <int P, int PF>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_ns_condense2(NsArgs a) {
+    using D = NsDims<P, PF>;
+    using LY = NsLayout<P, PF>;
+    constexpr int NP = D::NP, N = D::N, NQ = D::NQ, NPF = D::NPF, F = D::F, NR = D::NR;
+    constexpr int NBW = (F + 1 + 3) / 4;
+    constexpr int NTH = 256;
+    constexpr int NALL = NQ + N;
     __shared__ double sX[(F + 1) * N];
-    __shared__ double fmul[N];
-    __shared__ double pvk[N];
-    __shared__ int perm[N];
-    __shared__ int used[N];
-    __shared__ int piv_s;
+    __shared__ double sC[F * N];
+    __shared__ double sG[2][NP][NP];
+    __shared__ double sBf[3][NP][NPF];
+    __shared__ double sMb[3][NP][NP];
+    __shared__ double sRq[8][NP];
+    __shared__ double sFm[2][64];
+    __shared__ double sPVk[N];
+    __shared__ int sPiv[2];
+    __shared__ int sBad;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int slot = a.start + blockIdx.x;
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
-    const double detj = E->detj;
-    const double* Z = a.zbuf + (int64_t)blockIdx.x * D::PER;
-    const double* R = Z + D::ZSZ + D::LSZ;
-    for (int t = tid; t < NC * N; t += NTH) {
-        const int c = t / N, r = t % N;
-        sM[c * LDM + r] = Z[(int64_t)c * NR + r];
+    const double invJ = 1.0 / E->detj;
+    const double* ws = a.zbuf + (int64_t)blockIdx.x * LY::PER;
+    const double* Zh = ws;
+    if (tid == 0) sBad = 0;
+    for (int t = tid; t < 2 * NP * NP; t += NTH) (&sG[0][0][0])[t] = ws[LY::G + t];
+    for (int t = tid; t < 3 * NP * NPF; t += NTH) (&sBf[0][0][0])[t] = ws[LY::BF + t];
+    for (int t = tid; t < 3 * NP * NP; t += NTH) (&sMb[0][0][0])[t] = ws[LY::MB + t];
+    for (int t = tid; t < 8 * NP; t += NTH) (&sRq[0][0])[t] = ws[LY::RQ + t];
+    for (int t = tid; t < F * N; t += NTH) {
+        const int r = t % F, j = t / F;
+        sC[r * N + j] = Zh[(int64_t)j * NR + N + r];
     }
-    for (int r = tid; r < N; r += NTH) used[r] = 0;
-    __syncthreads();
-    for (int k = 0; k < N; ++k) {
-        if (wave == 0) {
-            double best = -1.0;
-            int idx = N;
-            for (int r = lane; r < N; r += 64) {
-                const double v = used[r] ? -1.0 : fabs(sM[k * LDM + r]);
-                if (v > best) {
-                    best = v;
-                    idx = r;
-                }
-            }
+    const int rr = lane < N ? lane : N - 1;
+    double mA[NP], mB[NBW];
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(best, off, 64);
-                const int oi = __shfl_xor(idx, off, 64);
-                if (ov > best || (ov == best && oi < idx)) {
-                    best = ov;
-                    idx = oi;
-                }
-            }
-            if (lane == 0) {
-                piv_s = idx;
-                used[idx] = 1;
-                perm[k] = idx;
-                pvk[k] = sM[k * LDM + idx];
+    for (int j = 0; j < NP; ++j) mA[j] = Zh[(int64_t)(wave * NP + j) * NR + rr];
+#pragma unroll
+    for (int i = 0; i < NBW; ++i) {
+        const int cb = wave * NBW + i;
+        mB[i] = cb <= F ? Zh[(int64_t)(N + cb) * NR + rr] : 0.0;
+    }
+    int mykk = 0;
+    gj_eliminate<NP, NBW>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
+    double* st = a.store + (int64_t)(slot - a.bucket_start) * ((F + 1) * NALL);
+    if (lane < N) {
+        const double pv = sPVk[mykk];
+        const double inv = 1.0 / pv;
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) {
+            const int cb = wave * NBW + i;
+            if (cb <= F) {
+                const double x = mB[i] * inv;
+                bad |= !isfinite(x);
+                sX[cb * N + mykk] = x;
+                st[(int64_t)cb * NALL + NQ + mykk] = x;
             }
         }
-        __syncthreads();
-        const int pv_r = piv_s;
-        const double pv = pvk[k];
-        for (int r = tid; r < N; r += NTH) fmul[r] = (r == pv_r) ? 0.0 : sM[k * LDM + r] / pv;
-        __syncthreads();
-        for (int t = tid; t < (NC - k - 1) * N; t += NTH) {
-            const int c = k + 1 + t / N, r = t % N;
-            if (r != pv_r) sM[c * LDM + r] -= fmul[r] * sM[c * LDM + pv_r];
-        }
-        __syncthreads();
+        if (!(fabs(pv) > 0.0) || !isfinite(inv)) sBad = 1;
+        else if (bad && sBad == 0) sBad = 2;
     }
-    bool bad = false, singular = false;
-    for (int t = tid; t < (F + 1) * N; t += NTH) {
-        const int c = t / N, k = t % N;
-        const double pv = pvk[k];
-        const double x = sM[(N + c) * LDM + perm[k]] / pv;
-        singular |= !(fabs(pv) > 0.0);
-        bad |= !isfinite(x);
-        sX[c * N + k] = x;
-    }
-    if (bad || singular) {
-        a.status[e] = singular ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+    __syncthreads();
+    if (tid == 0 && sBad != 0) {
+        a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
         a.flag[0] = 1;
     }
-    __syncthreads();
-    // local store: [F + 1 columns] x [q rows (NQ) ; w rows (N)]
-    constexpr int NALL = NQ + N;
-    double* st = a.store + (int64_t)(slot - a.bucket_start) * ((F + 1) * NALL);
-    for (int t = tid; t < (F + 1) * NALL; t += NTH) {
-        const int c = t / NALL, r = t % NALL;
-        double v;
-        if (r >= NQ) {
-            v = sX[c * N + (r - NQ)];
-        } else {
-            // X_q = (B_q - G_qw X_w) / |J|, y_q = (r_q - G_qw y_w) / |J|
-            double s = R[(int64_t)(N + c) * NQ + r];
-            for (int j = 0; j < N; ++j) s -= R[(int64_t)j * NQ + r] * sX[c * N + j];
-            v = s / detj;
+    // gradient rows of the local solutions: X_q = (B_q - G_qw X_w)/|J|, y_q = (r_q - G_qw y_w)/|J|
+    for (int t = tid; t < (F + 1) * NQ; t += NTH) {
+        const int c = t / NQ, rq = t % NQ;
+        const int da = rq / NP, m = rq % NP, d = da / 4, fa = da % 4;
+        const double* xc = sX + c * N;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) s += sG[d][m][j] * xc[fa * NP + j];
+        double v = -s;
+        for (int lf = 0; lf < 3; ++lf) {
+            if (E->face[lf] >= 0) continue;
+            const double* Pp = a.bproj + 16 * E->bproj[lf];
+            double u = 0.0;
+            for (int b = 0; b < 4; ++b) {
+                double sb = 0.0;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) sb += sMb[lf][m][j] * xc[b * NP + j];
+                u += Pp[fa * 4 + b] * sb;
+            }
+            v += E->nrm[lf][d] * u;
         }
-        st[(int64_t)c * NALL + r] = v;
+        if (c == F) {
+            v += sRq[da][m];
+        } else {
+            const int lf = c / (4 * NPF), b = (c / NPF) % 4, k = c % NPF;
+            if (b == fa) v -= E->nrm[lf][d] * sBf[lf][m][k];
+        }
+        st[(int64_t)c * NALL + rq] = v * invJ;
     }
-    // S_K = Dhat - Chat X_w, g_K = rhat_lam - Chat y_w on the valid skeleton rows/columns
+    // S_K = Dhat - Chat X_w, g_K = rhat_lam - Chat y_w on the valid skeleton rows and columns
     for (int t = tid; t < F * (F + 1); t += NTH) {
         const int c2 = t / F, r = t % F;
         const int lf = r / (4 * NPF), b = (r / NPF) % 4, k = r % NPF;
         const int f = E->face[lf], pe = E->pe[lf];
         if (f < 0 || k > pe) continue;
         const int se = 4 * (pe + 1), row = b * (pe + 1) + k;
-        double v = Z[(int64_t)(N + c2) * NR + N + r];
-        for (int j = 0; j < N; ++j) v -= Z[(int64_t)j * NR + N + r] * sX[c2 * N + j];
+        double v = Zh[(int64_t)(N + c2) * NR + N + r];
+        const double* cr = sC + r * N;
+        const double* xc = sX + c2 * N;
+#pragma unroll 4
+        for (int j = 0; j < N; ++j) v -= cr[j] * xc[j];
         if (c2 == F) {
             a.g_part[2 * a.face_off[f] + E->side[lf] * se + row] = v;
             continue;
@@ -594,14 +1055,15 @@ static hipError_t ns_bucket(const Plan& p, const Bucket& bk, NsArgs a, double* z
         hipLaunchKernelGGL((k_ns_assemble<P, PF>), dim3(1), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(bk.count, zcap_doubles / D::PER));
+    (void)assemble_only;
+    using LY = NsLayout<P, PF>;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(bk.count, zcap_doubles / LY::PER));
     for (int c0 = 0; c0 < bk.count; c0 += chunk) {
         const int cnt = std::min(chunk, bk.count - c0);
         a.start = bk.start + c0;
-        hipLaunchKernelGGL((k_ns_assemble<P, PF>), dim3(cnt), dim3(256), 0, s, a);
-        if (assemble_only) continue;
-        hipLaunchKernelGGL((k_ns_reduce<P, PF>), dim3(cnt), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_ns_condense<P, PF>), dim3(cnt), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_ns_points<P, PF>), dim3(cnt), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_ns_zhat<P, PF>), dim3(cnt), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_ns_condense2<P, PF>), dim3(cnt), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -609,6 +1071,13 @@ static hipError_t ns_bucket(const Plan& p, const Bucket& bk, NsArgs a, double* z
 int64_t ns_workspace_per_element(int p, int pf) {
     const int np = n_modes(p), n = 4 * np, nq = 8 * np, f = 12 * (pf + 1);
     return (int64_t)(n + f) * (n + f + 1) + (int64_t)(n + f) * nq + (int64_t)nq * (n + f + 1);
+}
+
+int64_t ns_chunk_per_element(int p, int pf) {
+    const int np = n_modes(p), n = 4 * np, npf = pf + 1, f = 12 * npf;
+    const int q = n_vol_q(p), qf = pf + 2;
+    const int64_t points = (int64_t)q * (1 + 4 + 8 + 8 + 32 + 64) + 3 * qf * (1 + 4 + 16 + 16 + 32 + 4);
+    return (int64_t)(n + f) * (n + f + 1) + 2 * np * np + 3 * np * npf + 3 * np * np + 8 * np + points;
 }
 
 #define HDG_NS_BUCKETS(X) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 2) X(2, 3) X(2, 4) X(3, 3) X(3, 4) X(4, 4)

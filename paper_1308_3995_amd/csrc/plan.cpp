@@ -501,7 +501,7 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
             }
         int64_t need = 0, per_max = 0;
         for (const Bucket& b : P.buckets) {
-            const int64_t per = ns_workspace_per_element(b.p, b.pf);
+            const int64_t per = ns_chunk_per_element(b.p, b.pf);
             need = std::max(need, per * b.count);
             per_max = std::max(per_max, per);
         }
