@@ -306,10 +306,11 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
     }
 }
 
-// Degrees 1..4 (N = 4 Np <= 60 rows): four wavefronts per element, one row of the
-// augmented system [A_K | B_K | r_K] per lane, the columns split between the waves:
-// wave w holds the A_K columns of field w and every fourth block of the B_K / r_K
-// columns; the elimination is gj_eliminate.
+// Register kernel (degrees 1..4): four wavefronts per element, RH = ceil(N / 64) rows of the
+// augmented system [A_K | B_K | r_K] per lane, the columns split between the waves: wave w
+// holds the A_K columns of field w and every fourth block of the B_K / r_K columns; the
+// elimination is gj_eliminate. (Degree 5, N = 84, needs two rows per lane; at that size the
+// register arrays spill and the LDS-resident kernel below is faster.)
 template <int P, int PF, bool DBG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_condense_euler(CondArgs a) {
     constexpr int NP = n_modes(P);
@@ -319,11 +320,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     constexpr int FB = 4 * NPF;                // B_K columns of one local face
     constexpr int NBW = (F + 1 + 3) / 4;       // B_K / r_K columns per wave (zero padded)
     constexpr int Q = n_vol_q(P);
-    static_assert(N <= 64, "one row per lane");
+    constexpr int RH = (N + 63) / 64;          // rows per lane
 
     __shared__ ElemShared<P, PF> sh;
     __shared__ double sX[(F + 1) * N];
-    __shared__ double sFm[2][64];
+    __shared__ double sFm[2][64 * RH];
     __shared__ double sPVk[N];
     __shared__ int sPiv[2];
     __shared__ int sBad;
@@ -341,95 +342,99 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const auto& sJB = sh.sJB;
     const auto& sFH = sh.sFH;
 
-    const int rr = lane < N ? lane : N - 1;
-    const int fa = rr / NP, ii = rr % NP;
-
-    // ---- A_K columns of field b = wave: volume and face terms (eq. hdg_ls2 linearised)
-    double mA[NP];
+    double mA[RH][NP], mB[RH][NBW];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) mA[j] = 0.0;
-    {
-        const int b = wave;
-        for (int q = 0; q < Q; ++q) {
-            const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
-            const double s = -(g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]);
+    for (int h = 0; h < RH; ++h) {
+        const int row = h * 64 + lane;
+        const int rr = row < N ? row : N - 1;
+        const int fa = rr / NP, ii = rr % NP;
+        // ---- A_K columns of field b = wave: volume and face terms (eq. hdg_ls2 linearised)
 #pragma unroll
-            for (int j = 0; j < NP; ++j) mA[j] += s * a.vphi[q * NP + j];
-        }
-#pragma unroll
-        for (int lf = 0; lf < 3; ++lf) {
-            const int nq = E->pe[lf] + 2, o = E->orient[lf];
-            for (int g = 0; g < nq; ++g) {
-                const double t = a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJA[lf][g][fa * 4 + b];
-#pragma unroll
-                for (int j = 0; j < NP; ++j) mA[j] += t * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
-            }
-        }
-    }
-
-    // ---- B_K / r_K columns cb = wave * NBW + i (cb < F: face lf, field b, mode k; cb = F: r_K)
-    double mB[NBW];
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) {
-        const int cb = wave * NBW + i;
-        double v = 0.0;
-        if (cb < F) {
-            const int lf = cb / FB, b = (cb / NPF) % 4, k = cb % NPF;
-            const int pe = E->pe[lf];
-            if (E->face[lf] >= 0 && k <= pe) {
-                const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
-                for (int g = 0; g < nq; ++g)
-                    v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJB[lf][g][fa * 4 + b] *
-                         a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
-            }
-        } else if (cb == F) {
+        for (int j = 0; j < NP; ++j) mA[h][j] = 0.0;
+        {
+            const int b = wave;
             for (int q = 0; q < Q; ++q) {
                 const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
-                v += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
+                const double s = -(g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]);
+#pragma unroll
+                for (int j = 0; j < NP; ++j) mA[h][j] += s * a.vphi[q * NP + j];
             }
 #pragma unroll
-            for (int l2 = 0; l2 < 3; ++l2) {
-                const int nq = E->pe[l2] + 2, o = E->orient[l2];
-                for (int g = 0; g < nq; ++g) v -= a.fphi[face_phi_index(NP, l2, o, nq, g, ii)] * sFH[l2][g][fa];
+            for (int lf = 0; lf < 3; ++lf) {
+                const int nq = E->pe[lf] + 2, o = E->orient[lf];
+                for (int g = 0; g < nq; ++g) {
+                    const double t = a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJA[lf][g][fa * 4 + b];
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) mA[h][j] += t * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
+                }
             }
         }
-        mB[i] = v;
-    }
-    if (DBG) {
-        if (lane < N) {
+        // ---- B_K / r_K columns cb = wave * NBW + i (cb < F: face lf, field b, mode k; cb = F: r_K)
 #pragma unroll
-            for (int j = 0; j < NP; ++j) a.debug[(int64_t)(wave * NP + j) * N + lane] = mA[j];
+        for (int i = 0; i < NBW; ++i) {
+            const int cb = wave * NBW + i;
+            double v = 0.0;
+            if (cb < F) {
+                const int lf = cb / FB, b = (cb / NPF) % 4, k = cb % NPF;
+                const int pe = E->pe[lf];
+                if (E->face[lf] >= 0 && k <= pe) {
+                    const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+                    for (int g = 0; g < nq; ++g)
+                        v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJB[lf][g][fa * 4 + b] *
+                             a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
+                }
+            } else if (cb == F) {
+                for (int q = 0; q < Q; ++q) {
+                    const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
+                    v += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
+                }
+#pragma unroll
+                for (int l2 = 0; l2 < 3; ++l2) {
+                    const int nq = E->pe[l2] + 2, o = E->orient[l2];
+                    for (int g = 0; g < nq; ++g) v -= a.fphi[face_phi_index(NP, l2, o, nq, g, ii)] * sFH[l2][g][fa];
+                }
+            }
+            mB[h][i] = v;
+        }
+        if (DBG && row < N) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) a.debug[(int64_t)(wave * NP + j) * N + row] = mA[h][j];
 #pragma unroll
             for (int i = 0; i < NBW; ++i) {
                 const int cb = wave * NBW + i;
-                if (cb <= F) a.debug[(int64_t)(N + cb) * N + lane] = mB[i];
+                if (cb <= F) a.debug[(int64_t)(N + cb) * N + row] = mB[h][i];
             }
         }
+    }
+    if (DBG) {
         __syncthreads();
         schur_rows<P, PF, DBG>(a, E, sh, sX, tid, 256);
         return;
     }
 
     // ---- Gauss-Jordan elimination with partial pivoting
-    int mykk = 0;
-    gj_eliminate<NP, NBW>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
+    int mykk[RH];
+    gj_eliminate<NP, NBW, RH>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
 
     // ---- X_K = A_K^-1 B_K and y_K = A_K^-1 r_K: row kk of the solution sits in the row
     // whose pivot was taken at step kk
     const int bslot = slot - a.start;
-    if (lane < N) {
-        const double pv = sPVk[mykk];
+    double* st = a.store + (int64_t)bslot * ((F + 1) * N);
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        if (h * 64 + lane >= N) continue;
+        const int kk = mykk[h];
+        const double pv = sPVk[kk];
         const double inv = 1.0 / pv;
-        double* st = a.store + (int64_t)bslot * ((F + 1) * N);
         bool bad = false;
 #pragma unroll
         for (int i = 0; i < NBW; ++i) {
             const int cb = wave * NBW + i;
             if (cb <= F) {
-                const double x = mB[i] * inv;
+                const double x = mB[h][i] * inv;
                 bad |= !isfinite(x);
-                sX[cb * N + mykk] = x;
-                st[(int64_t)cb * N + mykk] = x;
+                sX[cb * N + kk] = x;
+                st[(int64_t)cb * N + kk] = x;
             }
         }
         if (!(fabs(pv) > 0.0) || !isfinite(inv)) sBad = 1;
@@ -633,8 +638,8 @@ __global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start
         }
 }
 
-// Degrees up to 3 take the register kernel (four wavefronts per element, columns split);
-// degrees 4 and 5 take the LDS-resident kernel.
+// Degrees up to 4 take the register kernel (four wavefronts per element, columns split);
+// degree 5 takes the LDS-resident kernel.
 template <int P, int PF>
 static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, hipStream_t s) {
     a.vphi = p.d_tab + p.tix.vol_phi[P];

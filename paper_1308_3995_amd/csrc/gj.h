@@ -1,7 +1,7 @@
 // Gauss-Jordan elimination with partial pivoting shared by the condensation kernels.
 //
 // A workgroup of four wavefronts holds an augmented local system [A | B | r] with N = 4 Np
-// rows (N <= 64), one row per lane: wave w holds the A columns w Np .. w Np + Np - 1 in
+// rows (N <= 64 RH), RH rows per lane: wave w holds the A columns w Np .. w Np + Np - 1 in
 // mA and NBW further right-hand-side columns in mB. The elimination runs step by step over
 // the whole workgroup: the wave holding column k picks the pivot row among the rows not
 // yet used and publishes the multipliers through LDS (double-buffered, one barrier per
@@ -9,7 +9,7 @@
 // from the pivot lane. The owner of the next pivot column updates that column first and
 // searches its pivot before finishing the rest of the step (one-column lookahead).
 // Afterwards row r holds (pivot of step kk) x (row kk of A^-1 [B | r]) with kk = mykk of
-// lane r, and sPVk[kk] holds that pivot.
+// row r, and sPVk[kk] holds that pivot. With RH = 2 a lane holds rows lane and 64 + lane.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,66 +36,110 @@ __device__ __forceinline__ unsigned wave_max_key(unsigned x) {
     return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Pivot row for column value v: the lowest lane among the unused rows whose |v|, rounded to
-// single precision, is largest. The single-precision comparison keeps the pivot within a
-// factor 1 - 2^-24 of the largest candidate, which is as stable as exact partial pivoting.
-// Keys: 0 for used rows, bits(|v|) + 1 otherwise (the bit pattern of a non-negative float
-// orders like its value).
-__device__ __forceinline__ int pivot_lane(double v, bool used) {
-    const unsigned key = used ? 0u : (unsigned)__float_as_int((float)fabs(v)) + 1u;
-    const unsigned mx = wave_max_key(key);
-    const unsigned long long m = __ballot(key == mx);
-    return m ? __ffsll((long long)m) - 1 : 0;
+// Pivot row for column values v[h] (row h * 64 + lane): the lowest row among the unused
+// rows whose |v|, rounded to single precision, is largest. The single-precision comparison
+// keeps the pivot within a factor 1 - 2^-24 of the largest candidate, which is as stable as
+// exact partial pivoting. Keys: 0 for used rows, bits(|v|) + 1 otherwise (the bit pattern
+// of a non-negative float orders like its value).
+template <int RH>
+__device__ __forceinline__ int pivot_row(const double (&v)[RH], const bool (&used)[RH]) {
+    unsigned key[RH], best = 0u;
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        key[h] = used[h] ? 0u : (unsigned)__float_as_int((float)fabs(v[h])) + 1u;
+        best = max(best, key[h]);
+    }
+    const unsigned mx = wave_max_key(best);
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        const unsigned long long m = __ballot(key[h] == mx);
+        if (m) return h * 64 + __ffsll((long long)m) - 1;
+    }
+    return 0;
 }
 
-template <int NP, int NBW>
-__device__ __forceinline__ void gj_eliminate(double (&mA)[NP], double (&mB)[NBW], int wave, int lane,
-                                             double (*sFm)[64], int* sPiv, double* sPVk, int& mykk) {
+// Gauss-Jordan elimination over a workgroup of four waves; RH row halves per lane (rows
+// lane and 64 + lane), N = 4 Np <= 64 RH rows. mykk[h] receives the step at which row
+// h * 64 + lane was the pivot row.
+template <int NP, int NBW, int RH>
+__device__ __forceinline__ void gj_eliminate(double (&mA)[RH][NP], double (&mB)[RH][NBW], int wave, int lane,
+                                             double (*sFm)[64 * RH], int* sPiv, double* sPVk, int (&mykk)[RH]) {
     constexpr int N = 4 * NP;
-    static_assert(N <= 64, "one row per lane");
-    bool used = lane >= N;
-    mykk = 0;
-    if (wave == 0) {
-        const int piv = pivot_lane(mA[0], used);
-        const double pv = lane_bcast(mA[0], piv);
-        sFm[0][lane] = (lane == piv || lane >= N) ? 0.0 : mA[0] / pv;
-        if (lane == 0) {
-            sPiv[0] = piv;
-            sPVk[0] = pv;
+    static_assert(N <= 64 * RH, "rows per lane");
+    bool used[RH];
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        used[h] = h * 64 + lane >= N;
+        mykk[h] = 0;
+    }
+    // entry of the pivot row held by this wave in a column (p uniform)
+    auto prow = [&](const double (&col)[RH], int p) {
+        double v = col[0];
+#pragma unroll
+        for (int h = 1; h < RH; ++h)
+            if ((p >> 6) == h) v = col[h];
+        return lane_bcast(v, p & 63);
+    };
+    auto publish = [&](int k, const double (&col)[RH]) {
+        const int pn = pivot_row<RH>(col, used);
+        const double pv = prow(col, pn);
+#pragma unroll
+        for (int h = 0; h < RH; ++h) {
+            const int row = h * 64 + lane;
+            sFm[k & 1][h * 64 + lane] = (row == pn || row >= N) ? 0.0 : col[h] / pv;
         }
+        if (lane == 0) {
+            sPiv[k & 1] = pn;
+            sPVk[k] = pv;
+        }
+    };
+    if (wave == 0) {
+        double c0[RH];
+#pragma unroll
+        for (int h = 0; h < RH; ++h) c0[h] = mA[h][0];
+        publish(0, c0);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 1; k <= N; ++k) {
         // apply step k - 1; the owner of column k (if any) then publishes step k
         const int piv = __builtin_amdgcn_readfirstlane(sPiv[(k - 1) & 1]);
-        const double f = sFm[(k - 1) & 1][lane];
-        if (lane == piv) {
-            used = true;
-            mykk = k - 1;
+        double f[RH];
+#pragma unroll
+        for (int h = 0; h < RH; ++h) {
+            f[h] = sFm[(k - 1) & 1][h * 64 + lane];
+            if (h * 64 + lane == piv) {
+                used[h] = true;
+                mykk[h] = k - 1;
+            }
         }
+        auto update = [&](auto& m, int j) {
+            double col[RH];
+#pragma unroll
+            for (int h = 0; h < RH; ++h) col[h] = m[h][j];
+            const double pr = prow(col, piv);
+#pragma unroll
+            for (int h = 0; h < RH; ++h) m[h][j] -= f[h] * pr;
+        };
         const int ow = k / NP, jk = k % NP;   // column k = A column jk of wave ow
         if (k < N && wave == ow) {
-            mA[jk] -= f * lane_bcast(mA[jk], piv);
-            const int pn = pivot_lane(mA[jk], used);
-            const double pv = lane_bcast(mA[jk], pn);
-            sFm[k & 1][lane] = (lane == pn || lane >= N) ? 0.0 : mA[jk] / pv;
-            if (lane == 0) {
-                sPiv[k & 1] = pn;
-                sPVk[k] = pv;
-            }
+            update(mA, jk);
+            double ck[RH];
 #pragma unroll
-            for (int j = jk + 1; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
+            for (int h = 0; h < RH; ++h) ck[h] = mA[h][jk];
+            publish(k, ck);
+#pragma unroll
+            for (int j = jk + 1; j < NP; ++j) update(mA, j);
         } else if (wave > (k - 1) / NP) {
             // every A column of this wave has index >= k
 #pragma unroll
-            for (int j = 0; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
+            for (int j = 0; j < NP; ++j) update(mA, j);
         } else if (wave == (k - 1) / NP) {
 #pragma unroll
-            for (int j = (k - 1) % NP + 1; j < NP; ++j) mA[j] -= f * lane_bcast(mA[j], piv);
+            for (int j = (k - 1) % NP + 1; j < NP; ++j) update(mA, j);
         }
 #pragma unroll
-        for (int i = 0; i < NBW; ++i) mB[i] -= f * lane_bcast(mB[i], piv);
+        for (int i = 0; i < NBW; ++i) update(mB, i);
         __syncthreads();
     }
 }

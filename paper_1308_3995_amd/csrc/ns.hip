@@ -948,16 +948,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         sC[r * N + j] = Zh[(int64_t)j * NR + N + r];
     }
     const int rr = lane < N ? lane : N - 1;
-    double mA[NP], mB[NBW];
+    double mA[1][NP], mB[1][NBW];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) mA[j] = Zh[(int64_t)(wave * NP + j) * NR + rr];
+    for (int j = 0; j < NP; ++j) mA[0][j] = Zh[(int64_t)(wave * NP + j) * NR + rr];
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
         const int cb = wave * NBW + i;
-        mB[i] = cb <= F ? Zh[(int64_t)(N + cb) * NR + rr] : 0.0;
+        mB[0][i] = cb <= F ? Zh[(int64_t)(N + cb) * NR + rr] : 0.0;
     }
-    int mykk = 0;
-    gj_eliminate<NP, NBW>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
+    int mk[1];
+    gj_eliminate<NP, NBW, 1>(mA, mB, wave, lane, sFm, sPiv, sPVk, mk);
+    const int mykk = mk[0];
     double* st = a.store + (int64_t)(slot - a.bucket_start) * ((F + 1) * NALL);
     if (lane < N) {
         const double pv = sPVk[mykk];
@@ -967,7 +968,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         for (int i = 0; i < NBW; ++i) {
             const int cb = wave * NBW + i;
             if (cb <= F) {
-                const double x = mB[i] * inv;
+                const double x = mB[0][i] * inv;
                 bad |= !isfinite(x);
                 sX[cb * N + mykk] = x;
                 st[(int64_t)cb * NALL + NQ + mykk] = x;
