@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the Poisson serving stream to run (0 = skip; 512 = the full stream)")
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-max-iter", type=int, default=20000,
+                    help="GMRES iterations per serving request before it counts as not converged")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -180,15 +182,17 @@ def main():
         from paper_1308_3995_amd.serving import ServingEngine, stream_requests
         log(f"[bench] serving: generating {args.serving_requests} requests")
         reqs = stream_requests(512, 200.0, rtol=args.rtol)[: args.serving_requests]
-        eng = ServingEngine(max_slots=args.serving_slots, precision="mixed", restart=args.restart)
+        eng = ServingEngine(max_slots=args.serving_slots, precision="mixed", restart=args.restart,
+                            max_iter=args.serving_max_iter)
         st = eng.run(reqs, on_result=lambda r: log(f"[bench] serving: request {r.index} done, "
                                                    f"latency {r.latency_s:.3f} s, {r.elements} elements, "
-                                                   f"{r.gmres_iters} GMRES iterations"))
+                                                   f"{r.gmres_iters} GMRES iterations, status {r.status}"))
         sm = st.summary()
         sm["workload"] = (f"first {args.serving_requests} of 512 Poisson requests at 200/s (seed 1313): "
                           f"2k-64k triangles log-uniform, p in 1..4, Euler or NS, Mach U(0.3,0.9), "
-                          f"alpha U(-3,3) deg; mixed precision, GMRES({args.restart}) to {args.rtol:g}; "
-                          f"{args.serving_slots} slots")
+                          f"alpha U(-3,3) deg; mixed precision, GMRES({args.restart}) to {args.rtol:g} "
+                          f"within {args.serving_max_iter} iterations; {args.serving_slots} slots; "
+                          f"latencies over the completed requests")
         out["serving"] = sm
         log(f"[bench] serving: p50 {sm['p50_latency_s']:.3f} s, p99 {sm['p99_latency_s']:.3f} s, "
             f"{sm['elements_per_s']:.0f} elements/s")

@@ -62,7 +62,12 @@ class ServeStats:
         lat = np.array([r.latency_s for r in ok]) if ok else np.zeros(1)
         ne = sum(r.elements for r in ok)
         nd = sum(r.skel_dofs for r in ok)
+        failed = {}
+        for r in self.results:
+            if r.status != 0:
+                failed[r.status] = failed.get(r.status, 0) + 1
         return {"requests": len(self.results), "completed": len(ok),
+                "failed_by_status": {int(k): v for k, v in sorted(failed.items())},
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "elements_per_s": ne / self.wall_s if self.wall_s > 0 else 0.0,
                 "skeleton_dof_per_s": nd / self.wall_s if self.wall_s > 0 else 0.0,
@@ -72,7 +77,7 @@ class ServeStats:
 
 class ServingEngine:
     def __init__(self, max_slots: int = 8, hbm_budget_bytes: Optional[int] = None, precision: str = "mixed",
-                 restart: int = 30, keep_results: bool = False, device: int = 0):
+                 restart: int = 30, max_iter: int = 20000, keep_results: bool = False, device: int = 0):
         import torch
         self.max_slots = max_slots
         if hbm_budget_bytes is None:
@@ -81,6 +86,7 @@ class ServingEngine:
         self.budget = int(hbm_budget_bytes)
         self.precision = precision
         self.restart = restart
+        self.max_iter = max_iter   # GMRES iterations per request before it is reported NOT_CONVERGED
         self.keep = keep_results
         self.device = device
         self._lock = threading.Lock()
@@ -113,8 +119,8 @@ class ServingEngine:
                 dw = torch.zeros_like(w)
                 dq = torch.zeros_like(q) if q is not None else None
                 plan.hdg_assemble_condense(w, lam, q=q, stream=stream)
-                it, rr, status = plan.hdg_skeleton_solve(dlam, rtol=req.rtol, restart=self.restart, stream=stream,
-                                                         raise_on_fail=False)
+                it, rr, status = plan.hdg_skeleton_solve(dlam, rtol=req.rtol, restart=self.restart,
+                                                         max_iter=self.max_iter, stream=stream, raise_on_fail=False)
                 plan.hdg_back_substitute(dlam, dw, dq, stream=stream)
                 stream.synchronize()
                 if self.keep:
