@@ -55,6 +55,86 @@ def cpu_baseline(ng: int = 16):
             "seconds": dt}
 
 
+def condensation_work(case):
+    """Algorithmic flops and HBM bytes of assembling and condensing every element once.
+
+    Per element with n = 4 N_p state unknowns and f skeleton unknowns on its interior faces
+    (f = sum of 4 (p_e + 1), no padding): LU-equivalent factorisation 2n^3/3, the solves for
+    the f + 1 right-hand sides 2n^2 (f + 1), the Schur complement C_K X_K with C_K's actual
+    structure (Euler: the field-diagonal trace mass, N_p entries per row; Navier-Stokes: dense
+    after the gradient elimination, plus that elimination 2 (n + f)(n + f + 1) 2 N_p and the
+    gradient rows of the local solutions 2 (8 N_p)(f + 1) N_p). The quadrature contractions of
+    the assembly are not counted. Bytes: state in (W, and Q for Navier-Stokes), lambda in, 100 B
+    of geometry, S_K, g_K, X_K, y_K out, all float64.
+    """
+    import hdg_inputs as hi
+    tri, deg = case.tri, case.degree.astype(np.int64)
+    ne = tri.shape[0]
+    e = np.sort(np.concatenate([tri[:, [0, 1]], tri[:, [1, 2]], tri[:, [2, 0]]], axis=0), axis=1)
+    _, inv, cnt = np.unique(e, axis=0, return_inverse=True, return_counts=True)
+    inv = inv.reshape(-1)
+    owner = np.tile(np.arange(ne), 3)
+    pe = np.zeros(cnt.shape[0], dtype=np.int64)
+    np.maximum.at(pe, inv, deg[owner])
+    interior = cnt[inv] == 2
+    f = np.zeros(ne, dtype=np.float64)
+    np.add.at(f, owner[interior], 4.0 * (pe[inv][interior] + 1))
+    npm = np.array([hi.n_modes(int(p)) for p in deg], dtype=np.float64)
+    n = 4.0 * npm
+    flops = 2.0 * n ** 3 / 3.0 + 2.0 * n ** 2 * (f + 1.0)
+    out_rows = n
+    if case.physics == "ns":
+        nq = 8.0 * npm
+        flops += 2.0 * n * f * (f + 1.0) + 2.0 * (n + f) * (n + f + 1.0) * 2.0 * npm + 2.0 * nq * (f + 1.0) * npm
+        bytes_in = (n + nq) * 8.0
+        out_rows = n + nq
+    else:
+        flops += 2.0 * npm * f * (f + 1.0)
+        bytes_in = n * 8.0
+    nbytes = bytes_in + f * 8.0 + 100.0 + (f * f + f + out_rows * (f + 1.0)) * 8.0
+    return float(flops.sum()), float(nbytes.sum())
+
+
+def condensation_report(names, reps: int = 10):
+    """Assemble + condense time of each named workload (float64 path), with its roofline."""
+    import torch
+    import hdg_inputs as hi
+    import paper_1308_3995_amd as hdg
+    out = {}
+    for name in names:
+        case = hi.config_case(name)
+        plan = hdg.HDGPlan.from_case(case, precision="fp64")
+        dev = plan.device
+        w = torch.tensor(case.W, dtype=torch.float64, device=dev)
+        q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
+        lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
+        for _ in range(2):
+            plan.hdg_assemble_condense(w, lam, q=q)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.hdg_assemble_condense(w, lam, q=q)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        fl, by = condensation_work(case)
+        t_f = fl / (FP64_PEAK_TFLOPS * 1e12)
+        t_b = by / (HBM_PEAK_GBS * 1e9)
+        out[name] = {"workload": f"{case.physics} {case.ng}x{case.ng}, degrees {sorted(set(case.degree.tolist()))}",
+                     "elements": case.n_elements, "ms": ms, "elements_per_s": case.n_elements / (ms * 1e-3),
+                     "algorithmic_gflop": fl / 1e9, "algorithmic_gb": by / 1e9,
+                     "achieved_tflops": fl / (ms * 1e-3) / 1e12, "achieved_gbs": by / (ms * 1e-3) / 1e9,
+                     "bound": "fp64" if t_f >= t_b else "hbm", "roofline_frac": max(t_f, t_b) / (ms * 1e-3)}
+        log(f"[bench] condensation {name}: {ms:.3f} ms, {case.n_elements / ms / 1e3:.2f} M elements/s, "
+            f"roofline {out[name]['roofline_frac']:.3f} ({out[name]['bound']})")
+        del plan
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +149,8 @@ def main():
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-max-iter", type=int, default=20000,
                     help="GMRES iterations per serving request before it counts as not converged")
+    ap.add_argument("--condense-configs", default="c2,c3,c4",
+                    help="workloads whose assemble + condense time is reported beside the step ('' = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -178,6 +260,8 @@ def main():
                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                        "launches": kl, "avg_launch_us": kms / max(1, kl) * 1e3,
                        "bytes_per_launch": kb / max(1, kl)}
+    if args.condense_configs:
+        out["condensation"] = condensation_report([c for c in args.condense_configs.split(",") if c])
     if args.serving_requests > 0:
         from paper_1308_3995_amd.serving import ServingEngine, stream_requests
         log(f"[bench] serving: generating {args.serving_requests} requests")

@@ -222,7 +222,49 @@ __device__ __forceinline__ void point_data(const CondArgs& a, const ElemInfo* E,
 
 }
 
-// Phase 6 of both kernels: skeleton rows (local face, field, mode) of
+// Face tables of one element for the skeleton rows, built once per element in LDS:
+// psi_k at the face points (zero for k > p_e), the trace mass T[lf][k][j] = int_e psi_k phi_j
+// and the skeleton residual r_lam[lf][k][b] = -int_e psi_k F^_b (zero on boundary faces).
+template <int P, int PF>
+struct FaceTables {
+    static constexpr int NP = n_modes(P), NPF = PF + 1, QF = PF + 2;
+    double ps[3][QF][NPF];
+    double T[3][NPF][NP];
+    double rl[3][NPF][4];
+};
+
+// sFp: the element's basis at its face points, [lf][g][i] (QF points per face, zero past p_e + 2).
+template <int P, int PF>
+__device__ __forceinline__ void face_tables(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
+                                            const double* sFp, FaceTables<P, PF>& ft, int tid, int nth) {
+    constexpr int NP = n_modes(P), NPF = PF + 1, QF = PF + 2;
+    for (int t = tid; t < 3 * QF * NPF; t += nth) {
+        const int lf = t / (QF * NPF), g = (t / NPF) % QF, k = t % NPF;
+        const int pe = E->pe[lf], nq = pe + 2;
+        ft.ps[lf][g][k] = (g < nq && k <= pe) ? a.leg[((nq - kMinFaceQ) * kMaxFaceQ + g) * (kMaxDegree + 1) + k] : 0.0;
+    }
+    __syncthreads();
+    for (int t = tid; t < 3 * NPF * NP; t += nth) {
+        const int lf = t / (NPF * NP), k = (t / NP) % NPF, j = t % NP;
+        const int pe = E->pe[lf], nq = pe + 2, rule = nq - kMinFaceQ;
+        double v = 0.0;
+        if (E->face[lf] >= 0 && k <= pe) {
+            const double hl = 0.5 * E->len[lf];
+            for (int g = 0; g < nq; ++g)
+                v += a.gw[rule * kMaxFaceQ + g] * hl * ft.ps[lf][g][k] * sFp[(lf * QF + g) * NP + j];
+        }
+        ft.T[lf][k][j] = v;
+    }
+    for (int t = tid; t < 3 * NPF * 4; t += nth) {
+        const int lf = t / (NPF * 4), k = (t / 4) % NPF, b = t % 4;
+        double v = 0.0;
+        if (E->face[lf] >= 0 && k <= E->pe[lf])
+            for (int g = 0; g < E->pe[lf] + 2; ++g) v -= ft.ps[lf][g][k] * sh.sFH[lf][g][b];
+        ft.rl[lf][k][b] = v;
+    }
+}
+
+// Skeleton rows (local face, field, mode) of
 //   S_K = D_K - C_K X_K,   g_K = r_lam,K - C_K y_K.
 // sX holds [X_K | y_K] column-major with N rows. The nth threads split the F x F entries:
 // thread t takes row t % F and every CH-th column from t / F, so consecutive threads store
@@ -230,7 +272,7 @@ __device__ __forceinline__ void point_data(const CondArgs& a, const ElemInfo* E,
 // written to the debug buffer instead.
 template <int P, int PF, bool DBG>
 __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
-                                           const double* sX, int tid, int nth) {
+                                           const FaceTables<P, PF>& ft, const double* sX, int tid, int nth) {
     constexpr int NP = n_modes(P);
     constexpr int N = 4 * NP;
     constexpr int NPF = PF + 1;
@@ -238,30 +280,18 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
     constexpr int NC = N + F + 1;
     const int CH = nth >= F ? nth / F : 1;
     const double alpha = a.alpha;
-    const auto& sFH = sh.sFH;
     const auto& sJB = sh.sJB;
     for (int t = tid; t < F * CH; t += nth) {
         const int r = t % F, ch = t / F;
         const int lf = r / (4 * NPF), b = (r / NPF) % 4, k = r % NPF;
         const int f = E->face[lf], pe = E->pe[lf];
         if (!DBG && (f < 0 || k > pe)) continue;
-        const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
+        const int nq = pe + 2;
         const bool valid = f >= 0 && k <= pe;
-        const double hl = 0.5 * E->len[lf];
-        // trace mass T[j] = int_e psi_k phi_j
         double T[NP];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) T[j] = 0.0;
-        double rl = 0.0;
-        if (valid) {
-            for (int g = 0; g < nq; ++g) {
-                const double pk = a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
-                const double wpk = a.gw[rule * kMaxFaceQ + g] * hl * pk;
-#pragma unroll
-                for (int j = 0; j < NP; ++j) T[j] += wpk * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
-                rl -= pk * sFH[lf][g][b];
-            }
-        }
+        for (int j = 0; j < NP; ++j) T[j] = ft.T[lf][k][j];
+        const double rl = ft.rl[lf][k][b];
         const int se = 4 * (pe + 1);
         const int row = b * (pe + 1) + k;
         if (ch == 0) {
@@ -280,12 +310,8 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
         for (int c2 = ch; c2 < F; c2 += CH) {
             const int lf2 = c2 / (4 * NPF), b2 = (c2 / NPF) % 4, l = c2 % NPF;
             double dv = 0.0;
-            if (lf2 == lf && valid && l <= pe) {
-                for (int g = 0; g < nq; ++g) {
-                    const double* lg = a.leg + (rule * kMaxFaceQ + g) * (kMaxDegree + 1);
-                    dv += lg[k] * lg[l] * sJB[lf][g][b * 4 + b2];
-                }
-            }
+            if (lf2 == lf && valid && l <= pe)
+                for (int g = 0; g < nq; ++g) dv += ft.ps[lf][g][k] * ft.ps[lf][g][l] * sJB[lf][g][b * 4 + b2];
             if (DBG) {
                 a.debug[(int64_t)NC * N + (int64_t)N * F + (int64_t)c2 * F + r] = dv;
                 continue;
@@ -306,23 +332,34 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
     }
 }
 
-// Register kernel (degrees 1..4): four wavefronts per element, RH = ceil(N / 64) rows of the
-// augmented system [A_K | B_K | r_K] per lane, the columns split between the waves: wave w
-// holds the A_K columns of field w and every fourth block of the B_K / r_K columns; the
-// elimination is gj_eliminate. (Degree 5, N = 84, needs two rows per lane; at that size the
-// register arrays spill and the LDS-resident kernel below is faster.)
+template <int P>
+struct EulerShape {
+    static constexpr int N = 4 * n_modes(P);
+    static constexpr int RH = (N + 63) / 64;   // rows per lane
+    static constexpr int WPF = RH;             // waves per field
+    static constexpr int NW = 4 * WPF;         // waves per element
+};
+
+// The register budget aims at four waves per SIMD (128 VGPRs); at degree 5 that spills a few
+// values, which measures faster than two waves per SIMD without spills.
 template <int P, int PF, bool DBG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_condense_euler(CondArgs a) {
+__global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_condense_euler(CondArgs a) {
     constexpr int NP = n_modes(P);
     constexpr int N = 4 * NP;
     constexpr int NPF = PF + 1;
     constexpr int F = 12 * NPF;
     constexpr int FB = 4 * NPF;                // B_K columns of one local face
-    constexpr int NBW = (F + 1 + 3) / 4;       // B_K / r_K columns per wave (zero padded)
+    constexpr int RH = EulerShape<P>::RH;
+    constexpr int WPF = EulerShape<P>::WPF;
+    constexpr int NW = EulerShape<P>::NW;
+    constexpr int NTH = 64 * NW;
+    constexpr int NPW = (NP + WPF - 1) / WPF;  // A_K columns per wave
+    constexpr int NBW = (F + 1 + NW - 1) / NW; // B_K / r_K columns per wave (zero padded)
     constexpr int Q = n_vol_q(P);
-    constexpr int RH = (N + 63) / 64;          // rows per lane
 
     __shared__ ElemShared<P, PF> sh;
+    __shared__ FaceTables<P, PF> ft;
     __shared__ double sX[(F + 1) * N];
     __shared__ double sFm[2][64 * RH];
     __shared__ double sPVk[N];
@@ -335,37 +372,56 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
     if (tid == 0) sBad = 0;
-    point_data<P, PF>(a, E, sh, tid, 256);
+    point_data<P, PF>(a, E, sh, tid, NTH);
+    // reference tables staged in the (not yet used) sX area: basis gradients [r][q][i] and the
+    // element's basis at its face points [lf][g][i]
+    constexpr int QF = PF + 2;
+    static_assert(2 * Q * NP + 3 * QF * NP <= (F + 1) * N, "table staging fits in sX");
+    double* sVg = sX;
+    double* sFp = sX + 2 * Q * NP;
+    for (int t = tid; t < 2 * Q * NP; t += NTH) sVg[t] = a.vgrad[t];
+    for (int t = tid; t < 3 * QF * NP; t += NTH) {
+        const int lf = t / (QF * NP), g = (t / NP) % QF, i = t % NP;
+        const int nq = E->pe[lf] + 2;
+        sFp[t] = g < nq ? a.fphi[face_phi_index(NP, lf, E->orient[lf], nq, g, i)] : 0.0;
+    }
+    face_tables<P, PF>(a, E, sh, sFp, ft, tid, NTH);
+    __syncthreads();
     const auto& sK = sh.sK;
     const auto& sF = sh.sF;
     const auto& sJA = sh.sJA;
     const auto& sJB = sh.sJB;
     const auto& sFH = sh.sFH;
+    const int fld = wave / WPF, part = wave % WPF;
 
-    double mA[RH][NP], mB[RH][NBW];
+    double mA[RH][NPW], mB[RH][NBW];
 #pragma unroll
     for (int h = 0; h < RH; ++h) {
         const int row = h * 64 + lane;
         const int rr = row < N ? row : N - 1;
         const int fa = rr / NP, ii = rr % NP;
-        // ---- A_K columns of field b = wave: volume and face terms (eq. hdg_ls2 linearised)
+        // ---- A_K columns (field fld, modes part NPW + jj): volume and face terms (eq. hdg_ls2
+        // linearised); columns past Np are padding and stay zero
 #pragma unroll
-        for (int j = 0; j < NP; ++j) mA[h][j] = 0.0;
+        for (int j = 0; j < NPW; ++j) mA[h][j] = 0.0;
         {
-            const int b = wave;
+            const int b = fld, j0 = part * NPW;
             for (int q = 0; q < Q; ++q) {
-                const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
+                const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
                 const double s = -(g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]);
 #pragma unroll
-                for (int j = 0; j < NP; ++j) mA[h][j] += s * a.vphi[q * NP + j];
+                for (int j = 0; j < NPW; ++j)
+                    if (j0 + j < NP) mA[h][j] += s * a.vphi[q * NP + j0 + j];
             }
 #pragma unroll
             for (int lf = 0; lf < 3; ++lf) {
-                const int nq = E->pe[lf] + 2, o = E->orient[lf];
+                const int nq = E->pe[lf] + 2;
+                const double* fp = sFp + lf * QF * NP;
                 for (int g = 0; g < nq; ++g) {
-                    const double t = a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJA[lf][g][fa * 4 + b];
+                    const double t = fp[g * NP + ii] * sJA[lf][g][fa * 4 + b];
 #pragma unroll
-                    for (int j = 0; j < NP; ++j) mA[h][j] += t * a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
+                    for (int j = 0; j < NPW; ++j)
+                        if (j0 + j < NP) mA[h][j] += t * fp[g * NP + j0 + j];
                 }
             }
         }
@@ -378,27 +434,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 const int lf = cb / FB, b = (cb / NPF) % 4, k = cb % NPF;
                 const int pe = E->pe[lf];
                 if (E->face[lf] >= 0 && k <= pe) {
-                    const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
-                    for (int g = 0; g < nq; ++g)
-                        v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJB[lf][g][fa * 4 + b] *
-                             a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
+                    const double* fp = sFp + lf * QF * NP;
+                    for (int g = 0; g < pe + 2; ++g) v += fp[g * NP + ii] * sJB[lf][g][fa * 4 + b] * ft.ps[lf][g][k];
                 }
             } else if (cb == F) {
                 for (int q = 0; q < Q; ++q) {
-                    const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
+                    const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
                     v += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
                 }
 #pragma unroll
                 for (int l2 = 0; l2 < 3; ++l2) {
-                    const int nq = E->pe[l2] + 2, o = E->orient[l2];
-                    for (int g = 0; g < nq; ++g) v -= a.fphi[face_phi_index(NP, l2, o, nq, g, ii)] * sFH[l2][g][fa];
+                    const double* fp = sFp + l2 * QF * NP;
+                    for (int g = 0; g < E->pe[l2] + 2; ++g) v -= fp[g * NP + ii] * sFH[l2][g][fa];
                 }
             }
             mB[h][i] = v;
         }
         if (DBG && row < N) {
 #pragma unroll
-            for (int j = 0; j < NP; ++j) a.debug[(int64_t)(wave * NP + j) * N + row] = mA[h][j];
+            for (int j = 0; j < NPW; ++j)
+                if (part * NPW + j < NP) a.debug[(int64_t)(fld * NP + part * NPW + j) * N + row] = mA[h][j];
 #pragma unroll
             for (int i = 0; i < NBW; ++i) {
                 const int cb = wave * NBW + i;
@@ -408,13 +463,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     }
     if (DBG) {
         __syncthreads();
-        schur_rows<P, PF, DBG>(a, E, sh, sX, tid, 256);
+        schur_rows<P, PF, DBG>(a, E, sh, ft, sX, tid, NTH);
         return;
     }
 
     // ---- Gauss-Jordan elimination with partial pivoting
     int mykk[RH];
-    gj_eliminate<NP, NBW, RH>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
+    gj_eliminate<NP, NBW, RH, WPF>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
 
     // ---- X_K = A_K^-1 B_K and y_K = A_K^-1 r_K: row kk of the solution sits in the row
     // whose pivot was taken at step kk
@@ -445,144 +500,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
         a.flag[0] = 1;
     }
-    schur_rows<P, PF, DBG>(a, E, sh, sX, tid, 256);
-}
-
-// Variant for large local blocks (degree 4 and 5: N = 60 or 84 rows, more than one
-// wavefront holds in registers): 256 threads per element, the augmented system
-// [A_K | B_K | r_K] resident in LDS (column-major), assembled entry by entry and eliminated
-// by Gauss-Jordan with partial pivoting (one wave searches the pivot, all threads update).
-template <int P, int PF, bool DBG>
-__global__ __launch_bounds__(256) void k_condense_euler_lds(CondArgs a) {
-    constexpr int NP = n_modes(P);
-    constexpr int N = 4 * NP;
-    constexpr int NPF = PF + 1;
-    constexpr int F = 12 * NPF;
-    constexpr int NC = N + F + 1;
-    constexpr int Q = n_vol_q(P);
-    constexpr int LDM = N + 1;                       // odd leading dimension
-    constexpr bool REUSE = (F + 1) * N <= N * LDM;   // X_K overwrites the dead A_K columns
-    constexpr int NTH = 256;
-
-    __shared__ ElemShared<P, PF> sh;
-    __shared__ double sM[NC * LDM];
-    __shared__ double sXsep[REUSE ? 1 : (F + 1) * N];
-    __shared__ double fmul[N];
-    __shared__ double pvk[N];
-    __shared__ int perm[N];
-    __shared__ int used[N];
-    __shared__ int piv_s;
-
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int slot = a.start + blockIdx.x;
-    if (DBG && slot != a.debug_slot) return;
-    const ElemInfo* E = a.einfo + slot;
-    const int e = E->elem;
-    point_data<P, PF>(a, E, sh, tid, NTH);
-    for (int r = tid; r < N; r += NTH) used[r] = 0;
-    __syncthreads();
-    const auto& sK = sh.sK;
-    const auto& sF = sh.sF;
-    const auto& sJA = sh.sJA;
-    const auto& sJB = sh.sJB;
-    const auto& sFH = sh.sFH;
-
-    // ---- assembly, one entry per thread iteration (consecutive threads: consecutive rows)
-    for (int t = tid; t < NC * N; t += NTH) {
-        const int c = t / N, r = t % N;
-        const int fa = r / NP, ii = r % NP;
-        double v = 0.0;
-        if (c < N) {
-            const int b = c / NP, j = c % NP;
-            for (int q = 0; q < Q; ++q) {
-                const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
-                v -= (g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]) * a.vphi[q * NP + j];
-            }
-            for (int lf = 0; lf < 3; ++lf) {
-                const int nq = E->pe[lf] + 2, o = E->orient[lf];
-                for (int g = 0; g < nq; ++g)
-                    v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJA[lf][g][fa * 4 + b] *
-                         a.fphi[face_phi_index(NP, lf, o, nq, g, j)];
-            }
-        } else if (c < N + F) {
-            const int cf = c - N, lf = cf / (4 * NPF), b = (cf / NPF) % 4, k = cf % NPF;
-            const int pe = E->pe[lf];
-            if (E->face[lf] >= 0 && k <= pe) {
-                const int nq = pe + 2, o = E->orient[lf], rule = nq - kMinFaceQ;
-                for (int g = 0; g < nq; ++g)
-                    v += a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sJB[lf][g][fa * 4 + b] *
-                         a.leg[(rule * kMaxFaceQ + g) * (kMaxDegree + 1) + k];
-            }
-        } else {
-            for (int q = 0; q < Q; ++q) {
-                const double g0 = a.vgrad[q * NP + ii], g1 = a.vgrad[(Q + q) * NP + ii];
-                v += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
-            }
-            for (int lf = 0; lf < 3; ++lf) {
-                const int nq = E->pe[lf] + 2, o = E->orient[lf];
-                for (int g = 0; g < nq; ++g) v -= a.fphi[face_phi_index(NP, lf, o, nq, g, ii)] * sFH[lf][g][fa];
-            }
-        }
-        sM[c * LDM + r] = v;
-        if (DBG) a.debug[(int64_t)c * N + r] = v;
-    }
-    __syncthreads();
-
-    double* sX = REUSE ? sM : sXsep;
-    if (!DBG) {
-        // ---- Gauss-Jordan with partial pivoting (first largest |a| in row order)
-        for (int k = 0; k < N; ++k) {
-            if (wave == 0) {
-                double best = -1.0;
-                int idx = N;
-                for (int r = lane; r < N; r += 64) {
-                    const double v = used[r] ? -1.0 : fabs(sM[k * LDM + r]);
-                    if (v > best) {
-                        best = v;
-                        idx = r;
-                    }
-                }
-                wave_argmax(best, idx);
-                if (lane == 0) {
-                    piv_s = idx;
-                    used[idx] = 1;
-                    perm[k] = idx;
-                    pvk[k] = sM[k * LDM + idx];
-                }
-            }
-            __syncthreads();
-            const int pv_r = piv_s;
-            const double pv = pvk[k];
-            for (int r = tid; r < N; r += NTH) fmul[r] = (r == pv_r) ? 0.0 : sM[k * LDM + r] / pv;
-            __syncthreads();
-            const int ncols = NC - k - 1;
-            for (int t = tid; t < ncols * N; t += NTH) {
-                const int c = k + 1 + t / N, r = t % N;
-                if (r != pv_r) sM[c * LDM + r] -= fmul[r] * sM[c * LDM + pv_r];
-            }
-            __syncthreads();
-        }
-        // ---- X_K, y_K (row k of the solution sits in row perm[k], scaled by its pivot)
-        const int bslot = slot - a.start;
-        double* st = a.store + (int64_t)bslot * ((F + 1) * N);
-        bool bad = false, singular = false;
-        for (int t = tid; t < (F + 1) * N; t += NTH) {
-            // sX (inside the dead A_K columns when REUSE) and the B/r columns read here are disjoint
-            const int c = t / N, k = t % N;
-            const double pv = pvk[k];
-            const double x = sM[(N + c) * LDM + perm[k]] / pv;
-            singular |= !(fabs(pv) > 0.0);
-            bad |= !isfinite(x);
-            st[c * N + k] = x;
-            sX[c * N + k] = x;
-        }
-        if (bad || singular) {
-            a.status[e] = singular ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
-            a.flag[0] = 1;
-        }
-        __syncthreads();
-    }
-    schur_rows<P, PF, DBG>(a, E, sh, sX, tid, NTH);
+    schur_rows<P, PF, DBG>(a, E, sh, ft, sX, tid, NTH);
 }
 
 // Sum the two diagonal contributions of every face in a fixed order and the two halves
@@ -638,8 +556,7 @@ __global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start
         }
 }
 
-// Degrees up to 4 take the register kernel (four wavefronts per element, columns split);
-// degree 5 takes the LDS-resident kernel.
+// One launch per (degree, face-degree) bucket; four waves per element (eight at degree 5).
 template <int P, int PF>
 static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, hipStream_t s) {
     a.vphi = p.d_tab + p.tix.vol_phi[P];
@@ -647,17 +564,11 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.vw = p.d_tab + p.tix.vol_w[P];
     a.fphi = p.d_tab + p.tix.face_phi[P];
     a.start = bk.start;
-    if constexpr (P <= 4) {
-        if (dbg)
-            hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(256), 0, s, a);
-    } else {
-        if (dbg)
-            hipLaunchKernelGGL((k_condense_euler_lds<P, PF, true>), dim3(bk.count), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_condense_euler_lds<P, PF, false>), dim3(bk.count), dim3(256), 0, s, a);
-    }
+    constexpr int nth = 64 * EulerShape<P>::NW;
+    if (dbg)
+        hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(nth), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(nth), 0, s, a);
     return hipGetLastError();
 }
 

@@ -58,14 +58,20 @@ __device__ __forceinline__ int pivot_row(const double (&v)[RH], const bool (&use
     return 0;
 }
 
-// Gauss-Jordan elimination over a workgroup of four waves; RH row halves per lane (rows
-// lane and 64 + lane), N = 4 Np <= 64 RH rows. mykk[h] receives the step at which row
-// h * 64 + lane was the pivot row.
-template <int NP, int NBW, int RH>
-__device__ __forceinline__ void gj_eliminate(double (&mA)[RH][NP], double (&mB)[RH][NBW], int wave, int lane,
-                                             double (*sFm)[64 * RH], int* sPiv, double* sPVk, int (&mykk)[RH]) {
+// Gauss-Jordan elimination over a workgroup of 4 WPF waves; RH row halves per lane (rows
+// lane and 64 + lane), N = 4 Np <= 64 RH rows. Wave w holds the A columns
+// (w / WPF) Np + (w % WPF) NPW + jj, jj < NPW (NPW = ceil(Np / WPF); columns past Np are
+// padding), in mA, and NBW right-hand-side columns in mB. mykk[h] receives the step at
+// which row h * 64 + lane was the pivot row.
+template <int NP, int NBW, int RH, int WPF>
+__device__ __forceinline__ void gj_eliminate(double (&mA)[RH][(NP + WPF - 1) / WPF], double (&mB)[RH][NBW],
+                                             int wave, int lane, double (*sFm)[64 * RH], int* sPiv, double* sPVk,
+                                             int (&mykk)[RH]) {
     constexpr int N = 4 * NP;
+    constexpr int NPW = (NP + WPF - 1) / WPF;
     static_assert(N <= 64 * RH, "rows per lane");
+    const int part = wave % WPF;
+    const int base = (wave / WPF) * NP + part * NPW;   // global index of this wave's first A column
     bool used[RH];
 #pragma unroll
     for (int h = 0; h < RH; ++h) {
@@ -121,22 +127,21 @@ __device__ __forceinline__ void gj_eliminate(double (&mA)[RH][NP], double (&mB)[
 #pragma unroll
             for (int h = 0; h < RH; ++h) m[h][j] -= f[h] * pr;
         };
-        const int ow = k / NP, jk = k % NP;   // column k = A column jk of wave ow
+        // column k = A column jk of field k / NP, held by wave ow at local index jl
+        const int jk = k % NP, ow = (k / NP) * WPF + jk / NPW, jl = jk % NPW;
         if (k < N && wave == ow) {
-            update(mA, jk);
+            update(mA, jl);
             double ck[RH];
 #pragma unroll
-            for (int h = 0; h < RH; ++h) ck[h] = mA[h][jk];
+            for (int h = 0; h < RH; ++h) ck[h] = mA[h][jl];
             publish(k, ck);
 #pragma unroll
-            for (int j = jk + 1; j < NP; ++j) update(mA, j);
-        } else if (wave > (k - 1) / NP) {
-            // every A column of this wave has index >= k
+            for (int j = jl + 1; j < NPW; ++j)
+                if (part * NPW + j < NP) update(mA, j);
+        } else {
 #pragma unroll
-            for (int j = 0; j < NP; ++j) update(mA, j);
-        } else if (wave == (k - 1) / NP) {
-#pragma unroll
-            for (int j = (k - 1) % NP + 1; j < NP; ++j) update(mA, j);
+            for (int j = 0; j < NPW; ++j)
+                if (base + j >= k && part * NPW + j < NP) update(mA, j);
         }
 #pragma unroll
         for (int i = 0; i < NBW; ++i) update(mB, i);

@@ -957,7 +957,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         mB[0][i] = cb <= F ? Zh[(int64_t)(N + cb) * NR + rr] : 0.0;
     }
     int mk[1];
-    gj_eliminate<NP, NBW, 1>(mA, mB, wave, lane, sFm, sPiv, sPVk, mk);
+    gj_eliminate<NP, NBW, 1, 1>(mA, mB, wave, lane, sFm, sPiv, sPVk, mk);
     const int mykk = mk[0];
     double* st = a.store + (int64_t)(slot - a.bucket_start) * ((F + 1) * NALL);
     if (lane < N) {
