@@ -55,6 +55,21 @@ def cpu_baseline(ng: int = 16):
             "seconds": dt}
 
 
+def measured_traffic(kernel_source: str, summary: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(line.split(None, 1) for line in open(os.path.join(ROOT, summary))
+                      if line.strip() and not line.startswith("#"))
+        cur = hashlib.sha256(open(os.path.join(ROOT, kernel_source), "rb").read()).hexdigest()
+        if fields.get("skeleton_hip_sha256", "").strip() != cur:
+            return None
+        return float(fields["traffic_per_launch_MB"]) * 1e6
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def condensation_work(case):
     """Algorithmic flops and HBM bytes of assembling and condensing every element once.
 
@@ -257,7 +272,11 @@ def main():
     achieved = kb / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     out["roofline"] = {"kernel": "k_spmv_dots (preconditioned skeleton SpMV fused with the first Gram-Schmidt dots)",
                        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": (measured_traffic("paper_1308_3995_amd/csrc/skeleton.hip",
+                                                    "profiles/k_spmv_dots_c2_euler_p3_mixed_hbm_traffic.txt")
+                                   if main_mode == "mixed" else None),
+                       "traffic_unit": "bytes/launch",
                        "launches": kl, "avg_launch_us": kms / max(1, kl) * 1e3,
                        "bytes_per_launch": kb / max(1, kl)}
     if args.condense_configs:
