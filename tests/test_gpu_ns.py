@@ -138,3 +138,81 @@ def test_c4_recipe_reduced_size_sampled(hdg):
     E = plan.rhs.cpu().numpy()
     x = dlam.cpu().numpy()
     assert relres <= 1e-10 and np.linalg.norm(E - K @ x) / np.linalg.norm(E) <= 2e-10
+
+
+def test_c4_full_size_sampled(hdg):
+    """The 256x256 Navier-Stokes workload (p in {2, 3, 4}, 131072 elements) in the launch
+    configuration the benchmark times: sampled local solutions (every degree, and elements on
+    the far field) against the oracle, and sampled skeleton rows and right-hand side entries
+    against the exact partial assembly from the two elements that share each face."""
+    import torch
+    case = hi.config_case("c4")
+    _say("c4 full size")
+    plan = hdg.HDGPlan.from_case(case)
+    w, q, lam = _state(plan, case)
+    plan.hdg_assemble_condense(w, lam, q=q)
+    torch.cuda.synchronize()
+    mesh = O.Mesh(case, O.make_physics(case))
+    st = O.State(mesh, case.W, case.lam, case.Q)
+    rng = np.random.default_rng(4)
+    fid = {tuple(v): i for i, v in enumerate(plan.face_vertices)}
+    owners = {}
+    n_bnd = np.zeros(case.n_elements, dtype=np.int64)
+    for e in range(case.n_elements):
+        t = case.tri[e]
+        for lf in range(3):
+            key = tuple(sorted((int(t[lf]), int(t[(lf + 1) % 3]))))
+            if key in fid:
+                owners.setdefault(fid[key], []).append(e)
+            else:
+                n_bnd[e] += 1
+    corner = np.flatnonzero(n_bnd == 2)
+    edge = np.flatnonzero(n_bnd == 1)
+    boundary = ([int(corner[0])] if corner.size else []) + [int(e) for e in rng.choice(edge, 2, replace=False)]
+    sample = boundary + [int(e) for p in (2, 3, 4) for e in rng.choice(np.flatnonzero(case.degree == p), 2,
+                                                                         replace=False)]
+    cache = {}
+
+    def cond(e):
+        if e not in cache:
+            ob = O.element_blocks(st, e)
+            cache[e] = (ob, O.condense(ob))
+        return cache[e]
+
+    for e in sample:
+        ob, oc = cond(e)
+        X, y = plan.debug_local_solution(e)
+        assert rel(X, oc.X) < TOL, (e, rel(X, oc.X))
+        assert rel(y, oc.y) < tol_resid(ob.A), (e, rel(y, oc.y))
+    # skeleton rows of sampled faces: only the face's two elements contribute
+    rp, col, voff = plan.pattern()
+    fo = plan.face_offset
+    E_gpu = plan.rhs
+    for f in rng.choice(len(plan.face_degree), 6, replace=False):
+        f = int(f)
+        f0, f1 = int(fo[f]), int(fo[f + 1])
+        ref_rows = {}
+        ref_E = np.zeros(f1 - f0)
+        for e in owners[f]:
+            ob, oc = cond(e)
+            d = O.elem_dofs(mesh, ob)
+            loc = np.flatnonzero((d >= f0) & (d < f1))
+            for i in loc:
+                for jj, gd in enumerate(d):
+                    ref_rows[(int(d[i]) - f0, int(gd))] = ref_rows.get((int(d[i]) - f0, int(gd)), 0.0) + oc.S[i, jj]
+                ref_E[int(d[i]) - f0] += oc.g[i]
+        got = {}
+        for k in range(rp[f], rp[f + 1]):
+            g = int(col[k])
+            g0, g1 = int(fo[g]), int(fo[g + 1])
+            blk = plan.bsr[int(voff[k]): int(voff[k]) + (f1 - f0) * (g1 - g0)].cpu().numpy()
+            blk = blk.reshape(g1 - g0, f1 - f0).T
+            for i in range(f1 - f0):
+                for j in range(g1 - g0):
+                    got[(i, g0 + j)] = blk[i, j]
+        keys = sorted(set(ref_rows) | set(got))
+        a = np.array([got.get(k, 0.0) for k in keys])
+        b = np.array([ref_rows.get(k, 0.0) for k in keys])
+        assert rel(a, b) < TOL, (f, rel(a, b))
+        e_got = E_gpu[f0:f1].cpu().numpy()
+        assert rel(e_got, ref_E) < 1e-12 + max(np.linalg.cond(cond(e)[0].A) for e in owners[f]) * RESID_ROUNDING
