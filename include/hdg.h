@@ -137,7 +137,13 @@ hdg_status hdg_plan_pattern(const hdg_plan* plan, int64_t* row_ptr_host, int32_t
  * per element 0, or HDG_ERR_SINGULAR_LOCAL / HDG_ERR_NONFINITE. res_norm_host
  * (optional): if non-NULL the call synchronises and returns ||E||_2. The call itself
  * returns HDG_ERR_SINGULAR_LOCAL or HDG_ERR_NONFINITE only when res_norm_host or
- * elem_status_dev asks it to look (that needs a synchronisation). */
+ * elem_status_dev asks it to look (that needs a synchronisation).
+ * Batching: one launch per (element degree, face degree) bucket. The first call on a plan
+ * times the two register-budget variants of every bucket's kernel, keeps the faster one and
+ * synchronises the stream once (the variants compute identical values). Later calls
+ * capture the whole launch sequence in a hipGraph once per set of buffer pointers and
+ * replay it; they are asynchronous unless res_norm_host or elem_status_dev is given.
+ * Call once outside any stream capture of the caller's own before capturing it. */
 hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const double* q_dev,
                                  const double* lam_dev, double* bsr_values_dev, double* rhs_dev,
                                  void* local_store_dev, void* workspace_dev,

@@ -5,6 +5,8 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "hdg_internal.h"
 
 namespace hdg {
@@ -206,21 +208,65 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
     int32_t* status = elem_status_dev ? elem_status_dev : (int32_t*)(ws + p.ws_status);
     int32_t* flag = (int32_t*)(ws + p.ws_status) + p.ne;
     CHECK_HIP(hipSetDevice(p.device));
-    CHECK_HIP(hipMemsetAsync(status, 0, (size_t)p.ne * 4, stream));
-    CHECK_HIP(hipMemsetAsync(flag, 0, 4, stream));
-    hipError_t e = p.ns ? launch_ns(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
-                                    (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag,
-                                    (double*)(ws + p.ws_ns), p.ns_zcap, -1, stream)
-                        : launch_condense(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
-                                          (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag,
-                                          nullptr, -1, stream);
+    // the whole sequence: clear the status words, condense every bucket, sum the face diagonals
+    auto enqueue = [&](hipStream_t q) -> hipError_t {
+        hipError_t e = launch_clear_status(p, status, flag, q);
+        if (e != hipSuccess) return e;
+        e = p.ns ? launch_ns(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
+                             (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag,
+                             (double*)(ws + p.ws_ns), p.ns_zcap, -1, q)
+                 : launch_condense(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
+                                   (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag, nullptr, -1,
+                                   q);
+        if (e != hipSuccess) return e;
+        return launch_diag_sum(p, (double*)(ws + p.ws_diag_part), (double*)(ws + p.ws_g_part), bsr_values_dev,
+                               rhs_dev, q);
+    };
+    hipError_t e = hipSuccess;
+    bool launched = false;
+    if (p.tuned && p.use_graphs) {
+        // after the first call (which picks the kernel variants) the sequence is captured once
+        // per set of buffers and replayed
+        uint64_t key = 1469598103934665603ull;
+        auto mix = [&](const void* v) { key = (key ^ (uint64_t)(uintptr_t)v) * 1099511628211ull; };
+        for (const void* v : {(const void*)w_dev, (const void*)q_dev, (const void*)lam_dev, (const void*)bsr_values_dev,
+                              (const void*)rhs_dev, (const void*)local_store_dev, (const void*)ws, (const void*)status})
+            mix(v);
+        if (!p.cond_exec || p.cond_key != key) {
+            if (p.cond_exec) (void)hipGraphExecDestroy(p.cond_exec);
+            if (p.cond_graph) (void)hipGraphDestroy(p.cond_graph);
+            p.cond_exec = nullptr;
+            p.cond_graph = nullptr;
+            std::lock_guard<std::mutex> lock(device_mutex());
+            if (!p.capture_stream) CHECK_HIP(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
+            hipError_t ce = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeRelaxed);
+            if (ce == hipSuccess) {
+                hipError_t le = enqueue(p.capture_stream);
+                ce = hipStreamEndCapture(p.capture_stream, &p.cond_graph);
+                if (ce == hipSuccess) ce = le;
+            }
+            if (ce == hipSuccess) ce = hipGraphInstantiate(&p.cond_exec, p.cond_graph, nullptr, nullptr, 0);
+            if (ce != hipSuccess) {
+                (void)hipGetLastError();
+                if (p.cond_exec) (void)hipGraphExecDestroy(p.cond_exec);
+                if (p.cond_graph) (void)hipGraphDestroy(p.cond_graph);
+                p.cond_exec = nullptr;
+                p.cond_graph = nullptr;
+            } else {
+                p.cond_key = key;
+            }
+        }
+        if (p.cond_exec) {
+            e = hipGraphLaunch(p.cond_exec, stream);
+            launched = true;
+        }
+    }
+    if (!launched) e = enqueue(stream);
     if (e == hipErrorInvalidValue) {
         set_error("hdg_assemble_condense: element degree or face degree outside the built kernels (1..5)");
         return HDG_ERR_INVALID_ARG;
     }
     CHECK_HIP(e);
-    CHECK_HIP(launch_diag_sum(p, (double*)(ws + p.ws_diag_part), (double*)(ws + p.ws_g_part), bsr_values_dev, rhs_dev,
-                              stream));
     if (res_norm_host || elem_status_dev) {
         hdg_status st = check_status(p, status, flag, stream);
         if (st != HDG_OK) return st;

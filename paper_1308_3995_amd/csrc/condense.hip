@@ -13,6 +13,9 @@
 // blocks of S_K have one owner element and are stored straight into the skeleton
 // matrix; the diagonal blocks and g_K go to per-face slots summed by k_diag_sum in a
 // fixed order, so the assembly is deterministic and atomic-free.
+#include <algorithm>
+#include <vector>
+
 #include "gj.h"
 #include "hdg_internal.h"
 
@@ -340,10 +343,10 @@ struct EulerShape {
     static constexpr int NW = 4 * WPF;         // waves per element
 };
 
-// The register budget aims at four waves per SIMD (128 VGPRs); at degree 5 that spills a few
-// values, which measures faster than two waves per SIMD without spills.
-template <int P, int PF, bool DBG>
-__global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// MINW is the register budget's target in waves per SIMD (4: 128 VGPRs, 2: 256); both are
+// built and the faster one per bucket is picked by timing on the plan's first call.
+template <int P, int PF, bool DBG, int MINW>
+__global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_condense_euler(CondArgs a) {
     constexpr int NP = n_modes(P);
     constexpr int N = 4 * NP;
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start
 
 // One launch per (degree, face-degree) bucket; four waves per element (eight at degree 5).
 template <int P, int PF>
-static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, hipStream_t s) {
+static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, int variant, hipStream_t s) {
     a.vphi = p.d_tab + p.tix.vol_phi[P];
     a.vgrad = p.d_tab + p.tix.vol_grad[P];
     a.vw = p.d_tab + p.tix.vol_w[P];
@@ -566,9 +569,11 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.start = bk.start;
     constexpr int nth = 64 * EulerShape<P>::NW;
     if (dbg)
-        hipLaunchKernelGGL((k_condense_euler<P, PF, true>), dim3(bk.count), dim3(nth), 0, s, a);
+        hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4>), dim3(bk.count), dim3(nth), 0, s, a);
+    else if (variant == 1)
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2>), dim3(bk.count), dim3(nth), 0, s, a);
     else
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false>), dim3(bk.count), dim3(nth), 0, s, a);
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4>), dim3(bk.count), dim3(nth), 0, s, a);
     return hipGetLastError();
 }
 
@@ -579,9 +584,10 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     X(4, 4) X(4, 5)                                             \
     X(5, 5)
 
-static hipError_t dispatch_condense(const Plan& p, const Bucket& bk, const CondArgs& a, bool dbg, hipStream_t s) {
+static hipError_t dispatch_condense(const Plan& p, const Bucket& bk, const CondArgs& a, bool dbg, int variant,
+                                    hipStream_t s) {
 #define HDG_CASE(PP, FF) \
-    if (bk.p == PP && bk.pf == FF) return launch_bucket<PP, FF>(p, bk, a, dbg, s);
+    if (bk.p == PP && bk.pf == FF) return launch_bucket<PP, FF>(p, bk, a, dbg, variant, s);
     HDG_BUCKETS(HDG_CASE)
 #undef HDG_CASE
     return hipErrorInvalidValue;
@@ -589,7 +595,57 @@ static hipError_t dispatch_condense(const Plan& p, const Bucket& bk, const CondA
 
 static bool bucket_supported(const Bucket& bk) { return bk.p >= 1 && bk.p <= 5 && bk.pf >= bk.p && bk.pf <= 5; }
 
-hipError_t launch_condense(const Plan& p, const double* w, const double* q, const double* lam, double* bsr,
+// Zero the per-element status words and the failure flag (a kernel, so that the sequence can be
+// captured in a graph).
+__global__ void k_clear_status(int n, int32_t* status, int32_t* flag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) status[k] = 0;
+    if (k == 0) flag[0] = 0;
+}
+
+hipError_t launch_clear_status(const Plan& p, int32_t* status, int32_t* flag, hipStream_t s) {
+    const int n = std::max(1, p.ne);
+    hipLaunchKernelGGL(k_clear_status, dim3((n + 255) / 256), dim3(256), 0, s, p.ne, status, flag);
+    return hipGetLastError();
+}
+
+// Times both register-budget variants of every bucket (two interleaved rounds, the faster of
+// each variant's two launches counts) and keeps the faster. Both variants compute the same
+// values, so the outputs of the last launch are the condensed system. Synchronises once.
+template <typename LaunchFn>
+static hipError_t tune_buckets(Plan& p, hipStream_t s, LaunchFn launch_variant) {
+    const int nb = (int)p.buckets.size();
+    std::vector<hipEvent_t> ev((size_t)nb * 8, nullptr);
+    hipError_t err = hipSuccess;
+    for (auto& e : ev)
+        if (err == hipSuccess) err = hipEventCreate(&e);
+    for (int b = 0; b < nb && err == hipSuccess; ++b)
+        for (int round = 0; round < 2 && err == hipSuccess; ++round)
+            for (int v = 0; v < 2 && err == hipSuccess; ++v) {
+                hipEvent_t* e = &ev[(size_t)b * 8 + round * 4 + v * 2];
+                err = hipEventRecord(e[0], s);
+                if (err == hipSuccess) err = launch_variant(b, v);
+                if (err == hipSuccess) err = hipEventRecord(e[1], s);
+            }
+    if (err == hipSuccess && nb > 0) err = hipEventSynchronize(ev.back());
+    p.variant.assign(nb, 0);
+    for (int b = 0; b < nb && err == hipSuccess; ++b) {
+        float t[2] = {1e30f, 1e30f};
+        for (int round = 0; round < 2; ++round)
+            for (int v = 0; v < 2; ++v) {
+                float ms = 0.f;
+                const hipEvent_t* e = &ev[(size_t)b * 8 + round * 4 + v * 2];
+                if (hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) t[v] = std::min(t[v], ms);
+            }
+        p.variant[b] = t[1] < t[0] ? 1 : 0;
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (err == hipSuccess) p.tuned = true;
+    return err;
+}
+
+hipError_t launch_condense(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
                            double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag,
                            double* debug, int debug_slot, hipStream_t s) {
     (void)q;
@@ -614,11 +670,21 @@ hipError_t launch_condense(const Plan& p, const double* w, const double* q, cons
     for (int i = 0; i < 4; ++i) a.winf[i] = p.winf[i];
     a.alpha = p.alpha;
     a.gamma = p.prm.gamma;
-    for (const Bucket& bk : p.buckets) {
+    for (const Bucket& bk : p.buckets)
         if (!bucket_supported(bk)) return hipErrorInvalidValue;
+    if (!debug && !p.tuned) {
+        return tune_buckets(p, s, [&](int b, int v) {
+            CondArgs ab = a;
+            ab.store = store + p.buckets[b].store_off;
+            return dispatch_condense(p, p.buckets[b], ab, false, v, s);
+        });
+    }
+    for (size_t b = 0; b < p.buckets.size(); ++b) {
+        const Bucket& bk = p.buckets[b];
         if (debug && !(debug_slot >= bk.start && debug_slot < bk.start + bk.count)) continue;
         a.store = store + bk.store_off;
-        hipError_t e = dispatch_condense(p, bk, a, debug != nullptr, s);
+        const int v = debug || b >= p.variant.size() ? 0 : p.variant[b];
+        hipError_t e = dispatch_condense(p, bk, a, debug != nullptr, v, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -134,6 +134,13 @@ struct Plan {
     hipGraph_t cycle_graph[2] = {nullptr, nullptr};
     uint64_t cycle_key[2] = {0, 0};
     bool use_graphs = true;
+    // condensation: register-budget variant per bucket (chosen by timing on the first call)
+    // and the captured launch sequence replayed on later calls
+    std::vector<int> variant;             // per bucket, -1 until tuned
+    bool tuned = false;
+    hipGraphExec_t cond_exec = nullptr;
+    hipGraph_t cond_graph = nullptr;
+    uint64_t cond_key = 0;
 };
 
 // Workspace carving for the skeleton solver (offsets in bytes from ws_solver).
@@ -143,14 +150,15 @@ struct SolverLayout {
 SolverLayout solver_layout(const Plan& p, int restart);
 
 // kernel launchers (condense.hip, skeleton.hip)
-hipError_t launch_condense(const Plan& p, const double* w, const double* q, const double* lam,
+hipError_t launch_condense(Plan& p, const double* w, const double* q, const double* lam,
                            double* bsr, double* diag_part, double* g_part, double* store,
                            int32_t* status, int32_t* flag, double* debug, int debug_slot, hipStream_t s);
+hipError_t launch_clear_status(const Plan& p, int32_t* status, int32_t* flag, hipStream_t s);
 hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double* g_part, double* bsr,
                            double* rhs, hipStream_t s);
 hipError_t launch_back_substitute(const Plan& p, const double* store, const double* dlam, double* dw,
                                   double* dq, hipStream_t s);
-hipError_t launch_ns(const Plan& p, const double* w, const double* q, const double* lam, double* bsr,
+hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
                      double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag, double* zbuf,
                      int64_t zcap_doubles, int only_slot, hipStream_t s);
 int64_t ns_workspace_per_element(int p, int pf);   // Z, L, R of one element (block inspection)

@@ -24,6 +24,9 @@
 //                   scatter.
 // Block inspection (one element) runs k_ns_assemble, which writes Z, L = [A_wq ; C_q] and
 // R = [G_qw | B_q | r_q] as dense matrices.
+#include <algorithm>
+#include <vector>
+
 #include "gj.h"
 #include "hdg_internal.h"
 
@@ -913,8 +916,8 @@ __global__ __launch_bounds__(256) void k_ns_zhat(NsArgs a) {
 // Condensation of the reduced system: Gauss-Jordan on [Ahat | Bhat | rhat] (gj_eliminate),
 // the gradient part of the local solutions X_q = (B_q - G_qw X_w)/|J|, y_q likewise, the
 // local store, S_K = Dhat - Chat X_w, g_K = rhat_lam - Chat y_w and the scatter.
-template <int P, int PF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_ns_condense2(NsArgs a) {
+template <int P, int PF, int MINW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW, 8))) void k_ns_condense2(NsArgs a) {
     using D = NsDims<P, PF>;
     using LY = NsLayout<P, PF>;
     constexpr int NP = D::NP, N = D::N, NQ = D::NQ, NPF = D::NPF, F = D::F, NR = D::NR;
@@ -1041,9 +1044,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
 // ---------------------------------------------------------------------------
 // launch
 // ---------------------------------------------------------------------------
+// variant: 0 or 1 = register budget of k_ns_condense2 (2 or 4 waves per SIMD); -1 = time both
+// on the first chunk (tune[4] receives the events' timings through the caller).
 template <int P, int PF>
 static hipError_t ns_bucket(const Plan& p, const Bucket& bk, NsArgs a, double* zbuf, int64_t zcap_doubles,
-                            bool assemble_only, int only_slot, hipStream_t s) {
+                            bool assemble_only, int only_slot, int variant, hipEvent_t* tune, hipStream_t s) {
     using D = NsDims<P, PF>;
     a.vphi = p.d_tab + p.tix.vol_phi[P];
     a.vgrad = p.d_tab + p.tix.vol_grad[P];
@@ -1064,7 +1069,23 @@ static hipError_t ns_bucket(const Plan& p, const Bucket& bk, NsArgs a, double* z
         a.start = bk.start + c0;
         hipLaunchKernelGGL((k_ns_points<P, PF>), dim3(cnt), dim3(64), 0, s, a);
         hipLaunchKernelGGL((k_ns_zhat<P, PF>), dim3(cnt), dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_ns_condense2<P, PF>), dim3(cnt), dim3(256), 0, s, a);
+        if (variant < 0 && c0 == 0) {
+            // two interleaved rounds of both variants on the first chunk (same outputs)
+            for (int round = 0; round < 2; ++round)
+                for (int v = 0; v < 2; ++v) {
+                    hipEvent_t* e = tune + round * 4 + v * 2;
+                    (void)hipEventRecord(e[0], s);
+                    if (v == 0)
+                        hipLaunchKernelGGL((k_ns_condense2<P, PF, 2>), dim3(cnt), dim3(256), 0, s, a);
+                    else
+                        hipLaunchKernelGGL((k_ns_condense2<P, PF, 4>), dim3(cnt), dim3(256), 0, s, a);
+                    (void)hipEventRecord(e[1], s);
+                }
+        } else if (variant == 1) {
+            hipLaunchKernelGGL((k_ns_condense2<P, PF, 4>), dim3(cnt), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_ns_condense2<P, PF, 2>), dim3(cnt), dim3(256), 0, s, a);
+        }
     }
     return hipGetLastError();
 }
@@ -1083,7 +1104,7 @@ int64_t ns_chunk_per_element(int p, int pf) {
 
 #define HDG_NS_BUCKETS(X) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 2) X(2, 3) X(2, 4) X(3, 3) X(3, 4) X(4, 4)
 
-hipError_t launch_ns(const Plan& p, const double* w, const double* q, const double* lam, double* bsr,
+hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
                      double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag, double* zbuf,
                      int64_t zcap_doubles, int only_slot, hipStream_t s) {
     NsArgs a{};
@@ -1108,17 +1129,44 @@ hipError_t launch_ns(const Plan& p, const double* w, const double* q, const doub
     a.gamma = p.prm.gamma;
     a.mu = p.mu;
     a.prandtl = p.prm.prandtl;
-    for (const Bucket& bk : p.buckets) {
+    const bool tuning = only_slot < 0 && !p.tuned;
+    const int nb = (int)p.buckets.size();
+    std::vector<hipEvent_t> ev(tuning ? (size_t)nb * 8 : 0, nullptr);
+    for (auto& e : ev) {
+        hipError_t ce = hipEventCreate(&e);
+        if (ce != hipSuccess) return ce;
+    }
+    hipError_t err = hipSuccess;
+    for (int b = 0; b < nb && err == hipSuccess; ++b) {
+        const Bucket& bk = p.buckets[b];
         if (only_slot >= 0 && !(only_slot >= bk.start && only_slot < bk.start + bk.count)) continue;
         a.store = store ? store + bk.store_off : nullptr;
+        const int variant = tuning ? -1 : (b < (int)p.variant.size() ? p.variant[b] : 0);
+        hipEvent_t* tune = tuning ? &ev[(size_t)b * 8] : nullptr;
         hipError_t e = hipErrorInvalidValue;
 #define HDG_CASE(PP, FF) \
-        if (bk.p == PP && bk.pf == FF) e = ns_bucket<PP, FF>(p, bk, a, zbuf, zcap_doubles, false, only_slot, s);
+        if (bk.p == PP && bk.pf == FF) e = ns_bucket<PP, FF>(p, bk, a, zbuf, zcap_doubles, false, only_slot, variant, tune, s);
         HDG_NS_BUCKETS(HDG_CASE)
 #undef HDG_CASE
-        if (e != hipSuccess) return e;
+        err = e;
     }
-    return hipSuccess;
+    if (tuning) {
+        if (err == hipSuccess && nb > 0) err = hipStreamSynchronize(s);
+        p.variant.assign(nb, 0);
+        for (int b = 0; b < nb && err == hipSuccess; ++b) {
+            float t[2] = {1e30f, 1e30f};
+            for (int round = 0; round < 2; ++round)
+                for (int v = 0; v < 2; ++v) {
+                    float ms = 0.f;
+                    const hipEvent_t* e = &ev[(size_t)b * 8 + round * 4 + v * 2];
+                    if (hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) t[v] = std::min(t[v], ms);
+                }
+            p.variant[b] = t[1] < t[0] ? 1 : 0;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        if (err == hipSuccess) p.tuned = true;
+    }
+    return err;
 }
 
 }  // namespace hdg

@@ -560,6 +560,10 @@ void free_plan(Plan& P) {
         P.cycle_exec[i] = nullptr;
         P.cycle_graph[i] = nullptr;
     }
+    if (P.cond_exec) (void)hipGraphExecDestroy(P.cond_exec);
+    if (P.cond_graph) (void)hipGraphDestroy(P.cond_graph);
+    P.cond_exec = nullptr;
+    P.cond_graph = nullptr;
     if (P.capture_stream) (void)hipStreamDestroy(P.capture_stream);
     P.capture_stream = nullptr;
     void* ptrs[] = {P.d_einfo, P.d_tab, P.d_bproj, P.d_face_off, P.d_face_deg, P.d_row_ptr, P.d_col,
