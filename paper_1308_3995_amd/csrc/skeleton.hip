@@ -25,7 +25,11 @@
 namespace hdg {
 
 
-static int row_blocks(const Plan& p) { return std::max(1, (p.nf + 3) / 4); }
+// Face rows per wave of the row kernels (a block is four waves).
+constexpr int kRowsPerWave = 2;
+constexpr int kRowsPerBlock = 4 * kRowsPerWave;
+
+static int row_blocks(const Plan& p) { return std::max(1, (p.nf + kRowsPerBlock - 1) / kRowsPerBlock); }
 static int vec_blocks(const Plan& p) {
     const int64_t n = p.face_off.back();
     return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 511) / 512));
@@ -136,7 +140,7 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 // ---------------------------------------------------------------------------
 // Krylov kernels. Per Arnoldi step j (cnt = j + 1 basis vectors):
 //   k_spmv_dots   y = Khat v_j, v_j = scale * src written on the fly (one wave per face
-//                 row, four rows per block), block partials of V^T y
+//                 row at a time, kRowsPerBlock rows per block), block partials of V^T y
 //   k_reduce_h    h = sum of the partials (one block per coefficient), H(:, j) = h
 //   k_update_dots w = y - V h, block partials of V^T w          (CGS, first pass)
 //   k_reduce_h    h2, H(:, j) += h2
@@ -262,28 +266,31 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
     constexpr int cnt = CNT;
     constexpr int kPerWave = kMaxRestart / 4;   // Krylov vectors per wave in the dot phase
     __shared__ double red[4][64];
-    __shared__ double yf[4 * 4 * (kMaxDegree + 1)];
-    __shared__ double xf[4 * 4 * (kMaxDegree + 1)];
+    __shared__ double yf[kRowsPerBlock * 4 * (kMaxDegree + 1)];
+    __shared__ double xf[kRowsPerBlock * 4 * (kMaxDegree + 1)];
     if (a.scal[SC_DONE] != 0.0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int f0 = blockIdx.x * 4;
-    const int f = f0 + wave;
+    const int f0 = blockIdx.x * kRowsPerBlock;
     const double scale = a.scal[SC_SCALE];
     const int j = cnt - 1;
     double* vj = a.V + (int64_t)j * a.n;
-    const int flast = f0 + 4 < a.nf ? f0 + 4 : a.nf;
+    const int flast = f0 + kRowsPerBlock < a.nf ? f0 + kRowsPerBlock : a.nf;
     const int64_t e0 = a.face_off[f0];
     const int ne = (int)(a.face_off[flast] - e0);
-    if (f < a.nf) {
-        double xv;
-        const double out = row_spmv<VT, true>(a, val, src, scale, f, lane, red[wave], xv);
-        const int64_t fo = a.face_off[f];
-        const int s = (int)(a.face_off[f + 1] - fo);
-        if (lane < s) {
-            a.y[fo + lane] = out;
-            vj[fo + lane] = xv;
-            yf[fo - e0 + lane] = out;
-            xf[fo - e0 + lane] = xv;
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const int f = f0 + rr * 4 + wave;
+        if (f < a.nf) {
+            double xv;
+            const double out = row_spmv<VT, true>(a, val, src, scale, f, lane, red[wave], xv);
+            const int64_t fo = a.face_off[f];
+            const int s = (int)(a.face_off[f + 1] - fo);
+            if (lane < s) {
+                a.y[fo + lane] = out;
+                vj[fo + lane] = xv;
+                yf[fo - e0 + lane] = out;
+                xf[fo - e0 + lane] = xv;
+            }
         }
     }
     __syncthreads();
@@ -459,17 +466,20 @@ __global__ __launch_bounds__(kThreads) void k_resid(GmArgs a, const VT* val, con
     __shared__ double sh[8];
     __shared__ double red[4][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int f = blockIdx.x * 4 + wave;
     double nacc = 0.0;
-    if (f < a.nf) {
-        double xv;
-        const double out = row_spmv<VT, IDENT>(a, val, u, 1.0, f, lane, red[wave], xv);
-        const int64_t fo = a.face_off[f];
-        const int s = (int)(a.face_off[f + 1] - fo);
-        if (lane < s) {
-            const double v = r0[fo + lane] - out;
-            r[fo + lane] = v;
-            nacc = v * v;
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const int f = blockIdx.x * kRowsPerBlock + rr * 4 + wave;
+        if (f < a.nf) {
+            double xv;
+            const double out = row_spmv<VT, IDENT>(a, val, u, 1.0, f, lane, red[wave], xv);
+            const int64_t fo = a.face_off[f];
+            const int s = (int)(a.face_off[f + 1] - fo);
+            if (lane < s) {
+                const double v = r0[fo + lane] - out;
+                r[fo + lane] = v;
+                nacc += v * v;
+            }
         }
     }
     const double t = block_sum1(nacc, sh);
