@@ -339,7 +339,8 @@ template <int P>
 struct EulerShape {
     static constexpr int N = 4 * n_modes(P);
     static constexpr int RH = (N + 63) / 64;   // rows per lane
-    static constexpr int WPF = RH;             // waves per field
+    // waves per field (measured: one is best up to degree 3, two at degree 4, four at degree 5)
+    static constexpr int WPF = P <= 3 ? 1 : (P == 4 ? 2 : 4);
     static constexpr int NW = 4 * WPF;         // waves per element
 };
 
@@ -559,7 +560,7 @@ __global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start
         }
 }
 
-// One launch per (degree, face-degree) bucket; four waves per element (eight at degree 5).
+// One launch per (degree, face-degree) bucket; 4, 8 or 16 waves per element (degree <= 3, 4, 5).
 template <int P, int PF>
 static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, int variant, hipStream_t s) {
     a.vphi = p.d_tab + p.tix.vol_phi[P];
