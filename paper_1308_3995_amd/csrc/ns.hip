@@ -916,13 +916,24 @@ __global__ __launch_bounds__(256) void k_ns_zhat(NsArgs a) {
 // Condensation of the reduced system: Gauss-Jordan on [Ahat | Bhat | rhat] (gj_eliminate),
 // the gradient part of the local solutions X_q = (B_q - G_qw X_w)/|J|, y_q likewise, the
 // local store, S_K = Dhat - Chat X_w, g_K = rhat_lam - Chat y_w and the scatter.
+// Waves per field of k_ns_condense2 (two at degree 4, where the state block has 60 rows).
+template <int P>
+struct NsCondShape {
+    static constexpr int WPF = P == 4 ? 2 : 1;
+    static constexpr int NTH = 256 * WPF;
+};
+
 template <int P, int PF, int MINW>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW, 8))) void k_ns_condense2(NsArgs a) {
+__global__ __launch_bounds__(NsCondShape<P>::NTH) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
+void k_ns_condense2(NsArgs a) {
     using D = NsDims<P, PF>;
     using LY = NsLayout<P, PF>;
     constexpr int NP = D::NP, N = D::N, NQ = D::NQ, NPF = D::NPF, F = D::F, NR = D::NR;
-    constexpr int NBW = (F + 1 + 3) / 4;
-    constexpr int NTH = 256;
+    constexpr int WPF = NsCondShape<P>::WPF;
+    constexpr int NTH = NsCondShape<P>::NTH;
+    constexpr int NW = 4 * WPF;
+    constexpr int NPW = (NP + WPF - 1) / WPF;
+    constexpr int NBW = (F + 1 + NW - 1) / NW;
     constexpr int NALL = NQ + N;
     __shared__ double sX[(F + 1) * N];
     __shared__ double sC[F * N];
@@ -951,16 +962,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MINW, 8))) 
         sC[r * N + j] = Zh[(int64_t)j * NR + N + r];
     }
     const int rr = lane < N ? lane : N - 1;
-    double mA[1][NP], mB[1][NBW];
+    const int fld = wave / WPF, part = wave % WPF;
+    double mA[1][NPW], mB[1][NBW];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) mA[0][j] = Zh[(int64_t)(wave * NP + j) * NR + rr];
+    for (int j = 0; j < NPW; ++j) {
+        const int jj = part * NPW + j;
+        mA[0][j] = jj < NP ? Zh[(int64_t)(fld * NP + jj) * NR + rr] : 0.0;
+    }
 #pragma unroll
     for (int i = 0; i < NBW; ++i) {
         const int cb = wave * NBW + i;
         mB[0][i] = cb <= F ? Zh[(int64_t)(N + cb) * NR + rr] : 0.0;
     }
     int mk[1];
-    gj_eliminate<NP, NBW, 1, 1>(mA, mB, wave, lane, sFm, sPiv, sPVk, mk);
+    gj_eliminate<NP, NBW, 1, WPF>(mA, mB, wave, lane, sFm, sPiv, sPVk, mk);
     const int mykk = mk[0];
     double* st = a.store + (int64_t)(slot - a.bucket_start) * ((F + 1) * NALL);
     if (lane < N) {
@@ -1063,6 +1078,7 @@ static hipError_t ns_bucket(const Plan& p, const Bucket& bk, NsArgs a, double* z
     }
     (void)assemble_only;
     using LY = NsLayout<P, PF>;
+    constexpr int cth = NsCondShape<P>::NTH;
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(bk.count, zcap_doubles / LY::PER));
     for (int c0 = 0; c0 < bk.count; c0 += chunk) {
         const int cnt = std::min(chunk, bk.count - c0);
@@ -1076,15 +1092,15 @@ static hipError_t ns_bucket(const Plan& p, const Bucket& bk, NsArgs a, double* z
                     hipEvent_t* e = tune + round * 4 + v * 2;
                     (void)hipEventRecord(e[0], s);
                     if (v == 0)
-                        hipLaunchKernelGGL((k_ns_condense2<P, PF, 2>), dim3(cnt), dim3(256), 0, s, a);
+                        hipLaunchKernelGGL((k_ns_condense2<P, PF, 2>), dim3(cnt), dim3(cth), 0, s, a);
                     else
-                        hipLaunchKernelGGL((k_ns_condense2<P, PF, 4>), dim3(cnt), dim3(256), 0, s, a);
+                        hipLaunchKernelGGL((k_ns_condense2<P, PF, 4>), dim3(cnt), dim3(cth), 0, s, a);
                     (void)hipEventRecord(e[1], s);
                 }
         } else if (variant == 1) {
-            hipLaunchKernelGGL((k_ns_condense2<P, PF, 4>), dim3(cnt), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_ns_condense2<P, PF, 4>), dim3(cnt), dim3(cth), 0, s, a);
         } else {
-            hipLaunchKernelGGL((k_ns_condense2<P, PF, 2>), dim3(cnt), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_ns_condense2<P, PF, 2>), dim3(cnt), dim3(cth), 0, s, a);
         }
     }
     return hipGetLastError();
