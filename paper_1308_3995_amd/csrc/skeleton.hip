@@ -141,10 +141,14 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 // Krylov kernels. Per Arnoldi step j (cnt = j + 1 basis vectors):
 //   k_spmv_dots   y = Khat v_j, v_j = scale * src written on the fly (one wave per face
 //                 row at a time, kRowsPerBlock rows per block), block partials of V^T y
+//                 and of ||y||^2
 //   k_reduce_h    h = sum of the partials (one block per coefficient), H(:, j) = h
-//   k_update_dots w = y - V h, block partials of V^T w          (CGS, first pass)
-//   k_reduce_h    h2, H(:, j) += h2
-//   k_update_norm w = w - V h2, block partials of ||w||^2       (re-orthogonalisation)
+//   k_update_dots w = y - V h (CGS, first pass); the second pass is needed only when the
+//                 first one cancelled, ||w||^2 = ||y||^2 - ||h||^2 < ||y||^2 / 2 (the
+//                 "twice is enough" test of Daniel, Gragg, Kaufman and Stewart, 1976), and
+//                 then block partials of V^T w
+//   k_reduce_h    h2, H(:, j) += h2                              (skipped without pass 2)
+//   k_update_norm w = w - V h2 (pass 2 only), block partials of ||w||^2
 //   k_givens      ||w||, Givens rotation of column j, residual estimate, scale = 1/||w||
 // All sums are fixed-order, so every run gives the same bits.
 // ---------------------------------------------------------------------------
@@ -153,7 +157,7 @@ constexpr int kThreads = 256;
 constexpr int kVecBlocksMax = 1024;
 static_assert(kMaxRestart == 32, "the dot reductions assume 32 accumulators");
 
-enum { SC_DONE = 0, SC_RES = 1, SC_JDONE = 2, SC_TOL = 3, SC_BETA = 5, SC_SCALE = 6 };
+enum { SC_DONE = 0, SC_RES = 1, SC_JDONE = 2, SC_TOL = 3, SC_BETA = 5, SC_SCALE = 6, SC_REORTH = 7 };
 
 struct GmArgs {
     int nf;
@@ -303,13 +307,14 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
 #pragma unroll
         for (int k = 0; k < kPerWave; ++k) {
             const int i = wave + 4 * k;
-            if (i < cnt) acc[k] += ye * ((i == j) ? xf[e] : a.V[(int64_t)i * a.n + e0 + e]);
+            if (i <= cnt)   // i == cnt: ||y||^2
+                acc[k] += ye * ((i == cnt) ? ye : (i == j) ? xf[e] : a.V[(int64_t)i * a.n + e0 + e]);
         }
     }
     const double r = wave_reduce_many<kPerWave>(acc);
     const int k = lane >> 3;              // 64 / kPerWave lanes share one value index
     const int i = wave + 4 * k;
-    if ((lane & 7) == 0 && i < cnt) a.P1[(int64_t)i * a.B1 + blockIdx.x] = r;
+    if ((lane & 7) == 0 && i <= cnt) a.P1[(int64_t)i * a.B1 + blockIdx.x] = r;
 }
 
 // h_i = sum_b P[i * B + b] (block i); H(i, j) = h_i or += h_i
@@ -317,6 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_h(GmArgs a, const double* P
                                                        int accumulate) {
     __shared__ double sh[8];
     if (a.scal[SC_DONE] != 0.0) return;
+    if (accumulate && a.scal[SC_REORTH] == 0.0) return;
     const int i = blockIdx.x;
     const double* Pi = P + (int64_t)i * B;
     double v = 0.0;
@@ -324,8 +330,10 @@ __global__ __launch_bounds__(kThreads) void k_reduce_h(GmArgs a, const double* P
     const double t = block_sum1(v, sh);
     if (threadIdx.x == 0) {
         a.h[i] = t;
-        double* hc = a.H + (int64_t)j * kMaxV;
-        hc[i] = accumulate ? hc[i] + t : t;
+        if (i < cnt) {
+            double* hc = a.H + (int64_t)j * kMaxV;
+            hc[i] = accumulate ? hc[i] + t : t;
+        }
     }
 }
 
@@ -348,9 +356,25 @@ __global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
     constexpr int cnt = CNT;
     __shared__ double sh[4 * kMaxRestart];
     __shared__ double h[kMaxRestart];
+    __shared__ int reorth;
     if (a.scal[SC_DONE] != 0.0) return;
     if ((int)threadIdx.x < cnt) h[threadIdx.x] = a.h[threadIdx.x];
     __syncthreads();
+    if (threadIdx.x == 0) {
+        // every block takes the same decision from the same values
+        // (a full basis of kMaxRestart vectors has no slot for ||y||^2: always re-orthogonalise)
+        bool need = true;
+        if (cnt < kMaxRestart) {
+            double hh = 0.0;
+            for (int i = 0; i < cnt; ++i) hh += h[i] * h[i];
+            const double yy = a.h[cnt];
+            need = !(yy - hh >= 0.5 * yy);
+        }
+        reorth = need;
+        if (blockIdx.x == 0) a.scal[SC_REORTH] = reorth ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const bool dots = reorth != 0;
     const int64_t lo = (int64_t)blockIdx.x * a.chunk;
     const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     double acc[kMaxRestart];
@@ -363,11 +387,13 @@ __global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
             if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
         a.w[k] = wv;
         // second sweep over the same entries (cache hits) for the dot products
+        if (dots) {
 #pragma unroll
-        for (int i = 0; i < kMaxRestart; ++i)
-            if (i < cnt) acc[i] += a.V[(int64_t)i * a.n + k] * wv;
+            for (int i = 0; i < kMaxRestart; ++i)
+                if (i < cnt) acc[i] += a.V[(int64_t)i * a.n + k] * wv;
+        }
     }
-    block_sum_vec(acc, cnt, a.P2 + blockIdx.x, a.B2, sh);
+    if (dots) block_sum_vec(acc, cnt, a.P2 + blockIdx.x, a.B2, sh);
 }
 
 // w -= V h2, partials of ||w||^2
@@ -382,13 +408,20 @@ __global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a) {
     const int64_t lo = (int64_t)blockIdx.x * a.chunk;
     const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     double nacc = 0.0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-        double wv = a.w[k];
+    if (a.scal[SC_REORTH] != 0.0) {
+        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+            double wv = a.w[k];
 #pragma unroll
-        for (int i = 0; i < kMaxV; ++i)
-            if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
-        a.w[k] = wv;
-        nacc += wv * wv;
+            for (int i = 0; i < kMaxV; ++i)
+                if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
+            a.w[k] = wv;
+            nacc += wv * wv;
+        }
+    } else {
+        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+            const double wv = a.w[k];
+            nacc += wv * wv;
+        }
     }
     const double t = block_sum1(nacc, sh);
     if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
@@ -556,7 +589,7 @@ static void launch_step(const GmArgs& a, const VT* hat, const double* src, int c
         if (e0) (void)hipEventRecord(e0, s);
         hipLaunchKernelGGL((k_spmv_dots<VT, C>), g1, blk, 0, s, a, hat, src);
         if (e1) (void)hipEventRecord(e1, s);
-        hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P1, a.B1, C, j, 0);
+        hipLaunchKernelGGL(k_reduce_h, dim3(C < kMaxRestart ? C + 1 : C), blk, 0, s, a, a.P1, a.B1, C, j, 0);
         hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
         hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P2, a.B2, C, j, 1);
         hipLaunchKernelGGL((k_update_norm<C>), g2, blk, 0, s, a);
