@@ -148,7 +148,8 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 //                 "twice is enough" test of Daniel, Gragg, Kaufman and Stewart, 1976), and
 //                 then block partials of V^T w
 //   k_reduce_h    h2, H(:, j) += h2                              (skipped without pass 2)
-//   k_update_norm w = w - V h2 (pass 2 only), block partials of ||w||^2
+//   k_update_norm w = w - V h2 and block partials of ||w||^2 (pass 2 only; without it
+//                 k_update_dots leaves the partials of ||w||^2)
 //   k_givens      ||w||, Givens rotation of column j, residual estimate, scale = 1/||w||
 // All sums are fixed-order, so every run gives the same bits.
 // ---------------------------------------------------------------------------
@@ -380,12 +381,14 @@ __global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
     double acc[kMaxRestart];
 #pragma unroll
     for (int i = 0; i < kMaxRestart; ++i) acc[i] = 0.0;
+    double nacc = 0.0;
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
         double wv = a.y[k];
 #pragma unroll
         for (int i = 0; i < kMaxRestart; ++i)
             if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
         a.w[k] = wv;
+        nacc += wv * wv;
         // second sweep over the same entries (cache hits) for the dot products
         if (dots) {
 #pragma unroll
@@ -393,7 +396,13 @@ __global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
                 if (i < cnt) acc[i] += a.V[(int64_t)i * a.n + k] * wv;
         }
     }
-    if (dots) block_sum_vec(acc, cnt, a.P2 + blockIdx.x, a.B2, sh);
+    if (dots) {
+        block_sum_vec(acc, cnt, a.P2 + blockIdx.x, a.B2, sh);
+    } else {
+        // no second pass: ||w||^2 partials for k_givens (k_update_norm returns at once)
+        const double t = block_sum1(nacc, sh);
+        if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
+    }
 }
 
 // w -= V h2, partials of ||w||^2
@@ -402,26 +411,19 @@ __global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a) {
     constexpr int cnt = CNT;
     __shared__ double sh[8];
     __shared__ double h[kMaxV];
-    if (a.scal[SC_DONE] != 0.0) return;
+    if (a.scal[SC_DONE] != 0.0 || a.scal[SC_REORTH] == 0.0) return;
     if ((int)threadIdx.x < cnt) h[threadIdx.x] = a.h[threadIdx.x];
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * a.chunk;
     const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     double nacc = 0.0;
-    if (a.scal[SC_REORTH] != 0.0) {
-        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-            double wv = a.w[k];
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+        double wv = a.w[k];
 #pragma unroll
-            for (int i = 0; i < kMaxV; ++i)
-                if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
-            a.w[k] = wv;
-            nacc += wv * wv;
-        }
-    } else {
-        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-            const double wv = a.w[k];
-            nacc += wv * wv;
-        }
+        for (int i = 0; i < kMaxV; ++i)
+            if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
+        a.w[k] = wv;
+        nacc += wv * wv;
     }
     const double t = block_sum1(nacc, sh);
     if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
