@@ -152,7 +152,7 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
 
 /* Skeleton solve K dLambda = E (Sec. 3.4 eq. hybridsystem): restarted GMRES(restart)
  * with right block-Jacobi preconditioning on the face-diagonal blocks and classical
- * Gram-Schmidt with one re-orthogonalisation, all in float64 (HDG_MIXED: inner
+ * Gram-Schmidt (a second pass when the first one cancels), all in float64 (HDG_MIXED: inner
  * solves on a float32 preconditioned matrix inside float64 iterative refinement).
  * Stops when ||E - K dLambda||_2 <= rtol ||E||_2 or after max_iter inner iterations.
  * Outputs dlambda_dev[n_skel_dof]; iters_out (total inner iterations) and relres_out

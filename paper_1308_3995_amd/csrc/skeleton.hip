@@ -10,8 +10,8 @@
 // row: lane l handles row l % s_f and every (64 / s_f)-th column, so each load of the
 // wave reads 64 consecutive values.
 //
-// Krylov method: restarted GMRES(m), classical Gram-Schmidt with one full
-// re-orthogonalisation (CGS2), all vectors and reductions in float64. Every kernel
+// Krylov method: restarted GMRES(m), classical Gram-Schmidt with a second pass when the
+// first one cancels, all vectors and reductions in float64. Every kernel
 // checks a device-side "converged" flag so a restart cycle can be launched without a
 // host round trip per iteration; the host reads the flag once per cycle. Reductions
 // are two-stage and fixed-order (per-block partials, then a redundant reduction by the
