@@ -150,7 +150,9 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 //   k_reduce_h    h2, H(:, j) += h2                              (skipped without pass 2)
 //   k_update_norm w = w - V h2 and block partials of ||w||^2 (pass 2 only; without it
 //                 k_update_dots leaves the partials of ||w||^2)
-//   k_givens      ||w||, Givens rotation of column j, residual estimate, scale = 1/||w||
+// The next step's k_spmv_dots takes ||w_j|| from the partials (scale = 1/||w_j||) and its
+// block 0 applies the Givens rotation of column j and updates the residual estimate and
+// the flags; k_cycle_end rotates the cycle's last column.
 // All sums are fixed-order, so every run gives the same bits.
 // ---------------------------------------------------------------------------
 constexpr int kMaxV = kMaxRestart + 1;   // Krylov vectors per cycle
@@ -266,6 +268,46 @@ __device__ __forceinline__ double row_spmv(const GmArgs& a, const VT* val, const
     return out;
 }
 
+// Givens rotation of Hessenberg column j with ||w_j|| = nrm, by one thread: the column H(:, j)
+// rotated by the previous rotations into col[0..j] (R(:, j)), the new rotation (c, s), the
+// rotated residual vector entries gb[j] = c ga[j], ga[j + 1] = -s ga[j], and the residual
+// estimate |s ga[j]|. With `store` the results go to the solver arrays and flags.
+__device__ double givens_column(const GmArgs& a, int j, double nrm, double* col, bool store) {
+    for (int i = 0; i <= j; ++i) col[i] = a.H[(int64_t)j * kMaxV + i];
+    col[j + 1] = nrm;
+    for (int i = 0; i < j; ++i) {
+        const double c = a.cs[i], s = a.sn[i];
+        const double x0 = col[i], x1 = col[i + 1];
+        col[i] = c * x0 + s * x1;
+        col[i + 1] = -s * x0 + c * x1;
+    }
+    const double x0 = col[j], x1 = col[j + 1];
+    const double r = hypot(x0, x1);
+    const double c = r > 0.0 ? x0 / r : 1.0, s = r > 0.0 ? x1 / r : 0.0;
+    col[j] = r;
+    const double gj = a.ga[j];
+    const double gbj = c * gj;
+    const double res = fabs(s * gj);
+    if (store) {
+        for (int i = 0; i <= j; ++i) a.R[(int64_t)j * kMaxV + i] = col[i];
+        a.cs[j] = c;
+        a.sn[j] = s;
+        a.gb[j] = gbj;
+        a.ga[j + 1] = -s * gj;
+        a.scal[SC_RES] = res;
+        a.scal[SC_JDONE] = (double)(j + 1);
+        if (res <= a.scal[SC_TOL] || !(nrm > 0.0) || !isfinite(res)) a.scal[SC_DONE] = 1.0;
+    }
+    return gbj;
+}
+
+// ||w_j|| from the block partials of ||w||^2 (fixed order; every block gets the same bits)
+__device__ __forceinline__ double norm_from_partials(const GmArgs& a, double* sh) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < a.B2; b += blockDim.x) v += a.P3[b];
+    return sqrt(block_sum1(v, sh));
+}
+
 template <typename VT, int CNT>
 __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val, const double* src) {
     constexpr int cnt = CNT;
@@ -273,24 +315,48 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
     __shared__ double red[4][64];
     __shared__ double yf[kRowsPerBlock * 4 * (kMaxDegree + 1)];
     __shared__ double xf[kRowsPerBlock * 4 * (kMaxDegree + 1)];
+    __shared__ double sh[8];
+    __shared__ double gcol[kMaxV + 1];
     if (a.scal[SC_DONE] != 0.0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int f0 = blockIdx.x * kRowsPerBlock;
-    const double scale = a.scal[SC_SCALE];
+    // partial sum of the ||w_{j-1}||^2 block partials, loaded before the SpMV so that the
+    // reduction below overlaps with it
+    double npart = 0.0;
+    if constexpr (CNT > 1)
+        for (int b = threadIdx.x; b < a.B2; b += blockDim.x) npart += a.P3[b];
     const int j = cnt - 1;
     double* vj = a.V + (int64_t)j * a.n;
     const int flast = f0 + kRowsPerBlock < a.nf ? f0 + kRowsPerBlock : a.nf;
     const int64_t e0 = a.face_off[f0];
     const int ne = (int)(a.face_off[flast] - e0);
+    // unscaled rows: t = Khat src and src itself (y = scale t + scale src below)
+    double tout[kRowsPerWave], tsrc[kRowsPerWave];
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const int f = f0 + rr * 4 + wave;
+        tout[rr] = tsrc[rr] = 0.0;
+        if (f < a.nf) tout[rr] = row_spmv<VT, false>(a, val, src, 1.0, f, lane, red[wave], tsrc[rr]);
+    }
+    double scale;
+    if constexpr (CNT == 1) {
+        scale = a.scal[SC_SCALE];
+    } else {
+        // v_j = w_{j-1} / ||w_{j-1}|| (fixed-order sum: every block gets the same bits); block 0
+        // also rotates column j - 1 (the flags it sets are seen by the kernels after this one)
+        const double nrm = sqrt(block_sum1(npart, sh));
+        scale = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) (void)givens_column(a, CNT - 2, nrm, gcol, true);
+    }
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWave; ++rr) {
         const int f = f0 + rr * 4 + wave;
         if (f < a.nf) {
-            double xv;
-            const double out = row_spmv<VT, true>(a, val, src, scale, f, lane, red[wave], xv);
             const int64_t fo = a.face_off[f];
             const int s = (int)(a.face_off[f + 1] - fo);
             if (lane < s) {
+                const double xv = scale * tsrc[rr];
+                const double out = scale * tout[rr] + xv;
                 a.y[fo + lane] = out;
                 vj[fo + lane] = xv;
                 yf[fo - e0 + lane] = out;
@@ -399,7 +465,7 @@ __global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
     if (dots) {
         block_sum_vec(acc, cnt, a.P2 + blockIdx.x, a.B2, sh);
     } else {
-        // no second pass: ||w||^2 partials for k_givens (k_update_norm returns at once)
+        // no second pass: the ||w||^2 partials (k_update_norm returns at once)
         const double t = block_sum1(nacc, sh);
         if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
     }
@@ -429,55 +495,47 @@ __global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a) {
     if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
 }
 
-// ||w|| from the partials, Givens rotation of column j, residual estimate and flags (one block)
-__global__ __launch_bounds__(kThreads) void k_givens(GmArgs a, int j, int B) {
-    __shared__ double sh[8];
-    __shared__ double col[kMaxV + 1];
-    __shared__ double rot[2 * kMaxV];
-    if (a.scal[SC_DONE] != 0.0) return;
-    double v = 0.0;
-    for (int b = threadIdx.x; b < B; b += blockDim.x) v += a.P3[b];
-    const double nrm = sqrt(block_sum1(v, sh));
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = a.H[(int64_t)j * kMaxV + i];
-    for (int i = threadIdx.x; i < j; i += blockDim.x) {
-        rot[2 * i] = a.cs[i];
-        rot[2 * i + 1] = a.sn[i];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    col[j + 1] = nrm;
-    for (int i = 0; i < j; ++i) {
-        const double c = rot[2 * i], s = rot[2 * i + 1];
-        const double x0 = col[i], x1 = col[i + 1];
-        col[i] = c * x0 + s * x1;
-        col[i + 1] = -s * x0 + c * x1;
-    }
-    const double x0 = col[j], x1 = col[j + 1];
-    const double r = hypot(x0, x1);
-    const double c = r > 0.0 ? x0 / r : 1.0, s = r > 0.0 ? x1 / r : 0.0;
-    col[j] = r;
-    for (int i = 0; i <= j; ++i) a.R[(int64_t)j * kMaxV + i] = col[i];
-    a.cs[j] = c;
-    a.sn[j] = s;
-    const double gj = a.ga[j];
-    a.gb[j] = c * gj;
-    a.ga[j + 1] = -s * gj;
-    const double res = fabs(s * gj);
-    a.scal[SC_RES] = res;
-    a.scal[SC_JDONE] = (double)(j + 1);
-    a.scal[SC_SCALE] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    if (res <= a.scal[SC_TOL] || !(nrm > 0.0) || !isfinite(res)) a.scal[SC_DONE] = 1.0;
-}
-
-// End of a cycle: coef = R^-1 gb over the completed columns, u += V coef.
-__global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u) {
+// End of a cycle: the Givens rotation of the cycle's last column (if the cycle did not stop
+// earlier), coef = R^-1 gb over the completed columns, u += V coef. Every block rotates the
+// last column itself (same bits); block 0 stores the flags the host reads.
+__global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u, int steps) {
     __shared__ double coef[kMaxV];
     __shared__ double Rl[kMaxRestart * kMaxV];
-    const int jd = (int)a.scal[SC_JDONE];
-    for (int t = threadIdx.x; t < jd * kMaxV; t += blockDim.x) Rl[t] = a.R[t];
-    for (int t = threadIdx.x; t < jd; t += blockDim.x) coef[t] = a.gb[t];
+    __shared__ double sh[8];
+    __shared__ double lastcol[kMaxV + 1];
+    __shared__ double lastgb;
+    __shared__ int jd_s;
+    const bool pending = a.scal[SC_DONE] == 0.0 && steps > 0;
+    double nrm = 0.0;
+    if (pending) nrm = norm_from_partials(a, sh);
+    if (threadIdx.x == 0) {
+        int jd = (int)a.scal[SC_JDONE];
+        if (pending) {
+            lastgb = givens_column(a, steps - 1, nrm, lastcol, false);
+            jd = steps;
+            if (blockIdx.x == 0) {
+                // flags for the host (the rotation itself is not needed after this cycle)
+                const double gj = a.ga[steps - 1];
+                const double r = lastcol[steps - 1];
+                const double s = r > 0.0 ? nrm / r : 0.0;
+                const double res = fabs(s * gj);
+                a.scal[SC_RES] = res;
+                a.scal[SC_JDONE] = (double)steps;
+                if (res <= a.scal[SC_TOL] || !(nrm > 0.0) || !isfinite(res)) a.scal[SC_DONE] = 1.0;
+            }
+        }
+        jd_s = jd;
+    }
+    __syncthreads();
+    const int jd = jd_s;
+    const int jfix = pending ? jd - 1 : jd;   // columns whose rotation is stored globally
+    for (int t = threadIdx.x; t < jfix * kMaxV; t += blockDim.x) Rl[t] = a.R[t];
+    for (int t = threadIdx.x; t < jfix; t += blockDim.x) coef[t] = a.gb[t];
+    if (pending)
+        for (int i = threadIdx.x; i < jd; i += blockDim.x) Rl[(jd - 1) * kMaxV + i] = lastcol[i];
     __syncthreads();
     if (threadIdx.x == 0) {
+        if (pending) coef[jd - 1] = lastgb;
         for (int i = jd - 1; i >= 0; --i) {
             double v = coef[i];
             for (int k = i + 1; k < jd; ++k) v -= Rl[k * kMaxV + i] * coef[k];
@@ -595,7 +653,6 @@ static void launch_step(const GmArgs& a, const VT* hat, const double* src, int c
         hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
         hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P2, a.B2, C, j, 1);
         hipLaunchKernelGGL((k_update_norm<C>), g2, blk, 0, s, a);
-        hipLaunchKernelGGL(k_givens, dim3(1), blk, 0, s, a, j, a.B2);
     }
 }
 
@@ -685,7 +742,7 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
         for (int j = 0; j < steps; ++j)
             launch_step<VT, 1>(a, hat, j == 0 ? S.r : a.w, j + 1, q, p.timing ? p.t_events[2 * j] : nullptr,
                                p.timing ? p.t_events[2 * j + 1] : nullptr);
-        hipLaunchKernelGGL(k_cycle_end, g2, blk, 0, q, a, S.u);
+        hipLaunchKernelGGL(k_cycle_end, g2, blk, 0, q, a, S.u, steps);
     };
     const int gi = sizeof(VT) == 8 ? 0 : 1;
     while (total < max_iter) {
