@@ -401,3 +401,23 @@ def test_mixed_mode_meets_gate(hdg, which, c1_oracle):
     for e in range(case.n_elements):
         ref[e], _ = O.unpack_local(step.mesh, e, step.du[e], case.W.shape[2])
     assert rel(gw, ref) < 1e-6
+
+
+@pytest.mark.parametrize("precision,restart", [("fp64", 2), ("fp64", 32), ("mixed", 32)])
+def test_gmres_restart_edges(hdg, c1_oracle, precision, restart):
+    """Restart lengths at the ends of the supported range: with 2 nearly every column is the
+    last of its cycle (rotated at the cycle's end); with 32 the basis is full and the second
+    Gram-Schmidt pass is always taken. Both meet the gate on the oracle's K and E."""
+    import torch
+    case, step = c1_oracle
+    _say(f"gmres restart {restart} {precision}")
+    plan = hdg.HDGPlan.from_case(case, precision=precision)
+    w, lam = _device_state(hdg, plan, case)
+    plan.hdg_assemble_condense(w, lam)
+    dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=plan.device)
+    it, relres, _ = plan.hdg_skeleton_solve(dlam, rtol=1e-10, restart=restart, max_iter=400000)
+    x = dlam.cpu().numpy()
+    res_oracle = np.linalg.norm(step.E - step.K @ x) / np.linalg.norm(step.E)
+    _say(f"  iters {it} relres {relres:.3e} on oracle K {res_oracle:.3e}")
+    assert relres <= 1e-10
+    assert res_oracle <= 2e-10
