@@ -69,6 +69,7 @@ class Case:
     reynolds: float = 0.0
     prandtl: float = 0.72
     gamma: float = GAMMA
+    cfl: float = 0.0                # pseudo-time CFL number; 0 = pure Newton
     W: Optional[np.ndarray] = None
     Q: Optional[np.ndarray] = None
     lam: Optional[np.ndarray] = None
@@ -200,7 +201,8 @@ def _rngs(seed: int, n: int = 3):
 
 def make_case(physics: str, ng: int, degrees, mach: float, aoa_deg: float, amp: float,
               seed: int, reynolds: float = 0.0, prandtl: float = 0.72, name: str = "custom",
-              degree_weights=None, jitter: float = 0.1, free_stream_only: bool = False) -> Case:
+              degree_weights=None, jitter: float = 0.1, free_stream_only: bool = False,
+              cfl: float = 0.0) -> Case:
     """Build a case. `degrees` is an int (uniform) or a list of allowed degrees
     drawn per element with `degree_weights` (uniform if None)."""
     r_jit, r_deg, r_state = _rngs(seed)
@@ -212,7 +214,7 @@ def make_case(physics: str, ng: int, degrees, mach: float, aoa_deg: float, amp: 
         choices = np.asarray(list(degrees), dtype=np.int64)
         deg = r_deg.choice(choices, size=ne, p=degree_weights).astype(np.int8)
     case = Case(name=name, physics=physics, ng=ng, xy=xy, tri=tri, degree=deg, mach=mach,
-                aoa_deg=aoa_deg, amp=amp, reynolds=reynolds, prandtl=prandtl, seed=seed)
+                aoa_deg=aoa_deg, amp=amp, reynolds=reynolds, prandtl=prandtl, seed=seed, cfl=cfl)
     return fill_state(case, r_state, free_stream_only)
 
 

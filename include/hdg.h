@@ -76,6 +76,11 @@ typedef struct {
     double reynolds;      /* Navier-Stokes: mu = rho_inf |v_inf| / Re (constant viscosity) */
     double prandtl;       /* Navier-Stokes: heat flux (mu gamma / Pr) grad e */
     double stab_alpha;    /* trace-flux constant alpha (Sec. 3.2); <= 0 selects |v_inf| + c_inf */
+    double cfl;           /* pseudo-time step (Sec. 3.3): A_K gains the element mass matrix over
+                             dt_K = cfl |K| / (lambda_c + 4 lambda_v) on its conserved-variable
+                             block, lambda_c = sum_e (|v.n| + c)|e| and lambda_v = (mu gamma /
+                             (rho Pr)) sum_e |e|^2 / |K| at the element-mean state; the right-hand
+                             side is unchanged. 0 = pure Newton; must be >= 0. */
 } hdg_params;
 
 typedef struct {

@@ -13,6 +13,10 @@ What it computes, in the paper's order (Woopen, Balan, May, Schuetz, 2013):
   * Sec. 3.3, eq. linearsystem: the Newton Jacobian, obtained here by
     complex-step differentiation of the element-local residual map (independent
     of any hand-derived Jacobian);
+  * Sec. 3.3, optional backward-Euler pseudo-time term: the element mass
+    matrix over a local step dt_K (CFL number times |K| over the element's
+    convective and viscous wave-speed sums at its mean state) added to the
+    conserved-variable block of A_K; CFL = 0 gives the pure Newton step;
   * Sec. 3.4, eq. ls/cons/hybridsystem: static condensation
     S_K = D_K - C_K A_K^-1 B_K, g_K = r_lam,K - C_K A_K^-1 r_K, summed into the
     skeleton system K dLam = E, solved directly, then the element-wise
@@ -34,6 +38,10 @@ written separately):
   * boundary term of the gradient equation with a minus sign, like the interior
     trace term, so that q = grad w is reproduced; q_bnd = q_h;
   * constant viscosity mu = rho_inf |v_inf| L / Re, heat flux (mu gamma/Pr) grad e.
+  * pseudo-time step: dt_K = CFL |K| / (lambda_c + 4 lambda_v) with
+    lambda_c = sum_e (|v.n| + c)|e| and lambda_v = (mu gamma / (rho Pr))
+    sum_e |e|^2 / |K|, both at the integral mean of w_h over K (the paper
+    names the step's ingredients but prints no formula for it);
   * unknown order inside an element: Navier-Stokes gradient fields (4d + a)
     first, then the 4 conserved fields; within a field the hierarchical modes.
     Skeleton unknowns per face: field-major, then the Legendre mode.
@@ -146,6 +154,7 @@ class Physics:
     alpha: float
     mu: float = 0.0
     prandtl: float = 0.72
+    cfl: float = 0.0   # pseudo-time CFL number (Sec. 3.3); 0 = pure Newton
 
 
 def make_physics(case, alpha: Optional[float] = None) -> Physics:
@@ -158,7 +167,7 @@ def make_physics(case, alpha: Optional[float] = None) -> Physics:
     mu = 0.0
     if case.physics == "ns":
         mu = winf[0] * speed * 1.0 / case.reynolds
-    return Physics(case.physics, case.gamma, winf, alpha, mu, case.prandtl)
+    return Physics(case.physics, case.gamma, winf, alpha, mu, case.prandtl, getattr(case, "cfl", 0.0))
 
 
 def euler_flux(w, gamma):
@@ -444,6 +453,33 @@ def pack_local(W, Q):
     return np.concatenate([Q.reshape(-1), W.reshape(-1)])
 
 
+def local_time_step(mesh: Mesh, W: np.ndarray, e: int) -> float:
+    """Local pseudo-time step of Sec. 3.3: dt_K = CFL |K| / (lambda_c + 4 lambda_v), with
+    lambda_c = sum over the element's edges of (|v.n| + c)|e| and lambda_v =
+    (mu gamma / (rho Pr)) sum |e|^2 / |K| (Navier-Stokes only), both at the element-mean state
+    (the integral mean of w_h over K). W: (4, Np) coefficients of the element."""
+    phys = mesh.phys
+    g = mesh.geom(e)
+    area = float(np.sum(g.wq))
+    wbar = (W @ g.phi) @ g.wq / area
+    rho, u, v = wbar[0], wbar[1] / wbar[0], wbar[2] / wbar[0]
+    p = (phys.gamma - 1.0) * (wbar[3] - 0.5 * rho * (u * u + v * v))
+    c = math.sqrt(phys.gamma * p / rho)
+    lam_c = sum((abs(u * sd.normal[0] + v * sd.normal[1]) + c) * sd.length for sd in g.sides)
+    lam_v = 0.0
+    if phys.kind == "ns":
+        lam_v = phys.mu * phys.gamma / (rho * phys.prandtl) * sum(sd.length ** 2 for sd in g.sides) / area
+    return phys.cfl * area / (lam_c + 4.0 * lam_v)
+
+
+def pseudo_time_block(mesh: Mesh, W: np.ndarray, e: int) -> np.ndarray:
+    """The term (phi_i, dw/dt_K) of the backward-Euler pseudo-time step (Sec. 3.3): the element
+    mass matrix, by quadrature, over dt_K, for each of the 4 conserved fields (4 Np square)."""
+    g = mesh.geom(e)
+    mass = (g.phi * g.wq[None, :]) @ g.phi.T
+    return np.kron(np.eye(4), mass) / local_time_step(mesh, W, e)
+
+
 def element_blocks(state: State, e: int) -> ElementBlocks:
     m = state.mesh
     ns = m.phys.kind == "ns"
@@ -475,7 +511,12 @@ def element_blocks(state: State, e: int) -> ElementBlocks:
     Rlam = np.concatenate([Rl[lf].reshape(nb, -1) for lf, _ in faces], axis=1) if faces else np.zeros((nb, 0))
     Jloc = (Rloc[: n + f].imag / CSTEP).T      # (n, n+f)
     Jlam = (Rlam[: n + f].imag / CSTEP).T      # (f, n+f)
-    return ElementBlocks(A=Jloc[:, :n], B=Jloc[:, n:], C=Jlam[:, :n], D=Jlam[:, n:],
+    A = Jloc[:, :n].copy()
+    if m.phys.cfl > 0.0:
+        # pseudo-time: left-hand side only, on the conserved-variable rows and columns
+        w0 = 8 * npe if ns else 0
+        A[w0:, w0:] += pseudo_time_block(m, W, e)
+    return ElementBlocks(A=A, B=Jloc[:, n:], C=Jlam[:, :n], D=Jlam[:, n:],
                          r=-Rloc[-1].real, rl=-Rlam[-1].real,
                          faces=[fid for _, fid in faces], fsizes=fsizes)
 

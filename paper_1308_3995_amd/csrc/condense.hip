@@ -18,6 +18,7 @@
 
 #include "gj.h"
 #include "hdg_internal.h"
+#include "ptime.h"
 
 namespace hdg {
 
@@ -47,6 +48,7 @@ struct CondArgs {
     int ne;
     double winf[4];
     double alpha, gamma;
+    double cfl;           // pseudo-time CFL number (0: pure Newton)
 };
 
 // Convective flux f_x, f_y and Jacobians A_x = df_x/dw, A_y = df_y/dw (row-major 4x4)
@@ -397,6 +399,13 @@ void k_condense_euler(CondArgs a) {
     const auto& sJB = sh.sJB;
     const auto& sFH = sh.sFH;
     const int fld = wave / WPF, part = wave % WPF;
+    double sig;
+    {
+        double wbar[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) wbar[f] = sh.sW[f * NP] * a.vphi[0];
+        sig = pseudo_time_shift(E, wbar, a.cfl, a.gamma, 0.0);
+    }
 
     double mA[RH][NPW], mB[RH][NBW];
 #pragma unroll
@@ -427,6 +436,12 @@ void k_condense_euler(CondArgs a) {
                     for (int j = 0; j < NPW; ++j)
                         if (j0 + j < NP) mA[h][j] += t * fp[g * NP + j0 + j];
                 }
+            }
+            // pseudo-time mass term on the diagonal of the field's own block
+            if (fa == b) {
+#pragma unroll
+                for (int j = 0; j < NPW; ++j)
+                    if (j0 + j == ii) mA[h][j] += sig;
             }
         }
         // ---- B_K / r_K columns cb = wave * NBW + i (cb < F: face lf, field b, mode k; cb = F: r_K)
@@ -671,6 +686,7 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
     for (int i = 0; i < 4; ++i) a.winf[i] = p.winf[i];
     a.alpha = p.alpha;
     a.gamma = p.prm.gamma;
+    a.cfl = p.prm.cfl;
     for (const Bucket& bk : p.buckets)
         if (!bucket_supported(bk)) return hipErrorInvalidValue;
     if (!debug && !p.tuned) {

@@ -29,6 +29,7 @@
 
 #include "gj.h"
 #include "hdg_internal.h"
+#include "ptime.h"
 
 namespace hdg {
 
@@ -174,6 +175,7 @@ struct NsArgs {
     int ne;
     double winf[4];
     double alpha, gamma, mu, prandtl;
+    double cfl;         // pseudo-time CFL number (0: pure Newton)
 };
 
 template <int P, int PF>
@@ -224,6 +226,12 @@ __global__ __launch_bounds__(256) void k_ns_assemble(NsArgs a) {
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
     const double alpha = a.alpha, gm = a.gamma, mu = a.mu, pr = a.prandtl, detj = E->detj;
+    double sig;
+    {
+        double wbar[4];
+        for (int f = 0; f < 4; ++f) wbar[f] = a.w[((int64_t)e * 4 + f) * a.npmax] * a.vphi[0];
+        sig = pseudo_time_shift(E, wbar, a.cfl, gm, mu * gm / pr);
+    }
 
     for (int t = tid; t < 4 * NP; t += NTH) sW[t] = a.w[((int64_t)e * 4 + t / NP) * a.npmax + t % NP];
     for (int t = tid; t < 8 * NP; t += NTH) sQ[t] = a.q[((int64_t)e * 8 + t / NP) * a.npmax + t % NP];
@@ -343,6 +351,7 @@ __global__ __launch_bounds__(256) void k_ns_assemble(NsArgs a) {
                          a.vphi[qp * NP + j];
                 for (int lf = 0; lf < 3; ++lf)
                     for (int g = 0; g < E->pe[lf] + 2; ++g) v += fphi(lf, g, ii) * fJA[lf][g][fa * 4 + b] * fphi(lf, g, j);
+                if (b == fa && j == ii) v += sig;
             } else if (c < N + F) {
                 const int cf = c - N, lf = cf / (4 * NPF), b = (cf / NPF) % 4, k = cf % NPF;
                 if (E->face[lf] >= 0 && k <= E->pe[lf])
@@ -635,6 +644,13 @@ __global__ __launch_bounds__(256) void k_ns_zhat(NsArgs a) {
     const ElemInfo* E = a.einfo + slot;
     const double alpha = a.alpha, detj = E->detj;
     const double invJ = 1.0 / detj;
+    double sig;
+    {
+        double wbar[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) wbar[f] = a.w[((int64_t)E->elem * 4 + f) * a.npmax] * a.vphi[0];
+        sig = pseudo_time_shift(E, wbar, a.cfl, a.gamma, a.mu * a.gamma / a.prandtl);
+    }
     double* ws = a.zbuf + (int64_t)blockIdx.x * LY::PER;
     {
         const double* src = ws + LY::PT;
@@ -767,6 +783,12 @@ __global__ __launch_bounds__(256) void k_ns_zhat(NsArgs a) {
                     }
                     if (c == 0) zr -= phi_i * fFH[lf][g][fa];
                 }
+            }
+            // pseudo-time mass term on the diagonal of the field's own block
+            if (c == fa) {
+#pragma unroll
+                for (int j = 0; j < NP; ++j)
+                    if (j == ii) zA[j] += sig;
             }
         } else {
             const int rf = r - N, lf = rf / (4 * NPF), fa = (rf / NPF) % 4, k = rf % NPF;
@@ -1145,6 +1167,7 @@ hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* la
     a.gamma = p.prm.gamma;
     a.mu = p.mu;
     a.prandtl = p.prm.prandtl;
+    a.cfl = p.prm.cfl;
     const bool tuning = only_slot < 0 && !p.tuned;
     const int nb = (int)p.buckets.size();
     std::vector<hipEvent_t> ev(tuning ? (size_t)nb * 8 : 0, nullptr);

@@ -102,6 +102,38 @@ def test_ns_newton_step_matches_oracle(hdg, which):
     assert rel(gq, rq) < 1e-11
 
 
+def test_ns_pseudo_time_step_matches_oracle(hdg):
+    """The local pseudo-time term of Sec. 3.3 (with the viscous wave speed) at CFL 5."""
+    import torch
+    case = _case("ns23")
+    case.cfl = 5.0
+    _say("ns pseudo-time ns23")
+    step = O.newton_step(case)
+    plan = hdg.HDGPlan.from_case(case)
+    w, q, lam = _state(plan, case)
+    for e in range(0, case.n_elements, 3):
+        gb = plan.debug_element_blocks(e, w, lam, q)
+        assert rel(gb["A"], step.blocks[e].A) < TOL, (e, rel(gb["A"], step.blocks[e].A))
+    plan.hdg_assemble_condense(w, lam, q=q)
+    torch.cuda.synchronize()
+    for e in range(case.n_elements):
+        X, y = plan.debug_local_solution(e)
+        c = step.cond[e]
+        assert rel(X, c.X) < TOL, (e, rel(X, c.X))
+        assert rel(y, c.y) < tol_resid(step.blocks[e].A), (e, rel(y, c.y))
+    assert rel(plan.skeleton_matrix_dense(), step.K.toarray()) < TOL
+    assert rel(plan.rhs.cpu().numpy(), step.E) < TOL
+    dl = torch.tensor(step.dlam, dtype=torch.float64, device=plan.device)
+    dw = torch.zeros_like(w)
+    dq = torch.zeros_like(q)
+    plan.hdg_back_substitute(dl, dw, dq)
+    rw, rq = np.zeros_like(case.W), np.zeros_like(case.Q)
+    for e in range(case.n_elements):
+        rw[e], rq[e] = O.unpack_local(step.mesh, e, step.du[e], case.W.shape[2])
+    assert rel(dw.cpu().numpy(), rw) < 1e-11
+    assert rel(dq.cpu().numpy(), rq) < 1e-11
+
+
 def test_ns_free_stream_gives_zero_rhs(hdg):
     case = hi.make_case("ns", 4, [1, 2, 3, 4], 0.5, 1.0, 0.0, seed=23, reynolds=100.0, free_stream_only=True)
     _say("ns free stream")

@@ -180,6 +180,41 @@ def test_newton_step_end_to_end_c1(hdg, c1_oracle):
     assert rel(dw.cpu().numpy(), ref) < 1e-10
 
 
+@pytest.mark.parametrize("which", ["c1", "hp"])
+def test_pseudo_time_step_matches_oracle(hdg, which):
+    """The local pseudo-time term of Sec. 3.3 at CFL 5: element blocks, local solutions,
+    skeleton system and the full Newton update agree with the oracle."""
+    import torch
+    case = _case(which)
+    case.cfl = 5.0
+    _say(f"pseudo-time {which}")
+    step = O.newton_step(case)
+    plan = hdg.HDGPlan.from_case(case)
+    w, lam = _device_state(hdg, plan, case)
+    for e in range(0, case.n_elements, max(1, case.n_elements // 8)):
+        gb = plan.debug_element_blocks(e, w, lam)
+        assert rel(gb["A"], step.blocks[e].A) < TOL, (e, rel(gb["A"], step.blocks[e].A))
+    plan.hdg_assemble_condense(w, lam)
+    torch.cuda.synchronize()
+    for e in range(case.n_elements):
+        X, y = plan.debug_local_solution(e)
+        c = step.cond[e]
+        assert rel(y, c.y) < TOL, (e, rel(y, c.y))
+        if c.X.size:
+            assert rel(X, c.X) < TOL, (e, rel(X, c.X))
+    assert rel(plan.skeleton_matrix_dense(), step.K.toarray()) < TOL
+    assert rel(plan.rhs.cpu().numpy(), step.E) < TOL
+    dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=plan.device)
+    plan.hdg_skeleton_solve(dlam, rtol=1e-13, restart=30)
+    dw = torch.zeros_like(w)
+    plan.hdg_back_substitute(dlam, dw)
+    ref = np.zeros_like(case.W)
+    for e in range(case.n_elements):
+        ref[e], _ = O.unpack_local(step.mesh, e, step.du[e], case.W.shape[2])
+    assert rel(dlam.cpu().numpy(), step.dlam) < 1e-10
+    assert rel(dw.cpu().numpy(), ref) < 1e-10
+
+
 def test_free_stream_gives_zero_rhs(hdg):
     """A uniform free stream is a discrete steady state: E = 0 and the local right-hand sides vanish."""
     import torch
