@@ -176,6 +176,76 @@ hdg_status hdg_back_substitute(hdg_plan* plan, const void* local_store_dev,
                                const double* dlambda_dev, double* dw_dev, double* dq_dev,
                                void* workspace_dev, hipStream_t stream);
 
+/* Pseudo-time CFL number used by later hdg_assemble_condense calls on this plan (the local
+ * step of hdg_params.cfl, Sec. 3.3). 0 or +inf: pure Newton. A captured launch sequence
+ * is re-captured on the next call. Errors: HDG_ERR_INVALID_ARG for a negative or NaN cfl. */
+hdg_status hdg_set_cfl(hdg_plan* plan, double cfl);
+
+/* ||N_h(x)||_2 at the state passed to the last hdg_assemble_condense that used workspace_dev
+ * (Sec. 3.3, the norm the CFL schedule reads): over every element row (Navier-Stokes: the
+ * gradient and the conserved-variable rows) and every skeleton row, the latter summed over
+ * both neighbours. The condensation kernels leave the partials in the workspace; this call
+ * reduces them on the device in a fixed order (repeated calls return the same bits).
+ * res_norm_dev (optional, one float64 on the device) receives it stream-ordered;
+ * res_norm_host (optional) makes the call synchronise and receives it. */
+hdg_status hdg_residual_norm(hdg_plan* plan, void* workspace_dev, double* res_norm_dev, double* res_norm_host,
+                             hipStream_t stream);
+
+/* Newton update x <- x + dx (Sec. 3.3): w_dev += dw_dev, q_dev += dq_dev (Navier-Stokes;
+ * both NULL for Euler), lam_dev += dlambda_dev, in the layouts above. The one call that
+ * modifies its state arguments in place. */
+hdg_status hdg_apply_update(hdg_plan* plan, double* w_dev, double* q_dev, double* lam_dev, const double* dw_dev,
+                            const double* dq_dev, const double* dlambda_dev, hipStream_t stream);
+
+/* The CFL schedule of Sec. 3.3 (eq. cfl), host arithmetic, iterations counted from n = 1:
+ *   n <= n0:  c0 (3 s^2 - 2 s^3), s = n / n0   (a smooth ramp to c0)
+ *   n >  n0:  cfl_prev (1 + c1 max(0, log(res_prev / res)))
+ * res_prev, res: ||N_h|| at the previous and the current iterate. A zero res returns +inf
+ * (the residual vanished: pure Newton). The paper's values: c0 = 1e6, c1 = 1e3, n0 = 4. */
+double hdg_cfl_schedule(int32_t n, double cfl_prev, double res_prev, double res, double c0, double c1,
+                        int32_t n0);
+
+typedef struct {
+    double c0;              /* eq. cfl ramp height (the paper: 1e6) */
+    double c1;              /* eq. cfl growth factor (the paper: 1e3) */
+    int32_t n0;             /* eq. cfl ramp length (the paper: 4) */
+    int32_t max_steps;      /* Newton iterations at most */
+    double rel_tol;         /* stop once ||N_h|| <= max(abs_tol, rel_tol ||N_h(x_1)||) */
+    double abs_tol;
+    double gmres_rtol;      /* hdg_skeleton_solve arguments of every iteration */
+    int32_t restart;
+    int32_t max_iter;
+} hdg_newton_opts;
+
+typedef struct {
+    int32_t steps;               /* Newton iterations taken */
+    int32_t converged;           /* 1 if the tolerance was met */
+    int64_t gmres_iters;         /* inner GMRES iterations summed over the iterations */
+    int32_t gmres_not_converged; /* iterations whose skeleton solve stopped at max_iter (their
+                                    best iterate was used: an inexact Newton step) */
+    double res0;                 /* ||N_h|| at the initial state */
+    double res;                  /* ||N_h|| at the returned state */
+} hdg_newton_report;
+
+/* The relaxed Newton iteration of Sec. 3.3 on the device: at iterate x_n it assembles and
+ * condenses with the local pseudo-time step of CFL_n (hdg_cfl_schedule, which reads
+ * ||N_h(x_n)||), solves the skeleton system, back-substitutes and applies x_(n+1) = x_n + dx,
+ * until ||N_h|| meets the tolerance or max_steps iterations are done. When CFL_n depends
+ * on ||N_h(x_n)|| (n > n0) the state is assembled twice (the residual does not depend on
+ * the CFL, the matrix does), unless the CFL is unchanged. w_dev, q_dev (Navier-Stokes, else
+ * NULL) and lam_dev are updated in place; bsr_values_dev, rhs_dev, local_store_dev,
+ * dlambda_dev, dw_dev, dq_dev and workspace_dev are caller-owned scratch of the sizes of
+ * hdg_plan_sizes. report (optional) receives the summary; res_history_host (optional,
+ * max_steps + 1 doubles) the residual norms at x_1, x_2, ..., cfl_history_host (optional,
+ * max_steps doubles) CFL_1, CFL_2, ... (entries past report->steps are left alone). The
+ * plan's CFL is left at the last value used. Synchronises. Errors: those of the calls it
+ * makes, except HDG_ERR_NOT_CONVERGED from a skeleton solve (counted in the report). */
+hdg_status hdg_pseudo_transient_solve(hdg_plan* plan, double* w_dev, double* q_dev, double* lam_dev,
+                                      double* bsr_values_dev, double* rhs_dev, void* local_store_dev,
+                                      double* dlambda_dev, double* dw_dev, double* dq_dev, void* workspace_dev,
+                                      const hdg_newton_opts* opts, hdg_newton_report* report,
+                                      double* res_history_host, double* cfl_history_host, hipStream_t stream);
+
 /* Inspection entry for tests: the uncondensed element blocks of one element in the
  * unknown order documented above (element: Navier-Stokes gradient fields 4d+a first,
  * then w fields, each mode-minor; faces: interior local faces in order, each

@@ -17,6 +17,9 @@ What it computes, in the paper's order (Woopen, Balan, May, Schuetz, 2013):
     matrix over a local step dt_K (CFL number times |K| over the element's
     convective and viscous wave-speed sums at its mean state) added to the
     conserved-variable block of A_K; CFL = 0 gives the pure Newton step;
+  * Sec. 3.3, eq. cfl: the CFL schedule (smooth ramp, then growth by the
+    residual reduction) and the relaxed Newton iteration it drives, with the
+    residual norm ||N_h||_2 over every element and skeleton row;
   * Sec. 3.4, eq. ls/cons/hybridsystem: static condensation
     S_K = D_K - C_K A_K^-1 B_K, g_K = r_lam,K - C_K A_K^-1 r_K, summed into the
     skeleton system K dLam = E, solved directly, then the element-wise
@@ -657,6 +660,69 @@ def global_residual(case, W, lam, Q=None, alpha: Optional[float] = None):
             if f >= 0:
                 Rsk[mesh.face_offset[f]: mesh.face_offset[f + 1]] += Rl[lf][0].reshape(-1)
     return mesh, Rloc, Rsk
+
+
+def residual_norm(case, W, lam, Q=None, alpha: Optional[float] = None) -> float:
+    """||N_h(x)||_2 over every residual row: the element rows of each K (Navier-Stokes: the
+    gradient rows and the conserved-variable rows) and the summed skeleton rows (Sec. 3.3)."""
+    _, Rloc, Rsk = global_residual(case, W, lam, Q, alpha)
+    s = float(Rsk @ Rsk)
+    for r in Rloc:
+        for x in (r if isinstance(r, tuple) else (r,)):
+            s += float(np.sum(x * x))
+    return math.sqrt(s)
+
+
+def cfl_schedule(n: int, cfl_prev: float, res_prev: float, res: float,
+                 c0: float = 1e6, c1: float = 1e3, n0: int = 4) -> float:
+    """eq. cfl: for the first n0 iterations a smooth ramp c0 (3 s^2 - 2 s^3), s = n / n0
+    (iterations counted from 1); afterwards the previous CFL grows by the factor
+    1 + c1 max(0, log(||N^(n-1)|| / ||N^n||)). The paper's values: c0 = 1e6, c1 = 1e3, n0 = 4."""
+    if n <= n0:
+        s = n / n0
+        return c0 * (3.0 * s * s - 2.0 * s * s * s)
+    if res == 0.0:
+        return math.inf   # the residual vanished: the pure Newton limit
+    return cfl_prev * (1.0 + c1 * max(0.0, math.log(res_prev / res)))
+
+
+@dataclass
+class PseudoTransient:
+    W: np.ndarray
+    lam: np.ndarray
+    Q: Optional[np.ndarray]
+    res: List[float]     # ||N_h|| at x_1 .. x_(steps+1)
+    cfl: List[float]     # CFL_1 .. CFL_steps
+
+
+def pseudo_transient(case, steps: int, c0: float = 1e6, c1: float = 1e3, n0: int = 4,
+                     alpha: Optional[float] = None) -> PseudoTransient:
+    """The relaxed Newton iteration of Sec. 3.3: at iterate x_n, ||N_h(x_n)|| sets CFL_n by
+    eq. cfl, one Newton step with the local pseudo-time term of that CFL gives dx, and
+    x_(n+1) = x_n + dx. `steps` iterations from the case's state; nothing stops early."""
+    import dataclasses
+    W = case.W.copy()
+    lam = case.lam.copy()
+    Q = None if case.Q is None else case.Q.copy()
+    res = [residual_norm(case, W, lam, Q, alpha)]
+    cfls: List[float] = []
+    cfl = 0.0
+    for n in range(1, steps + 1):
+        cfl = cfl_schedule(n, cfl, res[-2] if n > 1 else 0.0, res[-1], c0, c1, n0)
+        cfls.append(cfl)
+        cur = dataclasses.replace(case, W=W, lam=lam, Q=Q, cfl=cfl)
+        step = newton_step(cur, alpha)
+        m = step.mesh
+        for e in range(m.ne):
+            dW, dQ = unpack_local(m, e, step.du[e], W.shape[2])
+            W[e] += dW
+            if Q is not None:
+                Q[e] += dQ
+        for f in range(m.nf):
+            pf = m.face_degree[f]
+            lam[f, :, : pf + 1] += step.dlam[m.face_offset[f]: m.face_offset[f + 1]].reshape(4, pf + 1)
+        res.append(residual_norm(cur, W, lam, Q, alpha))
+    return PseudoTransient(W, lam, Q, res, cfls)
 
 
 def relative_error(x, ref) -> float:

@@ -132,6 +132,48 @@ class HDGPlan:
         check(self.lib.hdg_back_substitute(self.handle, _vp(self.store), _vp(dlam), _vp(dw), _vp(dq), _vp(self.ws),
                                            _stream(stream)))
 
+    # ---- the relaxed Newton iteration (pseudo-time continuation)
+    def hdg_set_cfl(self, cfl: float):
+        check(self.lib.hdg_set_cfl(self.handle, cfl))
+
+    def hdg_residual_norm(self, stream=None) -> float:
+        """||N_h||_2 at the state of the last hdg_assemble_condense (synchronises)."""
+        r = C.c_double(0.0)
+        check(self.lib.hdg_residual_norm(self.handle, _vp(self.ws), None, C.byref(r), _stream(stream)))
+        return r.value
+
+    def hdg_apply_update(self, w, lam, dw, dlam, q=None, dq=None, stream=None):
+        check(self.lib.hdg_apply_update(self.handle, _vp(w), _vp(q), _vp(lam), _vp(dw), _vp(dq), _vp(dlam),
+                                        _stream(stream)))
+
+    def hdg_cfl_schedule(self, n: int, cfl_prev: float, res_prev: float, res: float, c0: float = 1e6,
+                         c1: float = 1e3, n0: int = 4) -> float:
+        return self.lib.hdg_cfl_schedule(n, cfl_prev, res_prev, res, c0, c1, n0)
+
+    def hdg_pseudo_transient_solve(self, w, lam, q=None, c0: float = 1e6, c1: float = 1e3, n0: int = 4,
+                                   max_steps: int = 20, rel_tol: float = 1e-10, abs_tol: float = 0.0,
+                                   gmres_rtol: float = 1e-8, restart: int = 30, max_iter: int = 200000,
+                                   stream=None) -> dict:
+        """Relaxed Newton iteration of the state (w, lam[, q]) in place; returns the report and
+        the residual and CFL histories."""
+        import torch
+        from ._lib import HdgNewtonOpts, HdgNewtonReport
+        dlam = torch.zeros(max(1, self.n_skel), dtype=torch.float64, device=self.device)
+        dw = torch.zeros_like(w)
+        dq = torch.zeros_like(q) if q is not None else None
+        opts = HdgNewtonOpts(c0, c1, n0, max_steps, rel_tol, abs_tol, gmres_rtol, restart, max_iter)
+        rep = HdgNewtonReport()
+        res = np.zeros(max_steps + 1)
+        cfl = np.zeros(max(1, max_steps))
+        check(self.lib.hdg_pseudo_transient_solve(self.handle, _vp(w), _vp(q), _vp(lam), _vp(self.bsr),
+                                                  _vp(self.rhs), _vp(self.store), _vp(dlam), _vp(dw), _vp(dq),
+                                                  _vp(self.ws), C.byref(opts), C.byref(rep), res.ctypes.data,
+                                                  cfl.ctypes.data, _stream(stream)))
+        n = rep.steps
+        return dict(steps=n, converged=bool(rep.converged), gmres_iters=int(rep.gmres_iters),
+                    gmres_not_converged=int(rep.gmres_not_converged), res0=rep.res0, res=rep.res,
+                    res_history=res[: n + 1].copy(), cfl_history=cfl[:n].copy())
+
     # ---- dominant-kernel timing (benchmarks)
     def hdg_set_kernel_timing(self, enable: bool):
         check(self.lib.hdg_set_kernel_timing(self.handle, 1 if enable else 0))

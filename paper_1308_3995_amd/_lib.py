@@ -19,7 +19,8 @@ HDG_FP64, HDG_MIXED = 0, 1
 
 EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_pattern", "hdg_assemble_condense",
            "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
-           "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_last_error", "hdg_plan_destroy"]
+           "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_set_cfl", "hdg_residual_norm", "hdg_apply_update",
+           "hdg_cfl_schedule", "hdg_pseudo_transient_solve", "hdg_last_error", "hdg_plan_destroy"]
 
 
 class HdgParams(C.Structure):
@@ -32,6 +33,17 @@ class HdgSizes(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_elements", "n_faces", "n_boundary_faces", "n_skel_dof", "np_max",
                                          "n_fields", "bsr_blocks", "bsr_values", "local_store_bytes",
                                          "workspace_bytes", "n_buckets")]
+
+
+class HdgNewtonOpts(C.Structure):
+    _fields_ = [("c0", C.c_double), ("c1", C.c_double), ("n0", C.c_int32), ("max_steps", C.c_int32),
+                ("rel_tol", C.c_double), ("abs_tol", C.c_double), ("gmres_rtol", C.c_double),
+                ("restart", C.c_int32), ("max_iter", C.c_int32)]
+
+
+class HdgNewtonReport(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("converged", C.c_int32), ("gmres_iters", C.c_int64),
+                ("gmres_not_converged", C.c_int32), ("res0", C.c_double), ("res", C.c_double)]
 
 
 class HdgError(RuntimeError):
@@ -64,12 +76,19 @@ def load(path: str = LIB_PATH):
     lib.hdg_debug_local_solution.argtypes = [vp, vp, i64, vp, vp, P(i32), P(i32)]
     lib.hdg_set_kernel_timing.argtypes = [vp, i32]
     lib.hdg_kernel_timing.argtypes = [vp, P(i64), P(dbl), P(dbl), i32]
+    lib.hdg_set_cfl.argtypes = [vp, dbl]
+    lib.hdg_residual_norm.argtypes = [vp, vp, vp, P(dbl), vp]
+    lib.hdg_apply_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_cfl_schedule.argtypes = [i32, dbl, dbl, dbl, dbl, dbl, i32]
+    lib.hdg_cfl_schedule.restype = dbl
+    lib.hdg_pseudo_transient_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(HdgNewtonOpts),
+                                               P(HdgNewtonReport), vp, vp, vp]
     lib.hdg_last_error.argtypes = []
     lib.hdg_last_error.restype = C.c_char_p
     lib.hdg_plan_destroy.argtypes = [vp]
     lib.hdg_plan_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("hdg_last_error", "hdg_plan_destroy"):
+        if name not in ("hdg_last_error", "hdg_plan_destroy", "hdg_cfl_schedule"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib

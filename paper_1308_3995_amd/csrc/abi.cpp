@@ -1,4 +1,5 @@
 // C ABI: argument checking, error reporting and the call sequence of one Newton step.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -49,7 +50,8 @@ static hdg_status debug_blocks_ns(Plan& p, int64_t element, const double* w, con
     CHECK_HIP(hipSetDevice(p.device));
     double* buf = nullptr;
     CHECK_HIP(hipMalloc((void**)&buf, per * 8));
-    hipError_t e = launch_ns(p, w, q, lam, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, buf, per, slot, 0);
+    hipError_t e = launch_ns(p, w, q, lam, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                             buf, per, slot, 0);
     std::vector<double> h(per);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(h.data(), buf, per * 8, hipMemcpyDeviceToHost);
@@ -212,12 +214,14 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
     auto enqueue = [&](hipStream_t q) -> hipError_t {
         hipError_t e = launch_clear_status(p, status, flag, q);
         if (e != hipSuccess) return e;
+        double* res_elem = (double*)(ws + p.ws_res_elem);
+        double* rl_part = (double*)(ws + p.ws_rl_part);
         e = p.ns ? launch_ns(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
-                             (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag,
+                             (double*)(ws + p.ws_g_part), res_elem, rl_part, (double*)local_store_dev, status, flag,
                              (double*)(ws + p.ws_ns), p.ns_zcap, -1, q)
                  : launch_condense(p, w_dev, q_dev, lam_dev, bsr_values_dev, (double*)(ws + p.ws_diag_part),
-                                   (double*)(ws + p.ws_g_part), (double*)local_store_dev, status, flag, nullptr, -1,
-                                   q);
+                                   (double*)(ws + p.ws_g_part), res_elem, rl_part, (double*)local_store_dev, status,
+                                   flag, nullptr, -1, q);
         if (e != hipSuccess) return e;
         return launch_diag_sum(p, (double*)(ws + p.ws_diag_part), (double*)(ws + p.ws_g_part), bsr_values_dev,
                                rhs_dev, q);
@@ -232,6 +236,9 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
         for (const void* v : {(const void*)w_dev, (const void*)q_dev, (const void*)lam_dev, (const void*)bsr_values_dev,
                               (const void*)rhs_dev, (const void*)local_store_dev, (const void*)ws, (const void*)status})
             mix(v);
+        uint64_t cfl_bits;
+        std::memcpy(&cfl_bits, &p.prm.cfl, 8);   // the CFL is a kernel argument baked into the graph
+        key = (key ^ cfl_bits) * 1099511628211ull;
         if (!p.cond_exec || p.cond_key != key) {
             if (p.cond_exec) (void)hipGraphExecDestroy(p.cond_exec);
             if (p.cond_graph) (void)hipGraphDestroy(p.cond_graph);
@@ -331,6 +338,150 @@ hdg_status hdg_back_substitute(hdg_plan* plan, const void* local_store_dev, cons
     return HDG_OK;
 }
 
+hdg_status hdg_set_cfl(hdg_plan* plan, double cfl) {
+    if (!plan || !(cfl >= 0.0)) {
+        set_error("hdg_set_cfl: null plan or a negative / NaN cfl");
+        return HDG_ERR_INVALID_ARG;
+    }
+    plan->p.prm.cfl = cfl;
+    return HDG_OK;
+}
+
+hdg_status hdg_residual_norm(hdg_plan* plan, void* workspace_dev, double* res_norm_dev, double* res_norm_host,
+                             hipStream_t stream) {
+    if (!plan || !workspace_dev || (!res_norm_dev && !res_norm_host)) {
+        set_error("hdg_residual_norm: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    char* ws = (char*)workspace_dev;
+    double* red = (double*)(ws + p.ws_res_red);
+    double* out = res_norm_dev ? res_norm_dev : red + kResPartials;
+    CHECK_HIP(hipSetDevice(p.device));
+    CHECK_HIP(launch_residual_norm(p, (const double*)(ws + p.ws_res_elem), (const double*)(ws + p.ws_rl_part), red,
+                                   out, stream));
+    if (res_norm_host) {
+        CHECK_HIP(hipMemcpyAsync(res_norm_host, out, 8, hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipStreamSynchronize(stream));
+        if (!std::isfinite(*res_norm_host)) {
+            set_error("hdg_residual_norm: non-finite residual");
+            return HDG_ERR_NONFINITE;
+        }
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_apply_update(hdg_plan* plan, double* w_dev, double* q_dev, double* lam_dev, const double* dw_dev,
+                            const double* dq_dev, const double* dlambda_dev, hipStream_t stream) {
+    if (!plan || !w_dev || !lam_dev || !dw_dev || !dlambda_dev) {
+        set_error("hdg_apply_update: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (p.ns && (!q_dev || !dq_dev)) {
+        set_error("hdg_apply_update: Navier-Stokes needs q and dq");
+        return HDG_ERR_INVALID_ARG;
+    }
+    CHECK_HIP(hipSetDevice(p.device));
+    CHECK_HIP(launch_axpy_update((int64_t)p.ne * 4 * p.npmax, w_dev, dw_dev, stream));
+    if (p.ns) CHECK_HIP(launch_axpy_update((int64_t)p.ne * 8 * p.npmax, q_dev, dq_dev, stream));
+    CHECK_HIP(launch_axpy_update(p.face_off.back(), lam_dev, dlambda_dev, stream));
+    return HDG_OK;
+}
+
+double hdg_cfl_schedule(int32_t n, double cfl_prev, double res_prev, double res, double c0, double c1, int32_t n0) {
+    if (n <= n0) {
+        const double s = (double)n / (double)n0;
+        return c0 * (3.0 * s * s - 2.0 * s * s * s);
+    }
+    if (res == 0.0) return INFINITY;
+    return cfl_prev * (1.0 + c1 * std::max(0.0, std::log(res_prev / res)));
+}
+
+hdg_status hdg_pseudo_transient_solve(hdg_plan* plan, double* w_dev, double* q_dev, double* lam_dev,
+                                      double* bsr_values_dev, double* rhs_dev, void* local_store_dev,
+                                      double* dlambda_dev, double* dw_dev, double* dq_dev, void* workspace_dev,
+                                      const hdg_newton_opts* opts, hdg_newton_report* report,
+                                      double* res_history_host, double* cfl_history_host, hipStream_t stream) {
+    if (!plan || !w_dev || !lam_dev || !bsr_values_dev || !rhs_dev || !local_store_dev || !dlambda_dev || !dw_dev ||
+        !workspace_dev || !opts) {
+        set_error("hdg_pseudo_transient_solve: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (p.ns && (!q_dev || !dq_dev)) {
+        set_error("hdg_pseudo_transient_solve: Navier-Stokes needs q and dq");
+        return HDG_ERR_INVALID_ARG;
+    }
+    const hdg_newton_opts o = *opts;
+    if (o.max_steps < 0 || o.n0 < 1 || !(o.c0 > 0.0) || !(o.c1 >= 0.0) || !(o.rel_tol >= 0.0) ||
+        !(o.abs_tol >= 0.0)) {
+        set_error("hdg_pseudo_transient_solve: need max_steps >= 0, n0 >= 1, c0 > 0, c1 >= 0, tolerances >= 0");
+        return HDG_ERR_INVALID_ARG;
+    }
+    char* ws = (char*)workspace_dev;
+    int32_t* status = (int32_t*)(ws + p.ws_status);
+    hdg_newton_report rep{};
+    // assemble and condense at the current state with the given CFL; returns ||N_h|| there
+    auto assemble = [&](double cfl, double* res) -> hdg_status {
+        hdg_status st = hdg_set_cfl(plan, cfl);
+        if (st != HDG_OK) return st;
+        st = hdg_assemble_condense(plan, w_dev, q_dev, lam_dev, bsr_values_dev, rhs_dev, local_store_dev,
+                                   workspace_dev, nullptr, nullptr, stream);
+        if (st != HDG_OK) return st;
+        st = check_status(p, status, status + p.ne, stream);
+        if (st != HDG_OK) return st;
+        return hdg_residual_norm(plan, workspace_dev, nullptr, res, stream);
+    };
+    double cfl = hdg_cfl_schedule(1, 0.0, 0.0, 0.0, o.c0, o.c1, o.n0);
+    double res = 0.0;
+    hdg_status st = assemble(cfl, &res);
+    if (st != HDG_OK) return st;
+    rep.res0 = res;
+    if (res_history_host) res_history_host[0] = res;
+    const double target = std::max(o.abs_tol, o.rel_tol * res);
+    for (int n = 1; n <= o.max_steps; ++n) {
+        if (res <= target) break;
+        if (cfl_history_host) cfl_history_host[n - 1] = cfl;
+        int32_t it = 0;
+        st = hdg_skeleton_solve(plan, bsr_values_dev, rhs_dev, dlambda_dev, o.gmres_rtol, o.restart, o.max_iter,
+                                workspace_dev, stream, &it, nullptr);
+        rep.gmres_iters += it;
+        if (st == HDG_ERR_NOT_CONVERGED) {
+            rep.gmres_not_converged += 1;
+        } else if (st != HDG_OK) {
+            return st;
+        }
+        st = hdg_back_substitute(plan, local_store_dev, dlambda_dev, dw_dev, dq_dev, workspace_dev, stream);
+        if (st != HDG_OK) return st;
+        st = hdg_apply_update(plan, w_dev, q_dev, lam_dev, dw_dev, dq_dev, dlambda_dev, stream);
+        if (st != HDG_OK) return st;
+        rep.steps = n;
+        // the next iterate: its residual, its CFL, and its system
+        const double res_prev = res;
+        if (n + 1 <= o.n0) {
+            cfl = hdg_cfl_schedule(n + 1, cfl, res_prev, 0.0, o.c0, o.c1, o.n0);
+            st = assemble(cfl, &res);
+            if (st != HDG_OK) return st;
+        } else {
+            st = assemble(cfl, &res);
+            if (st != HDG_OK) return st;
+            const double next = hdg_cfl_schedule(n + 1, cfl, res_prev, res, o.c0, o.c1, o.n0);
+            if (next != cfl) {
+                double again = 0.0;
+                cfl = next;
+                st = assemble(cfl, &again);
+                if (st != HDG_OK) return st;
+            }
+        }
+        if (res_history_host) res_history_host[n] = res;
+    }
+    rep.res = res;
+    rep.converged = res <= target ? 1 : 0;
+    if (report) *report = rep;
+    return HDG_OK;
+}
+
 hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const double* w_dev, const double* q_dev,
                                     const double* lam_dev, double* A_host, double* B_host, double* C_host,
                                     double* D_host, double* r_host, double* rl_host, int32_t* n_out, int32_t* f_out) {
@@ -360,8 +511,8 @@ hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const doubl
     double* dbg = nullptr;
     CHECK_HIP(hipMalloc((void**)&dbg, total * 8));
     CHECK_HIP(hipMemset(dbg, 0, total * 8));
-    hipError_t e = launch_condense(p, w_dev, q_dev, lam_dev, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, dbg,
-                                   slot, 0);
+    hipError_t e = launch_condense(p, w_dev, q_dev, lam_dev, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, nullptr, dbg, slot, 0);
     if (e != hipSuccess) {
         (void)hipFree(dbg);
         set_error(std::string("debug launch: ") + hipGetErrorString(e));

@@ -38,6 +38,8 @@ struct CondArgs {
     double* bsr;
     double* diag_part;
     double* g_part;
+    double* res_elem;     // [ne] squared norm of each element's residual rows (may be null)
+    double* rl_part;      // skeleton residual shares, g_part's slots (may be null)
     double* store;        // bucket store base
     int32_t* status;      // [ne] per-element status
     int32_t* flag;        // set to 1 when any element reports a failure
@@ -310,6 +312,7 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
 #pragma unroll
                 for (int j = 0; j < NP; ++j) gy -= alpha * T[j] * sX[F * N + b * NP + j];
                 a.g_part[2 * a.face_off[f] + E->side[lf] * se + row] = gy;
+                if (a.rl_part) a.rl_part[2 * a.face_off[f] + E->side[lf] * se + row] = rl;
             }
         }
         for (int c2 = ch; c2 < F; c2 += CH) {
@@ -479,6 +482,16 @@ void k_condense_euler(CondArgs a) {
                 if (cb <= F) a.debug[(int64_t)(N + cb) * N + row] = mB[h][i];
             }
         }
+    }
+    // squared norm of the element's residual rows r_K (the right-hand-side column)
+    if (!DBG && a.res_elem && wave == F / NBW) {
+        constexpr int IR = F % NBW;
+        double s = 0.0;
+#pragma unroll
+        for (int h = 0; h < RH; ++h)
+            if (h * 64 + lane < N) s += mB[h][IR] * mB[h][IR];
+        s = wave_sum_f64(s);
+        if (lane == 0) a.res_elem[slot] = s;
     }
     if (DBG) {
         __syncthreads();
@@ -662,8 +675,8 @@ static hipError_t tune_buckets(Plan& p, hipStream_t s, LaunchFn launch_variant) 
 }
 
 hipError_t launch_condense(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
-                           double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag,
-                           double* debug, int debug_slot, hipStream_t s) {
+                           double* diag_part, double* g_part, double* res_elem, double* rl_part, double* store,
+                           int32_t* status, int32_t* flag, double* debug, int debug_slot, hipStream_t s) {
     (void)q;
     CondArgs a{};
     a.einfo = p.d_einfo;
@@ -677,6 +690,8 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
     a.bsr = bsr;
     a.diag_part = diag_part;
     a.g_part = g_part;
+    a.res_elem = res_elem;
+    a.rl_part = rl_part;
     a.status = status;
     a.flag = flag;
     a.debug = debug;

@@ -16,6 +16,14 @@
 
 namespace hdg {
 
+// Sum over the 64 lanes of a wave by a butterfly of cross-lane exchanges (every lane gets
+// the same, order-fixed result).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // Broadcast of lane src's value (src uniform across the wave) through two readlanes.
 __device__ __forceinline__ double lane_bcast(double v, int src) {
     const long long b = __double_as_longlong(v);

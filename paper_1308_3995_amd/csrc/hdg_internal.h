@@ -16,6 +16,7 @@ constexpr int kMaxDegree = 5;
 constexpr int kMaxFaceQ = 8;          // face Gauss points stored per rule (p_f + 2 <= 7 used)
 constexpr int kMinFaceQ = 2;
 constexpr int kNumFaceRules = kMaxFaceQ - kMinFaceQ + 1;
+constexpr int kResPartials = 1024;    // blocks of the residual-norm reduction (fixed: deterministic)
 constexpr int kMaxRestart = 32;       // GMRES restart length limit (Krylov basis kept in registers per element)
 
 __host__ __device__ constexpr int n_modes(int p) { return (p + 1) * (p + 2) / 2; }
@@ -120,6 +121,7 @@ struct Plan {
 
     // workspace layout (offsets in bytes)
     int64_t ws_diag_part = 0, ws_g_part = 0, ws_status = 0, ws_solver = 0, ws_total = 0;
+    int64_t ws_res_elem = 0, ws_rl_part = 0, ws_res_red = 0;   // residual-norm partials
     int64_t ws_ns = 0, ns_zcap = 0;       // Navier-Stokes assembly chunk workspace (doubles)
     int64_t hat_values = 0;
     int solver_restart_max = 0;
@@ -150,17 +152,26 @@ struct SolverLayout {
 SolverLayout solver_layout(const Plan& p, int restart);
 
 // kernel launchers (condense.hip, skeleton.hip)
+// res_elem[slot] receives the squared norm of the element's residual rows and rl_part the
+// element's share of the skeleton residual rows (same slots as g_part); both may be null.
 hipError_t launch_condense(Plan& p, const double* w, const double* q, const double* lam,
-                           double* bsr, double* diag_part, double* g_part, double* store,
-                           int32_t* status, int32_t* flag, double* debug, int debug_slot, hipStream_t s);
+                           double* bsr, double* diag_part, double* g_part, double* res_elem, double* rl_part,
+                           double* store, int32_t* status, int32_t* flag, double* debug, int debug_slot,
+                           hipStream_t s);
 hipError_t launch_clear_status(const Plan& p, int32_t* status, int32_t* flag, hipStream_t s);
 hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double* g_part, double* bsr,
                            double* rhs, hipStream_t s);
 hipError_t launch_back_substitute(const Plan& p, const double* store, const double* dlam, double* dw,
                                   double* dq, hipStream_t s);
 hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
-                     double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag, double* zbuf,
-                     int64_t zcap_doubles, int only_slot, hipStream_t s);
+                     double* diag_part, double* g_part, double* res_elem, double* rl_part, double* store,
+                     int32_t* status, int32_t* flag, double* zbuf, int64_t zcap_doubles, int only_slot,
+                     hipStream_t s);
+// Residual norm ||N_h||_2 from the partials of the last assembly: out_dev[0] (device).
+hipError_t launch_residual_norm(const Plan& p, const double* res_elem, const double* rl_part, double* partials,
+                                double* out_dev, hipStream_t s);
+// x += dx over n doubles.
+hipError_t launch_axpy_update(int64_t n, double* x, const double* dx, hipStream_t s);
 int64_t ns_workspace_per_element(int p, int pf);   // Z, L, R of one element (block inspection)
 int64_t ns_chunk_per_element(int p, int pf);       // reduced system and factors (product path)
 hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol,

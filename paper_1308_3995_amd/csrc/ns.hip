@@ -165,6 +165,8 @@ struct NsArgs {
     double* bsr;
     double* diag_part;
     double* g_part;
+    double* res_elem;   // [ne] squared norm of each element's residual rows (may be null)
+    double* rl_part;    // skeleton residual shares, g_part's slots (may be null)
     double* store;      // bucket store base
     double* zbuf;       // chunk workspace: Z, L, R per element
     int32_t* status;
@@ -933,6 +935,23 @@ __global__ __launch_bounds__(256) void k_ns_zhat(NsArgs a) {
     __syncthreads();
     for (int r = tid; r < NR; r += NTH)
         Zh[(int64_t)(N + F) * NR + r] = sZr[r] - invJ * (((sPr[0][r] + sPr[1][r]) + sPr[2][r]) + sPr[3][r]);
+    // residual of the element before the gradient elimination: the squared norm of its
+    // gradient and conserved-variable rows, and its shares of the skeleton rows
+    if (a.res_elem && tid < 64) {
+        double s = 0.0;
+        for (int r = tid; r < N; r += 64) s += sZr[r] * sZr[r];
+        for (int t = tid; t < 8 * NP; t += 64) s += sRq[t / NP][t % NP] * sRq[t / NP][t % NP];
+        s = wave_sum_f64(s);
+        if (tid == 0) a.res_elem[slot] = s;
+    }
+    if (a.rl_part) {
+        for (int rf = tid; rf < F; rf += NTH) {
+            const int lf = rf / (4 * NPF), fa = (rf / NPF) % 4, k = rf % NPF;
+            const int f = E->face[lf], pe = E->pe[lf];
+            if (f < 0 || k > pe) continue;
+            a.rl_part[2 * a.face_off[f] + (int64_t)E->side[lf] * 4 * (pe + 1) + fa * (pe + 1) + k] = sZr[N + rf];
+        }
+    }
 }
 
 // Condensation of the reduced system: Gauss-Jordan on [Ahat | Bhat | rhat] (gj_eliminate),
@@ -1143,8 +1162,9 @@ int64_t ns_chunk_per_element(int p, int pf) {
 #define HDG_NS_BUCKETS(X) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(2, 2) X(2, 3) X(2, 4) X(3, 3) X(3, 4) X(4, 4)
 
 hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
-                     double* diag_part, double* g_part, double* store, int32_t* status, int32_t* flag, double* zbuf,
-                     int64_t zcap_doubles, int only_slot, hipStream_t s) {
+                     double* diag_part, double* g_part, double* res_elem, double* rl_part, double* store,
+                     int32_t* status, int32_t* flag, double* zbuf, int64_t zcap_doubles, int only_slot,
+                     hipStream_t s) {
     NsArgs a{};
     a.einfo = p.d_einfo;
     a.leg = p.d_tab + p.tix.leg;
@@ -1158,6 +1178,8 @@ hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* la
     a.bsr = bsr;
     a.diag_part = diag_part;
     a.g_part = g_part;
+    a.res_elem = res_elem;
+    a.rl_part = rl_part;
     a.status = status;
     a.flag = flag;
     a.npmax = p.npmax;

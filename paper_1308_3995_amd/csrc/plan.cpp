@@ -493,6 +493,9 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     P.ws_diag_part = carve(P.diag_off.back() * 8);
     P.ws_g_part = carve(2 * P.face_off.back() * 8);
     P.ws_status = carve(((int64_t)ne + 64) * 4);
+    P.ws_res_elem = carve((int64_t)ne * 8);
+    P.ws_rl_part = carve(2 * P.face_off.back() * 8);
+    P.ws_res_red = carve((kResPartials + 1) * 8);
     if (P.ns) {
         for (const Bucket& b : P.buckets)
             if (b.p > 4 || b.pf > 4) {

@@ -44,3 +44,25 @@ def test_error_string_starts_empty_and_plan_rejects_null():
     st = lib.hdg_plan_create(ctypes.byref(h), None, 0, None, 0, None, None, 0)
     assert st == 1
     assert b"null" in lib.hdg_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_cfl_schedule_matches_the_oracle():
+    """The library's eq. cfl (host arithmetic) against the oracle's, over the ramp, growth,
+    a growing residual and a vanished one."""
+    import math
+    from oracle import hdg_oracle as O
+    from paper_1308_3995_amd import _lib
+    lib = _lib.load()
+    cases = [(n, 0.0, 0.0, 1.0, 1e6, 1e3, 4) for n in range(1, 5)]
+    cases += [(5, 1e6, 3.0e-2, 1.0e-3, 1e6, 1e3, 4), (7, 12.5, 1.0, 2.0, 10.0, 1.0, 2),
+              (3, 21.5, 1.7e-3, 6.0e-4, 10.0, 1.0, 2), (9, 4.0, 1.0, 0.0, 1e6, 1e3, 4),
+              (2, 0.0, 0.0, 1.0, 10.0, 1.0, 3)]
+    for n, cp, rp, r, c0, c1, n0 in cases:
+        got = lib.hdg_cfl_schedule(n, cp, rp, r, c0, c1, n0)
+        ref = O.cfl_schedule(n, cp, rp, r, c0, c1, n0)
+        if math.isinf(ref):
+            assert math.isinf(got)
+        else:
+            assert abs(got - ref) <= 1e-15 * abs(ref), (n, got, ref)
+    assert lib.hdg_set_cfl(None, 1.0) == 1

@@ -1,5 +1,6 @@
 """Pins of the oracle's backward-Euler pseudo-time term (Sec. 3.3): the local step dt_K,
-the element mass matrix it divides, and where the term enters the element system."""
+the element mass matrix it divides, where the term enters the element system, the CFL
+schedule (eq. cfl) and the relaxed Newton iteration it drives."""
 import math
 
 import numpy as np
@@ -98,3 +99,39 @@ def test_large_cfl_is_pure_newton():
     c1 = hi.make_case("euler", 3, [1, 2], 0.5, 2.0, 2e-2, seed=5, cfl=1e12)
     d0, d1 = O.newton_step(c0).dlam, O.newton_step(c1).dlam
     assert np.abs(d1 - d0).max() < 1e-8 * np.abs(d0).max()
+
+
+def test_cfl_schedule_closed_form():
+    """eq. cfl with the paper's constants c0 = 1e6, c1 = 1e3, n0 = 4."""
+    ramp = [O.cfl_schedule(n, 0.0, 0.0, 1.0) for n in range(1, 5)]
+    # c0 (3 s^2 - 2 s^3) at s = 1/4, 1/2, 3/4, 1
+    assert ramp == [1e6 * (3 / 16 - 2 / 64), 5e5, 1e6 * (27 / 16 - 54 / 64), 1e6]
+    assert ramp[0] == 156250.0 and ramp[2] == 843750.0
+    # the smoothstep is symmetric about the middle of the ramp
+    assert ramp[0] + ramp[2] == 1e6
+    # growth: a residual reduced by the factor e multiplies the CFL by 1 + c1
+    assert abs(O.cfl_schedule(5, 2.0, math.e, 1.0) - 2.0 * 1001.0) < 1e-12
+    # a residual that grows leaves the CFL unchanged; a vanished one gives the Newton limit
+    assert O.cfl_schedule(6, 3.0, 1.0, 2.0) == 3.0
+    assert O.cfl_schedule(6, 3.0, 1.0, 0.0) == math.inf
+
+
+def test_relaxed_iteration_has_the_newton_fixed_point():
+    """The pseudo-time term changes the path, not the solution: a gently ramped iteration
+    and the pure Newton iteration converge to the same discrete state."""
+    c = hi.make_case("euler", 3, [1, 2], 0.5, 2.0, 2e-2, seed=8)
+    relaxed = O.pseudo_transient(c, 14, c0=10.0, c1=1.0, n0=2)
+    newton = O.pseudo_transient(c, 5, c0=1e14, c1=1.0, n0=1)
+    assert relaxed.res[-1] < 1e-11 * relaxed.res[0]
+    assert newton.res[-1] < 1e-11 * newton.res[0]
+    # the relaxed path is genuinely different (slower) on the way
+    assert relaxed.res[2] > 100 * newton.res[2]
+    assert np.abs(relaxed.W - newton.W).max() < 1e-11
+    assert np.abs(relaxed.lam - newton.lam).max() < 1e-11
+
+
+def test_free_stream_is_a_fixed_point_of_the_iteration():
+    c = hi.make_case("euler", 3, [1, 2, 3], 0.5, 2.0, 0.0, seed=9, free_stream_only=True)
+    r = O.pseudo_transient(c, 2, c0=10.0, c1=1.0, n0=2)
+    assert r.res[0] < 1e-13
+    assert np.abs(r.W - c.W).max() < 1e-13 and np.abs(r.lam - c.lam).max() < 1e-13
