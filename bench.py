@@ -9,6 +9,10 @@ A step is the whole hot path: assemble + condense (hdg_assemble_condense), block
 GMRES on the skeleton (hdg_skeleton_solve) to a relative residual of 1e-10, and
 back-substitution (hdg_back_substitute). Both precision modes are timed; the reported
 `value` is condensed elements per second of full Newton steps of the mixed mode.
+Beside the step: assemble + condense alone on three workloads (`condensation`), the
+relaxed Newton iteration with the pseudo-time CFL schedule run to convergence
+(`pseudo_transient`), a sample of the serving stream (`serving`) and the CPU oracle
+(`cpu_baseline`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -150,6 +154,37 @@ def condensation_report(names, reps: int = 10):
     return out
 
 
+def newton_loop_report(name: str, rtol: float, restart: int, max_steps: int = 12):
+    """The relaxed Newton iteration (pseudo-time, CFL schedule with the paper's constants) from
+    the workload's perturbed state to a residual reduction of 1e-10, mixed-precision skeleton
+    solves; host-timed around the library call, which synchronises."""
+    import torch
+    import hdg_inputs as hi
+    import paper_1308_3995_amd as hdg
+    case = hi.config_case(name)
+    plan = hdg.HDGPlan.from_case(case, precision="mixed")
+    dev = torch.device("cuda", 0)
+    w = torch.tensor(case.W, dtype=torch.float64, device=dev)
+    lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
+    q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
+    plan.hdg_assemble_condense(w, lam, q=q)   # kernel-variant tuning happens on a plan's first call
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = plan.hdg_pseudo_transient_solve(w, lam, q=q, c0=1e6, c1=1e3, n0=4, max_steps=max_steps, rel_tol=1e-10,
+                                        gmres_rtol=rtol, restart=restart)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    log(f"[bench] pseudo-transient {name}: {r['steps']} Newton steps in {sec:.3f} s, converged {r['converged']}, "
+        f"residual {r['res0']:.3e} -> {r['res']:.3e}")
+    return {"workload": f"{name}: {case.physics} {case.ng}x{case.ng}, degrees {sorted(set(case.degree.tolist()))}, "
+                        f"from the perturbed state to ||N_h|| reduced 1e-10; CFL schedule c0=1e6, c1=1e3, n0=4; "
+                        f"mixed precision, GMRES({restart}) to {rtol:g} per step",
+            "steps": r["steps"], "converged": r["converged"], "seconds": sec,
+            "ms_per_newton_step": sec / max(1, r["steps"]) * 1e3, "gmres_iters": r["gmres_iters"],
+            "gmres_not_converged": r["gmres_not_converged"],
+            "res_history": [float(x) for x in r["res_history"]], "cfl_history": [float(x) for x in r["cfl_history"]]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +201,8 @@ def main():
                     help="GMRES iterations per serving request before it counts as not converged")
     ap.add_argument("--condense-configs", default="c2,c3,c4",
                     help="workloads whose assemble + condense time is reported beside the step ('' = none)")
+    ap.add_argument("--newton-loop", default="c2",
+                    help="workload of the pseudo-transient Newton iteration report ('' = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -281,6 +318,8 @@ def main():
                        "bytes_per_launch": kb / max(1, kl)}
     if args.condense_configs:
         out["condensation"] = condensation_report([c for c in args.condense_configs.split(",") if c])
+    if args.newton_loop:
+        out["pseudo_transient"] = newton_loop_report(args.newton_loop, args.rtol, args.restart)
     if args.serving_requests > 0:
         from paper_1308_3995_amd.serving import ServingEngine, stream_requests
         log(f"[bench] serving: generating {args.serving_requests} requests")
