@@ -114,8 +114,30 @@ def condensation_work(case):
     return float(flops.sum()), float(nbytes.sum())
 
 
-def condensation_report(names, reps: int = 10):
-    """Assemble + condense time of each named workload (float64 path), with its roofline."""
+def measured_copy_peak(reps: int = 5) -> float:
+    """HBM bandwidth a plain device copy reaches (1 GiB read + 1 GiB written), best of `reps`:
+    the measured peak beside the published 8 TB/s."""
+    import torch
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del x, y
+    return 2.0 * n * 8 / (best * 1e-3) / 1e9
+
+
+def condensation_report(names, warmup: int = 5, reps: int = 30):
+    """Assemble + condense time of each named workload (float64 path), with its roofline:
+    `warmup` untimed calls, then the median and p99 of `reps` individually timed calls."""
     import torch
     import hdg_inputs as hi
     import paper_1308_3995_amd as hdg
@@ -127,7 +149,7 @@ def condensation_report(names, reps: int = 10):
         w = torch.tensor(case.W, dtype=torch.float64, device=dev)
         q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
         lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
-        for _ in range(2):
+        for _ in range(warmup):
             plan.hdg_assemble_condense(w, lam, q=q)
         torch.cuda.synchronize()
         ts = []
@@ -139,11 +161,13 @@ def condensation_report(names, reps: int = 10):
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
         ms = float(np.median(ts))
+        p99 = float(np.percentile(ts, 99))
         fl, by = condensation_work(case)
         t_f = fl / (FP64_PEAK_TFLOPS * 1e12)
         t_b = by / (HBM_PEAK_GBS * 1e9)
         out[name] = {"workload": f"{case.physics} {case.ng}x{case.ng}, degrees {sorted(set(case.degree.tolist()))}",
-                     "elements": case.n_elements, "ms": ms, "elements_per_s": case.n_elements / (ms * 1e-3),
+                     "elements": case.n_elements, "ms": ms, "ms_p99": p99, "reps": reps,
+                     "elements_per_s": case.n_elements / (ms * 1e-3),
                      "algorithmic_gflop": fl / 1e9, "algorithmic_gb": by / 1e9,
                      "achieved_tflops": fl / (ms * 1e-3) / 1e12, "achieved_gbs": by / (ms * 1e-3) / 1e9,
                      "bound": "fp64" if t_f >= t_b else "hbm", "roofline_frac": max(t_f, t_b) / (ms * 1e-3)}
@@ -188,8 +212,8 @@ def newton_loop_report(name: str, rtol: float, restart: int, max_steps: int = 12
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -246,15 +270,18 @@ def main():
             it, rr = step()
             log(f"[bench] mode {mode}: warmup {i} gmres iters {it} relres {rr:.2e}")
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         iters = []
-        e0.record(stream)
+        ev[0].record(stream)
         for i in range(args.steps):
             it, rr = step()
             iters.append((it, rr))
-        e1.record(stream)
+            ev[i + 1].record(stream)
         torch.cuda.synchronize()
-        ms_step = e0.elapsed_time(e1) / args.steps
+        per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+        ms_step = ev[0].elapsed_time(ev[-1]) / args.steps
+        ms_med, ms_p99 = float(np.median(per_step)), float(np.percentile(per_step, 99))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         # the same step once more with every launch of the dominant kernel bracketed by HIP
         # events on its stream (direct launches: events are not recorded inside graph replays)
         plan.hdg_kernel_timing(reset=True)
@@ -263,7 +290,8 @@ def main():
         torch.cuda.synchronize()
         plan.hdg_set_kernel_timing(False)
         k_launches, k_ms, k_bytes = plan.hdg_kernel_timing(reset=True)
-        log(f"[bench] mode {mode}: {ms_step:.3f} ms/step, gmres iters {iters[-1][0]}, relres {iters[-1][1]:.2e}")
+        log(f"[bench] mode {mode}: {ms_step:.3f} ms/step (median {ms_med:.3f}, p99 {ms_p99:.3f}), "
+            f"gmres iters {iters[-1][0]}, relres {iters[-1][1]:.2e}")
         # condensation alone
         reps = max(5, args.steps)
         e0.record(stream)
@@ -273,7 +301,8 @@ def main():
         torch.cuda.synchronize()
         ms_cond = e0.elapsed_time(e1) / reps
         log(f"[bench] mode {mode}: assemble+condense {ms_cond:.3f} ms")
-        results[mode] = dict(ms_step=ms_step, ms_condense=ms_cond, gmres_iters=iters[-1][0],
+        results[mode] = dict(ms_step=ms_step, ms_median=ms_med, ms_p99=ms_p99, ms_condense=ms_cond,
+                             gmres_iters=iters[-1][0],
                              relres=iters[-1][1], n_skel=plan.n_skel, k_launches=k_launches, k_ms=k_ms,
                              k_bytes=k_bytes)
         log(f"[bench] mode {mode}: spmv+dots kernel {k_launches} launches, {k_ms / max(1, k_launches) * 1e3:.2f} us avg, "
@@ -300,12 +329,15 @@ def main():
         "config": {"workload": "2-D Euler HDG, uniform p=3, 64x64 jittered unit square (8192 triangles), "
                                "Mach 0.5, alpha 2 deg, perturbation 1e-2; one Newton step, GMRES(30) to 1e-10",
                    "elements": ne, "skeleton_dofs": r["n_skel"], "precision": main_mode},
-        "modes": {m: {"ms_per_step": v["ms_step"], "elements_per_s": ne / (v["ms_step"] / 1e3),
+        "modes": {m: {"ms_per_step": v["ms_step"], "ms_per_step_median": v["ms_median"],
+                      "ms_per_step_p99": v["ms_p99"], "elements_per_s": ne / (v["ms_step"] / 1e3),
                       "skeleton_dof_per_s": v["n_skel"] / (v["ms_step"] / 1e3),
                       "condense_ms": v["ms_condense"], "condensed_elements_per_s": ne / (v["ms_condense"] / 1e3),
                       "gmres_iters": v["gmres_iters"], "relres": v["relres"]} for m, v in results.items()},
     }
     kl, kms, kb = r["k_launches"], r["k_ms"], r["k_bytes"]
+    copy_peak = measured_copy_peak()
+    log(f"[bench] device copy reaches {copy_peak:.0f} GB/s (published peak {HBM_PEAK_GBS:.0f})")
     achieved = kb / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     out["roofline"] = {"kernel": "k_spmv_dots (preconditioned skeleton SpMV fused with the first Gram-Schmidt dots)",
                        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -314,6 +346,7 @@ def main():
                                                     "profiles/k_spmv_dots_c2_euler_p3_mixed_hbm_traffic.txt")
                                    if main_mode == "mixed" else None),
                        "traffic_unit": "bytes/launch",
+                       "peak_measured_copy": copy_peak, "frac_of_measured": achieved / copy_peak,
                        "launches": kl, "avg_launch_us": kms / max(1, kl) * 1e3,
                        "bytes_per_launch": kb / max(1, kl)}
     if args.condense_configs:
