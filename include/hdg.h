@@ -246,6 +246,37 @@ hdg_status hdg_pseudo_transient_solve(hdg_plan* plan, double* w_dev, double* q_d
                                       const hdg_newton_opts* opts, hdg_newton_report* report,
                                       double* res_history_host, double* cfl_history_host, hipStream_t stream);
 
+/* Hybridized adjoint (Sec. 4, eq. adjoint; Sec. 4.1). For a target functional J with
+ * derivative F~ = J'(x) in the element unknowns (the functional depends on w and q only, so
+ * its skeleton part is zero), the adjoint system [A_K B_K; C_K D_K]^T [U~; Lambda~] = [F~; 0]
+ * condenses, with the blocks of hdg_assemble_condense, to
+ *     K^T Lambda~ = E~,   E~ = -sum_K X_K^T F~_K,   U~_K = A_K^-T (F~_K - C_K^T Lambda~_K).
+ * The paper solves it in the space of degree p + 1; a plan built with every degree raised by
+ * one, on the primal state padded with zero modes, is that space.
+ *
+ * K^T in the block pattern of K (the pattern is symmetric): kt_values_dev[bsr_values] from
+ * bsr_values_dev. Solve K^T Lambda~ = E~ by passing kt_values_dev to hdg_skeleton_solve. */
+hdg_status hdg_skeleton_transpose(hdg_plan* plan, const double* bsr_values_dev, double* kt_values_dev,
+                                  hipStream_t stream);
+
+/* E~ = -sum_K X_K^T F~_K from the local store of the last hdg_assemble_condense:
+ * fw_dev (the w part of F~, padded w layout) and, for Navier-Stokes, fq_dev (the q part,
+ * padded q layout; NULL for Euler) -> etilde_dev[n_skel_dof]. Uses workspace_dev as scratch
+ * (the per-face slots of the condensed right-hand side). */
+hdg_status hdg_adjoint_rhs(hdg_plan* plan, const void* local_store_dev, const double* fw_dev, const double* fq_dev,
+                           double* etilde_dev, void* workspace_dev, hipStream_t stream);
+
+/* Local adjoint solves U~_K = A_K^-T (F~_K - C_K^T Lambda~_K) at the state (w_dev, lam_dev)
+ * (A_K is assembled again, with the plan's CFL, and eliminated transposed with partial
+ * pivoting), written to wt_dev in the padded w layout, and the element indicators of Sec. 4
+ * with the skeleton adjoint dropped, eta_dev[ne] = |U~_K . R_K(x)| (R_K the element's
+ * residual rows). Euler only: returns HDG_ERR_INVALID_ARG for a Navier-Stokes plan.
+ * elem_status_dev (optional, int32[ne]) as in hdg_assemble_condense; when given the call
+ * synchronises and returns the first failure. */
+hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* lam_dev, const double* fw_dev,
+                             const double* lamt_dev, double* wt_dev, double* eta_dev, void* workspace_dev,
+                             int32_t* elem_status_dev, hipStream_t stream);
+
 /* Inspection entry for tests: the uncondensed element blocks of one element in the
  * unknown order documented above (element: Navier-Stokes gradient fields 4d+a first,
  * then w fields, each mode-minor; faces: interior local faces in order, each

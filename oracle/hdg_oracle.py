@@ -20,6 +20,10 @@ What it computes, in the paper's order (Woopen, Balan, May, Schuetz, 2013):
   * Sec. 3.3, eq. cfl: the CFL schedule (smooth ramp, then growth by the
     residual reduction) and the relaxed Newton iteration it drives, with the
     residual norm ||N_h||_2 over every element and skeleton row;
+  * Sec. 4, eq. adjoint and Sec. 4.1: the adjoint of the Newton matrix, solved
+    directly and in hybridized form (K^T Lam~ = E~ and the transposed local
+    solves), the element indicators with the skeleton adjoint dropped, and the
+    enrichment to one degree more;
   * Sec. 3.4, eq. ls/cons/hybridsystem: static condensation
     S_K = D_K - C_K A_K^-1 B_K, g_K = r_lam,K - C_K A_K^-1 r_K, summed into the
     skeleton system K dLam = E, solved directly, then the element-wise
@@ -617,8 +621,9 @@ def newton_step(case, alpha: Optional[float] = None, elements=None) -> NewtonSte
     return NewtonStep(mesh, blocks, cond, K, E, dlam, du)
 
 
-def monolithic_solve(step: NewtonStep):
-    """Solve the un-condensed Newton system [[A, B], [C, D]] [dU; dLam] = [r; r_lam] directly."""
+def global_jacobian(step: NewtonStep):
+    """The un-condensed Newton matrix [[A, B], [C, D]] over all element unknowns (first) and
+    skeleton unknowns, and its right-hand side [r; r_lam]."""
     mesh = step.mesh
     nloc = int(mesh.elem_offset[-1])
     N = nloc + mesh.n_skel
@@ -638,9 +643,83 @@ def monolithic_solve(step: NewtonStep):
         np.add.at(rhs, sk, b.rl)
     J = scipy.sparse.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                                 shape=(N, N)).tocsc()
+    return J, rhs, nloc
+
+
+def monolithic_solve(step: NewtonStep):
+    """Solve the un-condensed Newton system [[A, B], [C, D]] [dU; dLam] = [r; r_lam] directly."""
+    mesh = step.mesh
+    J, rhs, nloc = global_jacobian(step)
     x = scipy.sparse.linalg.spsolve(J, rhs)
     du = [x[mesh.elem_offset[e]: mesh.elem_offset[e + 1]] for e in range(mesh.ne)]
     return du, x[nloc:]
+
+
+# ---------------------------------------------------------------------------
+# Adjoint (Sec. 4): eq. adjoint in matrix form and its hybridized form (Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def adjoint_monolithic(step: NewtonStep, F: List[np.ndarray]):
+    """The transposed Newton matrix [[A, B], [C, D]]^T [U~; Lam~] = [F~; 0], solved directly:
+    the functional depends on the element unknowns only, so its skeleton part is zero.
+    F: per element, the functional derivative in the element's unknown order."""
+    mesh = step.mesh
+    J, _, nloc = global_jacobian(step)
+    rhs = np.zeros(J.shape[0])
+    rhs[:nloc] = np.concatenate(F)
+    z = scipy.sparse.linalg.spsolve(J.T.tocsc(), rhs)
+    Ut = [z[mesh.elem_offset[e]: mesh.elem_offset[e + 1]] for e in range(mesh.ne)]
+    return Ut, z[nloc:]
+
+
+def adjoint_hybridized(step: NewtonStep, F: List[np.ndarray]):
+    """Static condensation of the adjoint system: K^T Lam~ = E~ with
+    E~ = -sum_K B_K^T A_K^-T F~_K = -sum_K X_K^T F~_K (X_K = A_K^-1 B_K), then the local
+    adjoint solves U~_K = A_K^-T (F~_K - C_K^T Lam~_K)."""
+    mesh = step.mesh
+    Et = np.zeros(mesh.n_skel)
+    for e, (b, c) in enumerate(zip(step.blocks, step.cond)):
+        d = elem_dofs(mesh, b)
+        if d.size:
+            np.add.at(Et, d, -(c.X.T @ F[e]))
+    lamt = solve_skeleton(step.K.T.tocsr(), Et)
+    Ut = []
+    for e, b in enumerate(step.blocks):
+        d = elem_dofs(mesh, b)
+        rhs = F[e] - (b.C.T @ lamt[d] if d.size else 0.0)
+        Ut.append(scipy.linalg.solve(b.A.T, rhs))
+    return Ut, lamt, Et
+
+
+def element_indicators(step: NewtonStep, Ut: List[np.ndarray]) -> np.ndarray:
+    """eta_K = |N_h(x_h; q~, w~, 0) restricted to K| (Sec. 4): the element's residual rows
+    R_K = -r_K weighted by its adjoint, the skeleton adjoint dropped."""
+    return np.array([abs(float(Ut[e] @ (-b.r))) for e, b in enumerate(step.blocks)])
+
+
+def enrich(case):
+    """The case in the space of one degree more (Sec. 4): every element degree raised by one,
+    the state padded with zero coefficients past each element's (face's) own degree (the
+    bases are hierarchical, so the padded state is the same function)."""
+    import dataclasses
+    p1 = int(case.degree.max()) + 1
+    npm = n_modes(p1)
+    fdeg = Mesh(case, make_physics(case)).face_degree
+
+    def pad_elems(a):
+        if a is None:
+            return None
+        out = np.zeros(a.shape[:-1] + (npm,))
+        for e in range(a.shape[0]):
+            n = n_modes(int(case.degree[e]))     # modes past the element's degree carry no meaning
+            out[e, :, :n] = a[e, :, :n]
+        return out
+
+    lam = np.zeros(case.lam.shape[:-1] + (p1 + 1,))
+    for f in range(lam.shape[0]):
+        lam[f, :, : fdeg[f] + 1] = case.lam[f, :, : fdeg[f] + 1]
+    return dataclasses.replace(case, degree=(case.degree + 1).astype(case.degree.dtype), W=pad_elems(case.W),
+                               Q=pad_elems(case.Q), lam=lam)
 
 
 def global_residual(case, W, lam, Q=None, alpha: Optional[float] = None):

@@ -174,6 +174,39 @@ class HDGPlan:
                     gmres_not_converged=int(rep.gmres_not_converged), res0=rep.res0, res=rep.res,
                     res_history=res[: n + 1].copy(), cfl_history=cfl[:n].copy())
 
+    # ---- hybridized adjoint
+    def hdg_skeleton_transpose(self, kt, stream=None):
+        """K^T of the last assembly into kt (same pattern and length as the skeleton matrix)."""
+        check(self.lib.hdg_skeleton_transpose(self.handle, _vp(self.bsr), _vp(kt), _stream(stream)))
+
+    def hdg_adjoint_rhs(self, fw, etilde, fq=None, stream=None):
+        check(self.lib.hdg_adjoint_rhs(self.handle, _vp(self.store), _vp(fw), _vp(fq), _vp(etilde), _vp(self.ws),
+                                       _stream(stream)))
+
+    def hdg_adjoint_local(self, w, lam, fw, lamt, wt, eta, elem_status=None, stream=None):
+        check(self.lib.hdg_adjoint_local(self.handle, _vp(w), _vp(lam), _vp(fw), _vp(lamt), _vp(wt), _vp(eta),
+                                         _vp(self.ws), _vp(elem_status), _stream(stream)))
+
+    def hdg_adjoint_solve(self, w, lam, fw, rtol: float = 1e-12, restart: int = 30, max_iter: int = 200000,
+                          stream=None):
+        """The whole hybridized adjoint at the state (w, lam) for the functional derivative fw
+        (Euler): returns (Lambda~, W~, eta, gmres iterations)."""
+        import torch
+        self.hdg_assemble_condense(w, lam, stream=stream)
+        kt = torch.empty_like(self.bsr)
+        self.hdg_skeleton_transpose(kt, stream=stream)
+        et = torch.empty(max(1, self.n_skel), dtype=torch.float64, device=self.device)
+        self.hdg_adjoint_rhs(fw, et, stream=stream)
+        lamt = torch.zeros_like(et)
+        it = C.c_int32(0)
+        rr = C.c_double(0.0)
+        check(self.lib.hdg_skeleton_solve(self.handle, _vp(kt), _vp(et), _vp(lamt), rtol, restart, max_iter,
+                                          _vp(self.ws), _stream(stream), C.byref(it), C.byref(rr)))
+        wt = torch.zeros_like(w)
+        eta = torch.zeros(self.ne, dtype=torch.float64, device=self.device)
+        self.hdg_adjoint_local(w, lam, fw, lamt, wt, eta, stream=stream)
+        return lamt, wt, eta, it.value
+
     # ---- dominant-kernel timing (benchmarks)
     def hdg_set_kernel_timing(self, enable: bool):
         check(self.lib.hdg_set_kernel_timing(self.handle, 1 if enable else 0))
@@ -208,10 +241,11 @@ class HDGPlan:
         n, f = no.value, fo.value
         return X[: n * f].reshape(f, n).T, y[:n].copy()
 
-    def skeleton_matrix_dense(self) -> np.ndarray:
-        """Dense copy of the assembled skeleton matrix (small meshes only)."""
+    def skeleton_matrix_dense(self, values=None) -> np.ndarray:
+        """Dense copy of the assembled skeleton matrix, or of other values in its block pattern
+        (small meshes only)."""
         rp, col, voff = self.pattern()
-        vals = self.bsr.cpu().numpy()
+        vals = (self.bsr if values is None else values).cpu().numpy()
         K = np.zeros((self.n_skel, self.n_skel))
         for f in range(len(self.face_degree)):
             sf = self.face_offset[f + 1] - self.face_offset[f]

@@ -20,7 +20,8 @@ HDG_FP64, HDG_MIXED = 0, 1
 EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_pattern", "hdg_assemble_condense",
            "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
            "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_set_cfl", "hdg_residual_norm", "hdg_apply_update",
-           "hdg_cfl_schedule", "hdg_pseudo_transient_solve", "hdg_last_error", "hdg_plan_destroy"]
+           "hdg_cfl_schedule", "hdg_pseudo_transient_solve", "hdg_skeleton_transpose", "hdg_adjoint_rhs",
+           "hdg_adjoint_local", "hdg_last_error", "hdg_plan_destroy"]
 
 
 class HdgParams(C.Structure):
@@ -83,6 +84,9 @@ def load(path: str = LIB_PATH):
     lib.hdg_cfl_schedule.restype = dbl
     lib.hdg_pseudo_transient_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(HdgNewtonOpts),
                                                P(HdgNewtonReport), vp, vp, vp]
+    lib.hdg_skeleton_transpose.argtypes = [vp, vp, vp, vp]
+    lib.hdg_adjoint_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_adjoint_local.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_last_error.argtypes = []
     lib.hdg_last_error.restype = C.c_char_p
     lib.hdg_plan_destroy.argtypes = [vp]

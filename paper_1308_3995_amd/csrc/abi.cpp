@@ -482,6 +482,69 @@ hdg_status hdg_pseudo_transient_solve(hdg_plan* plan, double* w_dev, double* q_d
     return HDG_OK;
 }
 
+hdg_status hdg_skeleton_transpose(hdg_plan* plan, const double* bsr_values_dev, double* kt_values_dev,
+                                  hipStream_t stream) {
+    if (!plan || !bsr_values_dev || !kt_values_dev || bsr_values_dev == kt_values_dev) {
+        set_error("hdg_skeleton_transpose: null argument or in-place call");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    CHECK_HIP(hipSetDevice(p.device));
+    CHECK_HIP(launch_skeleton_transpose(p, bsr_values_dev, kt_values_dev, stream));
+    return HDG_OK;
+}
+
+hdg_status hdg_adjoint_rhs(hdg_plan* plan, const void* local_store_dev, const double* fw_dev, const double* fq_dev,
+                           double* etilde_dev, void* workspace_dev, hipStream_t stream) {
+    if (!plan || !local_store_dev || !fw_dev || !etilde_dev || !workspace_dev) {
+        set_error("hdg_adjoint_rhs: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (p.ns && !fq_dev) {
+        set_error("hdg_adjoint_rhs: Navier-Stokes needs the q part of the functional derivative");
+        return HDG_ERR_INVALID_ARG;
+    }
+    char* ws = (char*)workspace_dev;
+    CHECK_HIP(hipSetDevice(p.device));
+    hipError_t e = launch_adjoint_rhs(p, (const double*)local_store_dev, fw_dev, fq_dev, (double*)(ws + p.ws_g_part),
+                                      etilde_dev, stream);
+    if (e == hipErrorInvalidValue) {
+        set_error("hdg_adjoint_rhs: element degree outside the built kernels");
+        return HDG_ERR_INVALID_ARG;
+    }
+    CHECK_HIP(e);
+    return HDG_OK;
+}
+
+hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* lam_dev, const double* fw_dev,
+                             const double* lamt_dev, double* wt_dev, double* eta_dev, void* workspace_dev,
+                             int32_t* elem_status_dev, hipStream_t stream) {
+    if (!plan || !w_dev || !lam_dev || !fw_dev || !lamt_dev || !wt_dev || !eta_dev || !workspace_dev) {
+        set_error("hdg_adjoint_local: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    if (p.ns) {
+        set_error("hdg_adjoint_local: the local adjoint solve is built for the Euler equations only");
+        return HDG_ERR_INVALID_ARG;
+    }
+    char* ws = (char*)workspace_dev;
+    int32_t* status = elem_status_dev ? elem_status_dev : (int32_t*)(ws + p.ws_status);
+    int32_t* flag = (int32_t*)(ws + p.ws_status) + p.ne;
+    CHECK_HIP(hipSetDevice(p.device));
+    hipError_t e = launch_clear_status(p, status, flag, stream);
+    if (e == hipSuccess) e = launch_adjoint_local(p, w_dev, lam_dev, fw_dev, lamt_dev, wt_dev, eta_dev, status, flag,
+                                                 stream);
+    if (e == hipErrorInvalidValue) {
+        set_error("hdg_adjoint_local: element degree outside the built kernels");
+        return HDG_ERR_INVALID_ARG;
+    }
+    CHECK_HIP(e);
+    if (elem_status_dev) return check_status(p, status, flag, stream);
+    return HDG_OK;
+}
+
 hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const double* w_dev, const double* q_dev,
                                     const double* lam_dev, double* A_host, double* B_host, double* C_host,
                                     double* D_host, double* r_host, double* rl_host, int32_t* n_out, int32_t* f_out) {

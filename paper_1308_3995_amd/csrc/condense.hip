@@ -40,6 +40,10 @@ struct CondArgs {
     double* g_part;
     double* res_elem;     // [ne] squared norm of each element's residual rows (may be null)
     double* rl_part;      // skeleton residual shares, g_part's slots (may be null)
+    const double* fw;     // adjoint: functional derivative F~ in the padded w layout
+    const double* lamt;   // adjoint: skeleton adjoint Lambda~
+    double* wt;           // adjoint: element adjoint W~ (padded w layout)
+    double* eta;          // adjoint: [ne] element indicators
     double* store;        // bucket store base
     int32_t* status;      // [ne] per-element status
     int32_t* flag;        // set to 1 when any element reports a failure
@@ -340,6 +344,61 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
     }
 }
 
+// Entries A_K[(fa, ii)][(b, j0 + j)], j < NPW, of one row of the element matrix (eq. hdg_ls2
+// linearised): volume term from the weighted flux Jacobians, face terms from the trace-flux
+// Jacobians in w, and the pseudo-time shift sig on the diagonal. Columns past Np stay zero.
+// sVg: basis gradients [r][q][i]; sFp: the element's basis at its face points [lf][g][i].
+template <int P, int PF, int NPW>
+__device__ __forceinline__ void a_row_entries(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
+                                              const double* sVg, const double* sFp, int fa, int ii, int b, int j0,
+                                              double sig, double (&out)[NPW]) {
+    constexpr int NP = n_modes(P), Q = n_vol_q(P), QF = PF + 2;
+#pragma unroll
+    for (int j = 0; j < NPW; ++j) out[j] = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
+        const double s = -(g0 * sh.sK[q][0][fa * 4 + b] + g1 * sh.sK[q][1][fa * 4 + b]);
+#pragma unroll
+        for (int j = 0; j < NPW; ++j)
+            if (j0 + j < NP) out[j] += s * a.vphi[q * NP + j0 + j];
+    }
+#pragma unroll
+    for (int lf = 0; lf < 3; ++lf) {
+        const int nq = E->pe[lf] + 2;
+        const double* fp = sFp + lf * QF * NP;
+        for (int g = 0; g < nq; ++g) {
+            const double t = fp[g * NP + ii] * sh.sJA[lf][g][fa * 4 + b];
+#pragma unroll
+            for (int j = 0; j < NPW; ++j)
+                if (j0 + j < NP) out[j] += t * fp[g * NP + j0 + j];
+        }
+    }
+    // pseudo-time mass term on the diagonal of the field's own block
+    if (fa == b) {
+#pragma unroll
+        for (int j = 0; j < NPW; ++j)
+            if (j0 + j == ii) out[j] += sig;
+    }
+}
+
+// Entry (fa, ii) of the element right-hand side r_K = -R_K (eq. hdg_ls2).
+template <int P, int PF>
+__device__ __forceinline__ double r_entry(const ElemInfo* E, const ElemShared<P, PF>& sh, const double* sVg,
+                                          const double* sFp, int fa, int ii) {
+    constexpr int NP = n_modes(P), Q = n_vol_q(P), QF = PF + 2;
+    double v = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
+        v += g0 * sh.sF[q][0][fa] + g1 * sh.sF[q][1][fa];
+    }
+#pragma unroll
+    for (int l2 = 0; l2 < 3; ++l2) {
+        const double* fp = sFp + l2 * QF * NP;
+        for (int g = 0; g < E->pe[l2] + 2; ++g) v -= fp[g * NP + ii] * sh.sFH[l2][g][fa];
+    }
+    return v;
+}
+
 template <int P>
 struct EulerShape {
     static constexpr int N = 4 * n_modes(P);
@@ -396,11 +455,7 @@ void k_condense_euler(CondArgs a) {
     }
     face_tables<P, PF>(a, E, sh, sFp, ft, tid, NTH);
     __syncthreads();
-    const auto& sK = sh.sK;
-    const auto& sF = sh.sF;
-    const auto& sJA = sh.sJA;
     const auto& sJB = sh.sJB;
-    const auto& sFH = sh.sFH;
     const int fld = wave / WPF, part = wave % WPF;
     double sig;
     {
@@ -416,37 +471,8 @@ void k_condense_euler(CondArgs a) {
         const int row = h * 64 + lane;
         const int rr = row < N ? row : N - 1;
         const int fa = rr / NP, ii = rr % NP;
-        // ---- A_K columns (field fld, modes part NPW + jj): volume and face terms (eq. hdg_ls2
-        // linearised); columns past Np are padding and stay zero
-#pragma unroll
-        for (int j = 0; j < NPW; ++j) mA[h][j] = 0.0;
-        {
-            const int b = fld, j0 = part * NPW;
-            for (int q = 0; q < Q; ++q) {
-                const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
-                const double s = -(g0 * sK[q][0][fa * 4 + b] + g1 * sK[q][1][fa * 4 + b]);
-#pragma unroll
-                for (int j = 0; j < NPW; ++j)
-                    if (j0 + j < NP) mA[h][j] += s * a.vphi[q * NP + j0 + j];
-            }
-#pragma unroll
-            for (int lf = 0; lf < 3; ++lf) {
-                const int nq = E->pe[lf] + 2;
-                const double* fp = sFp + lf * QF * NP;
-                for (int g = 0; g < nq; ++g) {
-                    const double t = fp[g * NP + ii] * sJA[lf][g][fa * 4 + b];
-#pragma unroll
-                    for (int j = 0; j < NPW; ++j)
-                        if (j0 + j < NP) mA[h][j] += t * fp[g * NP + j0 + j];
-                }
-            }
-            // pseudo-time mass term on the diagonal of the field's own block
-            if (fa == b) {
-#pragma unroll
-                for (int j = 0; j < NPW; ++j)
-                    if (j0 + j == ii) mA[h][j] += sig;
-            }
-        }
+        // ---- A_K columns (field fld, modes part NPW + jj); columns past Np are padding
+        a_row_entries<P, PF, NPW>(a, E, sh, sVg, sFp, fa, ii, fld, part * NPW, sig, mA[h]);
         // ---- B_K / r_K columns cb = wave * NBW + i (cb < F: face lf, field b, mode k; cb = F: r_K)
 #pragma unroll
         for (int i = 0; i < NBW; ++i) {
@@ -460,15 +486,7 @@ void k_condense_euler(CondArgs a) {
                     for (int g = 0; g < pe + 2; ++g) v += fp[g * NP + ii] * sJB[lf][g][fa * 4 + b] * ft.ps[lf][g][k];
                 }
             } else if (cb == F) {
-                for (int q = 0; q < Q; ++q) {
-                    const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
-                    v += g0 * sF[q][0][fa] + g1 * sF[q][1][fa];
-                }
-#pragma unroll
-                for (int l2 = 0; l2 < 3; ++l2) {
-                    const double* fp = sFp + l2 * QF * NP;
-                    for (int g = 0; g < E->pe[l2] + 2; ++g) v -= fp[g * NP + ii] * sFH[l2][g][fa];
-                }
+                v = r_entry<P, PF>(E, sh, sVg, sFp, fa, ii);
             }
             mB[h][i] = v;
         }
@@ -744,6 +762,272 @@ hipError_t launch_back_substitute(const Plan& p, const double* store, const doub
             hipLaunchKernelGGL((k_backsub<PP, FF, 4>), dim3(bk.count), dim3(64), 0, s, p.d_einfo, bk.start,      \
                                store + bk.store_off, p.d_face_off, dlam, dw, dq, p.npmax);                      \
         }                                                                                                       \
+        continue;                                                                                               \
+    }
+        HDG_BUCKETS(HDG_CASE)
+#undef HDG_CASE
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Hybridized adjoint (Sec. 4.1). With the local blocks of the condensation the adjoint
+// system [A_K B_K; C_K D_K]^T [U~; Lambda~] = [F~; 0] condenses to
+//   K^T Lambda~ = E~,   E~ = -sum_K X_K^T F~_K   (X_K = A_K^-1 B_K from the local store),
+//   U~_K = A_K^-T (F~_K - C_K^T Lambda~_K).
+// ---------------------------------------------------------------------------
+
+// K^T in the pattern of K: block (f, g) of K^T is block (g, f) of K transposed. One
+// workgroup per block.
+__global__ __launch_bounds__(256) void k_bsr_transpose(const int32_t* blk_row, const int32_t* col,
+                                                       const int64_t* val_off, const int64_t* mirror,
+                                                       const int64_t* face_off, const double* k, double* kt) {
+    const int64_t b = blockIdx.x;
+    const int f = blk_row[b], g = col[b];
+    const int64_t sf = face_off[f + 1] - face_off[f], sg = face_off[g + 1] - face_off[g];
+    const double* src = k + val_off[mirror[b]];   // s_g x s_f, column-major
+    double* dst = kt + val_off[b];                // s_f x s_g, column-major
+    for (int64_t t = threadIdx.x; t < sf * sg; t += blockDim.x) {
+        const int64_t i = t % sf, j = t / sf;
+        dst[j * sf + i] = src[i * sg + j];
+    }
+}
+
+// -X_K^T F~_K for the element's interior-face columns into the per-face slots of its side.
+// One wave per element; F~_K in LDS.
+template <int P, int PF, int MLOC>
+__global__ __launch_bounds__(64) void k_adjoint_rhs(const ElemInfo* einfo, int start, const double* store,
+                                                    const int64_t* face_off, const double* fw, const double* fq,
+                                                    double* part, int npmax) {
+    constexpr int NP = n_modes(P), NALL = MLOC * NP, NPF = PF + 1, F = 12 * NPF;
+    constexpr int WOFF = (MLOC - 4) * NP;   // first conserved-field row
+    __shared__ double sF[NALL];
+    const int lane = threadIdx.x;
+    const ElemInfo* E = einfo + start + blockIdx.x;
+    const int e = E->elem;
+    for (int r = lane; r < NALL; r += 64) {
+        if (r >= WOFF) {
+            const int t = r - WOFF;
+            sF[r] = fw[((int64_t)e * 4 + t / NP) * npmax + t % NP];
+        } else {
+            sF[r] = fq[((int64_t)e * 8 + r / NP) * npmax + r % NP];
+        }
+    }
+    __syncthreads();
+    const double* st = store + (int64_t)blockIdx.x * ((F + 1) * NALL);
+    for (int c = lane; c < F; c += 64) {
+        const int lf = c / (4 * NPF), b = (c / NPF) % 4, k = c % NPF;
+        const int f = E->face[lf], pe = E->pe[lf];
+        if (f < 0 || k > pe) continue;
+        double v = 0.0;
+        for (int r = 0; r < NALL; ++r) v += st[(int64_t)c * NALL + r] * sF[r];
+        part[2 * face_off[f] + (int64_t)E->side[lf] * 4 * (pe + 1) + b * (pe + 1) + k] = -v;
+    }
+}
+
+// Sum of the two sides' shares of every face, in a fixed order.
+__global__ void k_pair_sum(int nf, const int64_t* face_off, const double* part, double* out) {
+    const int f = blockIdx.x;
+    if (f >= nf) return;
+    const int64_t o = face_off[f], s = face_off[f + 1] - o;
+    for (int64_t t = threadIdx.x; t < s; t += blockDim.x) out[o + t] = part[2 * o + t] + part[2 * o + s + t];
+}
+
+// Local adjoint solve of one Euler element: A_K is assembled as in the condensation,
+// transposed through LDS, and [A_K^T | F~_K - C_K^T Lambda~_K] is eliminated with the same
+// pivoted Gauss-Jordan. Also the element indicator of Sec. 4 with the skeleton adjoint
+// dropped: eta_K = |U~_K . R_K(x)| = |U~_K . r_K|.
+template <int P, int PF>
+__global__ __launch_bounds__(64 * EulerShape<P>::NW) void k_adjoint_euler(CondArgs a) {
+    constexpr int NP = n_modes(P);
+    constexpr int N = 4 * NP;
+    constexpr int NPF = PF + 1;
+    constexpr int RH = EulerShape<P>::RH;
+    constexpr int WPF = EulerShape<P>::WPF;
+    constexpr int NW = EulerShape<P>::NW;
+    constexpr int NTH = 64 * NW;
+    constexpr int NPW = (NP + WPF - 1) / WPF;
+    constexpr int Q = n_vol_q(P);
+    constexpr int QF = PF + 2;
+    constexpr int STAGE = 2 * Q * NP + 3 * QF * NP;
+    constexpr int SA = STAGE > N * N ? STAGE : N * N;
+
+    __shared__ ElemShared<P, PF> sh;
+    __shared__ FaceTables<P, PF> ft;
+    __shared__ double sT[SA];          // reference tables, then A_K column-major
+    __shared__ double sFm[2][64 * RH];
+    __shared__ double sPVk[N];
+    __shared__ double sR[N];           // r_K
+    __shared__ double sRhs[N];         // F~_K - C_K^T Lambda~_K, later U~_K
+    __shared__ double sLt[3][4][NPF];
+    __shared__ int sPiv[2];
+    __shared__ int sBad;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int slot = a.start + blockIdx.x;
+    const ElemInfo* E = a.einfo + slot;
+    const int e = E->elem;
+    if (tid == 0) sBad = 0;
+    point_data<P, PF>(a, E, sh, tid, NTH);
+    double* sVg = sT;
+    double* sFp = sT + 2 * Q * NP;
+    for (int t = tid; t < 2 * Q * NP; t += NTH) sVg[t] = a.vgrad[t];
+    for (int t = tid; t < 3 * QF * NP; t += NTH) {
+        const int lf = t / (QF * NP), g = (t / NP) % QF, i = t % NP;
+        const int nq = E->pe[lf] + 2;
+        sFp[t] = g < nq ? a.fphi[face_phi_index(NP, lf, E->orient[lf], nq, g, i)] : 0.0;
+    }
+    for (int t = tid; t < 12 * NPF; t += NTH) {
+        const int lf = t / (4 * NPF), fa = (t / NPF) % 4, k = t % NPF;
+        const int f = E->face[lf], pe = E->pe[lf];
+        sLt[lf][fa][k] = (f >= 0 && k <= pe) ? a.lamt[a.face_off[f] + fa * (pe + 1) + k] : 0.0;
+    }
+    face_tables<P, PF>(a, E, sh, sFp, ft, tid, NTH);
+    __syncthreads();
+    double sig;
+    {
+        double wbar[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) wbar[f] = sh.sW[f * NP] * a.vphi[0];
+        sig = pseudo_time_shift(E, wbar, a.cfl, a.gamma, 0.0);
+    }
+    // r_K and the right-hand side; C_K = alpha T acts field by field (trace mass)
+    for (int r = tid; r < N; r += NTH) {
+        const int fa = r / NP, ii = r % NP;
+        sR[r] = r_entry<P, PF>(E, sh, sVg, sFp, fa, ii);
+        double ct = 0.0;
+#pragma unroll
+        for (int lf = 0; lf < 3; ++lf)
+#pragma unroll
+            for (int k = 0; k < NPF; ++k) ct += ft.T[lf][k][ii] * sLt[lf][fa][k];
+        sRhs[r] = a.fw[((int64_t)e * 4 + fa) * a.npmax + ii] - a.alpha * ct;
+    }
+    const int fld = wave / WPF, part = wave % WPF;
+    double mA[RH][NPW], mB[RH][1];
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        const int row = h * 64 + lane;
+        const int rr = row < N ? row : N - 1;
+        a_row_entries<P, PF, NPW>(a, E, sh, sVg, sFp, rr / NP, rr % NP, fld, part * NPW, sig, mA[h]);
+    }
+    __syncthreads();   // the tables in sT are no longer read
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        const int row = h * 64 + lane;
+        if (row < N)
+#pragma unroll
+            for (int j = 0; j < NPW; ++j)
+                if (part * NPW + j < NP) sT[(fld * NP + part * NPW + j) * N + row] = mA[h][j];
+    }
+    __syncthreads();
+    // rows of A_K^T: A_K^T[row][col] = A_K[col][row]
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        const int row = h * 64 + lane;
+        const int rr = row < N ? row : N - 1;
+#pragma unroll
+        for (int j = 0; j < NPW; ++j)
+            mA[h][j] = part * NPW + j < NP ? sT[rr * N + fld * NP + part * NPW + j] : 0.0;
+        mB[h][0] = wave == 0 ? sRhs[rr] : 0.0;
+    }
+    int mykk[RH];
+    gj_eliminate<NP, 1, RH, WPF>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int h = 0; h < RH; ++h) {
+            if (h * 64 + lane >= N) continue;
+            const int kk = mykk[h];
+            const double pv = sPVk[kk];
+            const double x = mB[h][0] / pv;
+            sRhs[kk] = x;
+            if (!(fabs(pv) > 0.0)) sBad = 1;
+            else if (!isfinite(x) && sBad == 0) sBad = 2;
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < 4 * a.npmax; t += NTH) {
+        const int fa = t / a.npmax, i = t % a.npmax;
+        a.wt[(int64_t)e * 4 * a.npmax + t] = i < NP ? sRhs[fa * NP + i] : 0.0;
+    }
+    if (wave == 0) {
+        double s = 0.0;
+        for (int r = lane; r < N; r += 64) s += sRhs[r] * sR[r];
+        s = wave_sum_f64(s);
+        if (lane == 0) a.eta[e] = fabs(s);
+    }
+    if (tid == 0 && sBad != 0) {
+        a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+        a.flag[0] = 1;
+    }
+}
+
+hipError_t launch_skeleton_transpose(const Plan& p, const double* k, double* kt, hipStream_t s) {
+    const int64_t nb = (int64_t)p.col.size();
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsr_transpose, dim3((unsigned)nb), dim3(256), 0, s, p.d_blk_row, p.d_col, p.d_val_off,
+                       p.d_blk_mirror, p.d_face_off, k, kt);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_rhs(const Plan& p, const double* store, const double* fw, const double* fq, double* part,
+                              double* etilde, hipStream_t s) {
+    for (const Bucket& bk : p.buckets) {
+        if (!bucket_supported(bk)) return hipErrorInvalidValue;
+        const double* st = store + bk.store_off;
+#define HDG_CASE(PP, FF)                                                                                        \
+    if (bk.p == PP && bk.pf == FF) {                                                                            \
+        if (p.ns) {                                                                                             \
+            if constexpr (PP <= 4 && FF <= 4)                                                                   \
+                hipLaunchKernelGGL((k_adjoint_rhs<PP, FF, 12>), dim3(bk.count), dim3(64), 0, s, p.d_einfo,      \
+                                   bk.start, st, p.d_face_off, fw, fq, part, p.npmax);                          \
+        } else {                                                                                                \
+            hipLaunchKernelGGL((k_adjoint_rhs<PP, FF, 4>), dim3(bk.count), dim3(64), 0, s, p.d_einfo, bk.start,  \
+                               st, p.d_face_off, fw, fq, part, p.npmax);                                        \
+        }                                                                                                       \
+        continue;                                                                                               \
+    }
+        HDG_BUCKETS(HDG_CASE)
+#undef HDG_CASE
+    }
+    if (p.nf > 0) hipLaunchKernelGGL(k_pair_sum, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, part, etilde);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_local(Plan& p, const double* w, const double* lam, const double* fw, const double* lamt,
+                                double* wt, double* eta, int32_t* status, int32_t* flag, hipStream_t s) {
+    if (p.ns) return hipErrorNotSupported;
+    CondArgs a{};
+    a.einfo = p.d_einfo;
+    a.leg = p.d_tab + p.tix.leg;
+    a.gw = p.d_tab + p.tix.gw;
+    a.bproj = p.d_bproj;
+    a.face_off = p.d_face_off;
+    a.diag_off = p.d_diag_off;
+    a.w = w;
+    a.lam = lam;
+    a.fw = fw;
+    a.lamt = lamt;
+    a.wt = wt;
+    a.eta = eta;
+    a.status = status;
+    a.flag = flag;
+    a.npmax = p.npmax;
+    a.ne = p.ne;
+    for (int i = 0; i < 4; ++i) a.winf[i] = p.winf[i];
+    a.alpha = p.alpha;
+    a.gamma = p.prm.gamma;
+    a.cfl = p.prm.cfl;
+    for (const Bucket& bk : p.buckets) {
+        if (!bucket_supported(bk)) return hipErrorInvalidValue;
+#define HDG_CASE(PP, FF)                                                                                        \
+    if (bk.p == PP && bk.pf == FF) {                                                                            \
+        a.vphi = p.d_tab + p.tix.vol_phi[PP];                                                                   \
+        a.vgrad = p.d_tab + p.tix.vol_grad[PP];                                                                 \
+        a.vw = p.d_tab + p.tix.vol_w[PP];                                                                       \
+        a.fphi = p.d_tab + p.tix.face_phi[PP];                                                                  \
+        a.start = bk.start;                                                                                     \
+        hipLaunchKernelGGL((k_adjoint_euler<PP, FF>), dim3(bk.count), dim3(64 * EulerShape<PP>::NW), 0, s, a);  \
         continue;                                                                                               \
     }
         HDG_BUCKETS(HDG_CASE)

@@ -80,6 +80,8 @@ struct Plan {
     std::vector<int64_t> row_ptr;         // [nf+1] blocks per face row
     std::vector<int32_t> col;             // [nblk]
     std::vector<int64_t> val_off;         // [nblk+1]
+    std::vector<int32_t> blk_row;         // [nblk] face row of each block
+    std::vector<int64_t> blk_mirror;      // [nblk] index of the transposed block
     std::vector<int64_t> diag_off;        // [nf+1] offsets of the two diagonal parts (2 s^2 each)
     std::vector<ElemInfo> einfo;          // bucket order
     std::vector<int32_t> slot_of_elem;    // [ne]
@@ -105,6 +107,8 @@ struct Plan {
     int32_t* d_face_deg = nullptr;
     int64_t* d_row_ptr = nullptr;
     int32_t* d_col = nullptr;
+    int32_t* d_blk_row = nullptr;         // face row of every block
+    int64_t* d_blk_mirror = nullptr;      // block (g, f) of every block (f, g)
     int64_t* d_val_off = nullptr;
     int64_t* d_diag_off = nullptr;
     int64_t* d_hat_row_ptr = nullptr;
@@ -172,6 +176,14 @@ hipError_t launch_residual_norm(const Plan& p, const double* res_elem, const dou
                                 double* out_dev, hipStream_t s);
 // x += dx over n doubles.
 hipError_t launch_axpy_update(int64_t n, double* x, const double* dx, hipStream_t s);
+// Hybridized adjoint (condense.hip): K^T in the pattern of K; the shares -X_K^T F~_K into
+// part (the slots of the condensed right-hand side) summed per face into etilde; the local
+// adjoint solves and indicators (Euler).
+hipError_t launch_skeleton_transpose(const Plan& p, const double* k, double* kt, hipStream_t s);
+hipError_t launch_adjoint_rhs(const Plan& p, const double* store, const double* fw, const double* fq, double* part,
+                              double* etilde, hipStream_t s);
+hipError_t launch_adjoint_local(Plan& p, const double* w, const double* lam, const double* fw, const double* lamt,
+                                double* wt, double* eta, int32_t* status, int32_t* flag, hipStream_t s);
 int64_t ns_workspace_per_element(int p, int pf);   // Z, L, R of one element (block inspection)
 int64_t ns_chunk_per_element(int p, int pf);       // reduced system and factors (product path)
 hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol,

@@ -357,6 +357,21 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     }
     P.bsr_values = P.val_off.back();
     P.hat_values = P.hat_val_off.back();
+    // transposition map of the block pattern, which is symmetric: block (f, g) <-> block (g, f)
+    P.blk_row.assign(P.col.size(), 0);
+    P.blk_mirror.assign(P.col.size(), -1);
+    for (int f = 0; f < P.nf; ++f)
+        for (int64_t b = P.row_ptr[f]; b < P.row_ptr[f + 1]; ++b) P.blk_row[b] = f;
+    for (int f = 0; f < P.nf; ++f)
+        for (int64_t b = P.row_ptr[f]; b < P.row_ptr[f + 1]; ++b) {
+            const int g2 = P.col[b];
+            for (int64_t b2 = P.row_ptr[g2]; b2 < P.row_ptr[g2 + 1]; ++b2)
+                if (P.col[b2] == f) P.blk_mirror[b] = b2;
+            if (P.blk_mirror[b] < 0) {
+                set_error("internal: skeleton block pattern is not symmetric");
+                return HDG_ERR_INVALID_ARG;
+            }
+        }
     // row slabs: value base of each row and the gather index of every slab column
     auto slabs = [&](const std::vector<int64_t>& rp, const std::vector<int32_t>& cl, const std::vector<int64_t>& vo,
                      std::vector<int64_t>& rowbase, std::vector<int64_t>& colbase, std::vector<int32_t>& xidx) {
@@ -528,6 +543,8 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     if (err == hipSuccess) err = upload(&P.d_face_deg, P.face_deg, up);
     if (err == hipSuccess) err = upload(&P.d_row_ptr, P.row_ptr, up);
     if (err == hipSuccess) err = upload(&P.d_col, P.col, up);
+    if (err == hipSuccess) err = upload(&P.d_blk_row, P.blk_row, up);
+    if (err == hipSuccess) err = upload(&P.d_blk_mirror, P.blk_mirror, up);
     if (err == hipSuccess) err = upload(&P.d_val_off, P.val_off, up);
     if (err == hipSuccess) err = upload(&P.d_diag_off, P.diag_off, up);
     if (err == hipSuccess) err = upload(&P.d_hat_row_ptr, P.hat_row_ptr, up);
@@ -572,7 +589,7 @@ void free_plan(Plan& P) {
     void* ptrs[] = {P.d_einfo, P.d_tab, P.d_bproj, P.d_face_off, P.d_face_deg, P.d_row_ptr, P.d_col,
                     P.d_val_off, P.d_diag_off, P.d_hat_row_ptr, P.d_hat_col, P.d_hat_val_off, P.d_hat_src,
                     P.d_k_rowbase, P.d_k_colbase, P.d_k_xidx, P.d_hat_rowbase, P.d_hat_colbase, P.d_hat_xidx,
-                    P.d_kb_rows};
+                    P.d_kb_rows, P.d_blk_row, P.d_blk_mirror};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }

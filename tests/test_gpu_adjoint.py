@@ -1,0 +1,138 @@
+"""GPU parity of the hybridized adjoint (Sec. 4.1): K^T, the adjoint right-hand side
+E~ = -sum X_K^T F~_K, the local adjoint solves with the element indicators, and the whole
+adjoint solve, against the oracle on the same seeded inputs (functional derivatives drawn
+from a seeded generator)."""
+import sys
+
+import numpy as np
+import pytest
+
+import hdg_inputs as hi
+from oracle import hdg_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _case(which):
+    if which == "c1":
+        return hi.config_case("c1")
+    if which == "c1_enriched":          # the space of one degree more, as the paper solves the adjoint
+        return O.enrich(hi.config_case("c1"))
+    if which == "hp":
+        return hi.make_case("euler", 4, [1, 2, 3, 4], 0.6, 1.5, 2e-2, seed=3)
+    return hi.make_case("ns", 3, [2, 3], 0.5, 1.0, 2e-2, seed=21, reynolds=200.0)
+
+
+def _functional(step, case, seed=6):
+    """Seeded F~ per element in the oracle's unknown order, and the same in the padded layouts."""
+    rng = np.random.default_rng(seed)
+    F = [rng.standard_normal(b.A.shape[0]) for b in step.blocks]
+    npm = case.W.shape[2]
+    fw = np.zeros((case.n_elements, 4, npm))
+    fq = np.zeros((case.n_elements, 8, npm)) if case.physics == "ns" else None
+    for e in range(case.n_elements):
+        npe = hi.n_modes(int(case.degree[e]))
+        if fq is not None:
+            fq[e, :, :npe] = F[e][: 8 * npe].reshape(8, npe)
+            fw[e, :, :npe] = F[e][8 * npe:].reshape(4, npe)
+        else:
+            fw[e, :, :npe] = F[e].reshape(4, npe)
+    return F, fw, fq
+
+
+def _setup(hdg, which):
+    import torch
+    case = _case(which)
+    step = O.newton_step(case)
+    F, fw, fq = _functional(step, case)
+    plan = hdg.HDGPlan.from_case(case)
+    dev = plan.device
+    w = torch.tensor(case.W, dtype=torch.float64, device=dev)
+    lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
+    q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
+    fw_d = torch.tensor(fw, device=dev)
+    fq_d = torch.tensor(fq, device=dev) if fq is not None else None
+    plan.hdg_assemble_condense(w, lam, q=q)
+    return case, step, F, plan, w, lam, q, fw_d, fq_d
+
+
+@pytest.mark.parametrize("which", ["c1", "hp", "ns23"])
+def test_transpose_and_adjoint_rhs_match_oracle(hdg, which):
+    import torch
+    _say(f"adjoint rhs {which}")
+    case, step, F, plan, w, lam, q, fw, fq = _setup(hdg, which)
+    kt = torch.empty_like(plan.bsr)
+    plan.hdg_skeleton_transpose(kt)
+    K = plan.skeleton_matrix_dense()
+    assert np.array_equal(plan.skeleton_matrix_dense(kt), K.T)
+    et = torch.empty(plan.n_skel, dtype=torch.float64, device=plan.device)
+    plan.hdg_adjoint_rhs(fw, et, fq=fq)
+    _, _, Et = O.adjoint_hybridized(step, F)
+    assert O.relative_error(et.cpu().numpy(), Et) < 1e-12
+
+
+@pytest.mark.parametrize("which", ["c1", "hp", "c1_enriched"])
+def test_local_adjoint_matches_oracle(hdg, which):
+    """Given the oracle's Lambda~, the transposed local solves and the indicators."""
+    import torch
+    _say(f"adjoint local {which}")
+    case, step, F, plan, w, lam, q, fw, fq = _setup(hdg, which)
+    Ut, lt, _ = O.adjoint_hybridized(step, F)
+    lamt = torch.tensor(lt, device=plan.device)
+    wt = torch.zeros_like(w)
+    eta = torch.zeros(case.n_elements, dtype=torch.float64, device=plan.device)
+    st = torch.zeros(case.n_elements, dtype=torch.int32, device=plan.device)
+    plan.hdg_adjoint_local(w, lam, fw, lamt, wt, eta, elem_status=st)
+    got = wt.cpu().numpy()
+    for e in range(case.n_elements):
+        npe = hi.n_modes(int(case.degree[e]))
+        ref = Ut[e].reshape(4, npe)
+        tol = 1e-12 + np.linalg.cond(step.blocks[e].A) * 1e-15
+        assert O.relative_error(got[e, :, :npe], ref) < tol, (e, O.relative_error(got[e, :, :npe], ref))
+    assert O.relative_error(eta.cpu().numpy(), O.element_indicators(step, Ut)) < 1e-11
+
+
+@pytest.mark.parametrize("which", ["c1", "hp", "c1_enriched"])
+def test_adjoint_solve_matches_oracle(hdg, which):
+    _say(f"adjoint solve {which}")
+    case, step, F, plan, w, lam, q, fw, fq = _setup(hdg, which)
+    lamt, wt, eta, it = plan.hdg_adjoint_solve(w, lam, fw, rtol=1e-13)
+    _say(f"  gmres iterations on K^T: {it}")
+    Ut, lt, _ = O.adjoint_hybridized(step, F)
+    assert O.relative_error(lamt.cpu().numpy(), lt) < 1e-10
+    got = wt.cpu().numpy()
+    ref = np.zeros_like(got)
+    for e in range(case.n_elements):
+        npe = hi.n_modes(int(case.degree[e]))
+        ref[e, :, :npe] = Ut[e].reshape(4, npe)
+    assert O.relative_error(got, ref) < 1e-10
+    assert O.relative_error(eta.cpu().numpy(), O.element_indicators(step, Ut)) < 1e-9
+
+
+def test_navier_stokes_skeleton_adjoint_and_local_refusal(hdg):
+    """Navier-Stokes: K^T Lambda~ = E~ through the same solver; the local adjoint solve is
+    built for the Euler equations only and says so."""
+    import torch
+    _say("adjoint ns23")
+    case, step, F, plan, w, lam, q, fw, fq = _setup(hdg, "ns23")
+    kt = torch.empty_like(plan.bsr)
+    plan.hdg_skeleton_transpose(kt)
+    et = torch.empty(plan.n_skel, dtype=torch.float64, device=plan.device)
+    plan.hdg_adjoint_rhs(fw, et, fq=fq)
+    lamt = torch.zeros_like(et)
+    import ctypes as C
+    it, rr = C.c_int32(0), C.c_double(0.0)
+    st = plan.lib.hdg_skeleton_solve(plan.handle, kt.data_ptr(), et.data_ptr(), lamt.data_ptr(), 1e-13, 30, 100000,
+                                     plan.ws.data_ptr(), None, C.byref(it), C.byref(rr))
+    assert st == 0
+    _, lt, _ = O.adjoint_hybridized(step, F)
+    assert O.relative_error(lamt.cpu().numpy(), lt) < 1e-10
+    wt = torch.zeros_like(w)
+    eta = torch.zeros(case.n_elements, dtype=torch.float64, device=plan.device)
+    with pytest.raises(hdg.HdgError):
+        plan.hdg_adjoint_local(w, lam, fw, lamt, wt, eta)
