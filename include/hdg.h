@@ -277,6 +277,21 @@ hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* 
                              const double* lamt_dev, double* wt_dev, double* eta_dev, void* workspace_dev,
                              int32_t* elem_status_dev, hipStream_t stream);
 
+/* Adaptation decisions of Sec. 4. Marking: the smallest set M of elements with
+ * eta_M >= (1 - theta) eta_T, where eta_M^2 = sum_{K in M} eta_K^2 (Doerfler): the elements
+ * in order of decreasing eta_K (ties by increasing element id) up to the first whose partial
+ * sum of eta_K^2 reaches (1 - theta)^2 eta_T^2. Smoothness sensor:
+ * S_K = (w - w*, w - w*)_K / (w, w)_K, w* the projection of w onto degree p_K - 1 (the inner
+ * product sums the four conserved fields; with the hierarchical orthonormal basis this is
+ * the energy of the degree-p_K modes over the total). Inputs: w_dev (padded w layout),
+ * eta_dev[ne] (e.g. from hdg_adjoint_local), theta in [0, 1] (the paper: 0.05), eps_s >= 0
+ * (the paper: 1e-6). Outputs: flag_dev[ne] int32, 0 unmarked, 1 marked for p-enrichment
+ * (S_K < eps_s), 2 marked for mesh refinement; sensor_dev[ne] (optional) S_K;
+ * n_marked_host (optional) the size of M, which makes the call synchronise. */
+hdg_status hdg_mark_elements(hdg_plan* plan, const double* w_dev, const double* eta_dev, double theta, double eps_s,
+                             int32_t* flag_dev, double* sensor_dev, int32_t* n_marked_host, void* workspace_dev,
+                             hipStream_t stream);
+
 /* Inspection entry for tests: the uncondensed element blocks of one element in the
  * unknown order documented above (element: Navier-Stokes gradient fields 4d+a first,
  * then w fields, each mode-minor; faces: interior local faces in order, each

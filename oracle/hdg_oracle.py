@@ -22,8 +22,9 @@ What it computes, in the paper's order (Woopen, Balan, May, Schuetz, 2013):
     residual norm ||N_h||_2 over every element and skeleton row;
   * Sec. 4, eq. adjoint and Sec. 4.1: the adjoint of the Newton matrix, solved
     directly and in hybridized form (K^T Lam~ = E~ and the transposed local
-    solves), the element indicators with the skeleton adjoint dropped, and the
-    enrichment to one degree more;
+    solves), the element indicators with the skeleton adjoint dropped, the
+    enrichment to one degree more, Doerfler marking and the smoothness sensor
+    that picks p-enrichment or mesh refinement;
   * Sec. 3.4, eq. ls/cons/hybridsystem: static condensation
     S_K = D_K - C_K A_K^-1 B_K, g_K = r_lam,K - C_K A_K^-1 r_K, summed into the
     skeleton system K dLam = E, solved directly, then the element-wise
@@ -695,6 +696,48 @@ def element_indicators(step: NewtonStep, Ut: List[np.ndarray]) -> np.ndarray:
     """eta_K = |N_h(x_h; q~, w~, 0) restricted to K| (Sec. 4): the element's residual rows
     R_K = -r_K weighted by its adjoint, the skeleton adjoint dropped."""
     return np.array([abs(float(Ut[e] @ (-b.r))) for e, b in enumerate(step.blocks)])
+
+
+def smoothness_sensor(case, W: np.ndarray, e: int) -> float:
+    """S_K = (w - w*, w - w*)_K / (w, w)_K (Sec. 4), by its definition: w* is the L2 projection
+    of w onto the polynomials of degree p_K - 1, found from the projection's normal equations
+    by quadrature; the inner product sums the four conserved fields."""
+    m = Mesh(case, make_physics(case))
+    g = m.geom(e)
+    p = int(case.degree[e])
+    wq = W[e, :, : n_modes(p)] @ g.phi                    # (4, Q) at the quadrature points
+    low = g.phi[: n_modes(p - 1)]                          # a basis of degree p - 1 at the points
+    M = (low * g.wq[None, :]) @ low.T
+    c = np.linalg.solve(M, (low * g.wq[None, :]) @ wq.T)  # (Np(p-1), 4)
+    d = wq - c.T @ low
+    return float(np.sum(d * d * g.wq[None, :]) / np.sum(wq * wq * g.wq[None, :]))
+
+
+def doerfler_mark(eta: np.ndarray, theta: float) -> np.ndarray:
+    """The smallest set M with eta_M >= (1 - theta) eta_T, eta_M^2 = sum over M of eta_K^2
+    (Sec. 4): the elements by decreasing eta_K, ties by increasing id, up to the first whose
+    partial sum of eta_K^2 reaches (1 - theta)^2 eta_T^2. Returns a boolean mask."""
+    eta = np.asarray(eta, dtype=np.float64)
+    order = np.argsort(-eta, kind="stable")
+    cum = np.cumsum(eta[order] ** 2)
+    marked = np.zeros(eta.size, dtype=bool)
+    if eta.size == 0:
+        return marked
+    target = (1.0 - theta) ** 2 * cum[-1]
+    if not target > 0.0:
+        return marked
+    m = int(np.argmax(cum >= target)) + 1
+    marked[order[:m]] = True
+    return marked
+
+
+def adaptation_flags(case, W, eta, theta: float = 0.05, eps_s: float = 1e-6):
+    """Per element: 0 unmarked, 1 marked for p-enrichment (S_K < eps_S), 2 marked for mesh
+    refinement; and the sensor values."""
+    S = np.array([smoothness_sensor(case, W, e) for e in range(case.n_elements)])
+    marked = doerfler_mark(eta, theta)
+    flags = np.where(marked, np.where(S < eps_s, 1, 2), 0).astype(np.int32)
+    return flags, S
 
 
 def enrich(case):

@@ -207,6 +207,18 @@ class HDGPlan:
         self.hdg_adjoint_local(w, lam, fw, lamt, wt, eta, stream=stream)
         return lamt, wt, eta, it.value
 
+    # ---- adaptation decisions
+    def hdg_mark_elements(self, w, eta, theta: float = 0.05, eps_s: float = 1e-6, stream=None):
+        """Doerfler marking and the smoothness sensor: returns (flag, sensor, n_marked); flag is
+        0 (unmarked), 1 (p-enrichment) or 2 (mesh refinement)."""
+        import torch
+        flag = torch.zeros(max(1, self.ne), dtype=torch.int32, device=self.device)
+        sensor = torch.zeros(max(1, self.ne), dtype=torch.float64, device=self.device)
+        m = C.c_int32(0)
+        check(self.lib.hdg_mark_elements(self.handle, _vp(w), _vp(eta), theta, eps_s, _vp(flag), _vp(sensor),
+                                         C.byref(m), _vp(self.ws), _stream(stream)))
+        return flag[: self.ne], sensor[: self.ne], m.value
+
     # ---- dominant-kernel timing (benchmarks)
     def hdg_set_kernel_timing(self, enable: bool):
         check(self.lib.hdg_set_kernel_timing(self.handle, 1 if enable else 0))

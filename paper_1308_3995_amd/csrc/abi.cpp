@@ -545,6 +545,35 @@ hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* 
     return HDG_OK;
 }
 
+hdg_status hdg_mark_elements(hdg_plan* plan, const double* w_dev, const double* eta_dev, double theta, double eps_s,
+                             int32_t* flag_dev, double* sensor_dev, int32_t* n_marked_host, void* workspace_dev,
+                             hipStream_t stream) {
+    if (!plan || !w_dev || !eta_dev || !flag_dev || !workspace_dev) {
+        set_error("hdg_mark_elements: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    if (!(theta >= 0.0 && theta <= 1.0) || !(eps_s >= 0.0)) {
+        set_error("hdg_mark_elements: need 0 <= theta <= 1 and eps_s >= 0");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    char* base = (char*)workspace_dev + p.ws_mark;
+    int32_t* m_dev = (int32_t*)base;
+    double* sensor = sensor_dev ? sensor_dev : (double*)(base + 256);
+    char* scratch = base + 256 + (int64_t)p.ne * 8;
+    CHECK_HIP(hipSetDevice(p.device));
+    CHECK_HIP(launch_mark(p, w_dev, eta_dev, theta, eps_s, sensor, flag_dev, scratch, m_dev, stream));
+    if (n_marked_host) {
+        if (p.ne == 0) {
+            *n_marked_host = 0;
+            return HDG_OK;
+        }
+        CHECK_HIP(hipMemcpyAsync(n_marked_host, m_dev, 4, hipMemcpyDeviceToHost, stream));
+        CHECK_HIP(hipStreamSynchronize(stream));
+    }
+    return HDG_OK;
+}
+
 hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const double* w_dev, const double* q_dev,
                                     const double* lam_dev, double* A_host, double* B_host, double* C_host,
                                     double* D_host, double* r_host, double* rl_host, int32_t* n_out, int32_t* f_out) {

@@ -126,6 +126,7 @@ struct Plan {
     // workspace layout (offsets in bytes)
     int64_t ws_diag_part = 0, ws_g_part = 0, ws_status = 0, ws_solver = 0, ws_total = 0;
     int64_t ws_res_elem = 0, ws_rl_part = 0, ws_res_red = 0;   // residual-norm partials
+    int64_t ws_mark = 0, mark_temp_bytes = 0;                  // marking: sort buffers and sort scratch
     int64_t ws_ns = 0, ns_zcap = 0;       // Navier-Stokes assembly chunk workspace (doubles)
     int64_t hat_values = 0;
     int solver_restart_max = 0;
@@ -180,6 +181,14 @@ hipError_t launch_axpy_update(int64_t n, double* x, const double* dx, hipStream_
 // part (the slots of the condensed right-hand side) summed per face into etilde; the local
 // adjoint solves and indicators (Euler).
 hipError_t launch_skeleton_transpose(const Plan& p, const double* k, double* kt, hipStream_t s);
+// Adaptation decisions (adapt.hip). scratch: mark_scratch_bytes(p) bytes at the workspace's
+// marking region; m_dev receives the number of marked elements.
+int64_t mark_sort_temp_bytes(int n);
+inline int64_t mark_scratch_bytes(const Plan& p) {
+    return ((int64_t)p.ne * 24 + 255) / 256 * 256 + p.mark_temp_bytes + 256;
+}
+hipError_t launch_mark(const Plan& p, const double* w, const double* eta, double theta, double eps_s,
+                       double* sensor, int32_t* flag, char* scratch, int32_t* m_dev, hipStream_t s);
 hipError_t launch_adjoint_rhs(const Plan& p, const double* store, const double* fw, const double* fq, double* part,
                               double* etilde, hipStream_t s);
 hipError_t launch_adjoint_local(Plan& p, const double* w, const double* lam, const double* fw, const double* lamt,

@@ -511,6 +511,19 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     P.ws_res_elem = carve((int64_t)ne * 8);
     P.ws_rl_part = carve(2 * P.face_off.back() * 8);
     P.ws_res_red = carve((kResPartials + 1) * 8);
+    {
+        if (hipSetDevice(device) != hipSuccess) {
+            set_error("hipSetDevice failed");
+            return HDG_ERR_HIP;
+        }
+        P.mark_temp_bytes = mark_sort_temp_bytes(std::max(1, ne));
+        if (P.mark_temp_bytes < 0) {
+            set_error("sort scratch size query failed");
+            return HDG_ERR_HIP;
+        }
+        // [marked count | sensor (ne doubles) | sort keys, ids and scratch]
+        P.ws_mark = carve(256 + (int64_t)ne * 8 + mark_scratch_bytes(P));
+    }
     if (P.ns) {
         for (const Bucket& b : P.buckets)
             if (b.p > 4 || b.pf > 4) {

@@ -136,3 +136,31 @@ def test_navier_stokes_skeleton_adjoint_and_local_refusal(hdg):
     eta = torch.zeros(case.n_elements, dtype=torch.float64, device=plan.device)
     with pytest.raises(hdg.HdgError):
         plan.hdg_adjoint_local(w, lam, fw, lamt, wt, eta)
+
+
+@pytest.mark.parametrize("which", ["c1", "hp"])
+def test_marking_and_sensor_match_oracle(hdg, which):
+    """Doerfler marking and the smoothness sensor on seeded indicators: sensor values agree
+    to rounding, the marked sets and the p/h flags exactly (ties included: the indicators are
+    rounded so that many repeat)."""
+    import torch
+    _say(f"marking {which}")
+    case = _case(which)
+    plan = hdg.HDGPlan.from_case(case)
+    w = torch.tensor(case.W, dtype=torch.float64, device=plan.device)
+    S_ref = np.array([O.smoothness_sensor(case, case.W, e) for e in range(case.n_elements)])
+    s_sorted = np.sort(S_ref)
+    k = len(s_sorted) // 2
+    eps_mid = float(np.sqrt(s_sorted[k - 1] * s_sorted[k]))   # between two sensor values: both flags occur
+    rng = np.random.default_rng(11)
+    for rounding in (None, 1):
+        eta_h = rng.exponential(size=case.n_elements)
+        if rounding is not None:
+            eta_h = np.round(eta_h, rounding)
+        eta = torch.tensor(eta_h, device=plan.device)
+        for theta, eps in ((0.05, 1e-6), (0.3, eps_mid), (0.0, eps_mid), (1.0, eps_mid)):
+            flag, S, m = plan.hdg_mark_elements(w, eta, theta=theta, eps_s=eps)
+            ref, _ = O.adaptation_flags(case, case.W, eta_h, theta, eps)
+            assert np.all(np.abs(S.cpu().numpy() - S_ref) <= 1e-13 + 1e-10 * S_ref)
+            assert np.array_equal(flag.cpu().numpy(), ref), (theta, eps)
+            assert m == int((ref > 0).sum())

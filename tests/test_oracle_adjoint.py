@@ -95,3 +95,44 @@ def test_enrichment_keeps_the_function_and_adds_test_functions():
         new_rows = R1[e][:, n0:]
         assert np.abs(new_rows).max() > 1e-8          # tested against the new functions
         assert R1[e].shape[1] == hi.n_modes(int(c.degree[e]) + 1) and R0[e].shape[1] == n0
+
+
+def test_doerfler_marking_hand_cases_and_brute_force():
+    eta = np.array([3.0, 4.0, 0.0, 1.0, 2.0])             # eta_T^2 = 30
+    assert list(np.flatnonzero(O.doerfler_mark(eta, 0.5))) == [1]           # 16 >= 0.25 * 30
+    assert list(np.flatnonzero(O.doerfler_mark(eta, 0.05))) == [0, 1, 4]    # 16, 25, 29 >= 27.075
+    assert not O.doerfler_mark(eta, 1.0).any()
+    assert not O.doerfler_mark(np.zeros(4), 0.05).any()
+    # ties go to the lower element id
+    assert list(np.flatnonzero(O.doerfler_mark(np.array([1.0, 2.0, 2.0, 1.0]), 0.5))) == [1]
+    # the smallest qualifying set, by exhaustive search over subsets
+    import itertools
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        e = rng.exponential(size=8)
+        theta = rng.uniform(0.0, 0.9)
+        need = (1 - theta) ** 2 * np.sum(e * e)
+        best = min(k for k in range(9) for s in itertools.combinations(range(8), k)
+                   if np.sum(e[list(s)] ** 2) >= need - 1e-15 * need)
+        got = O.doerfler_mark(e, theta)
+        assert got.sum() == best and np.sum(e[got] ** 2) >= need * (1 - 1e-15)
+
+
+def test_smoothness_sensor_definition_cases():
+    """A degree-(p-1) state has S = 0, a state made of degree-p modes only has S = 1, and in
+    general S equals the energy of the degree-p coefficients over the total (orthonormal,
+    hierarchical basis), although the oracle computes it from the projection's definition."""
+    c = hi.make_case("euler", 3, [1, 2, 3], 0.5, 2.0, 5e-2, seed=12, jitter=0.2)
+    rng = np.random.default_rng(3)
+    for e in range(0, c.n_elements, 2):
+        p = int(c.degree[e])
+        n0, n1 = hi.n_modes(p - 1), hi.n_modes(p)
+        W = np.zeros_like(c.W)
+        W[e, :, :n0] = rng.standard_normal((4, n0))
+        assert O.smoothness_sensor(c, W, e) < 1e-24
+        W[:] = 0.0
+        W[e, :, n0:n1] = rng.standard_normal((4, n1 - n0))
+        assert abs(O.smoothness_sensor(c, W, e) - 1.0) < 1e-12
+        W[e, :, :n1] = c.W[e, :, :n1]
+        ref = np.sum(W[e, :, n0:n1] ** 2) / np.sum(W[e, :, :n1] ** 2)
+        assert abs(O.smoothness_sensor(c, W, e) - ref) < 1e-12 * ref
