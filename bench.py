@@ -11,8 +11,8 @@ back-substitution (hdg_back_substitute). Both precision modes are timed; the rep
 `value` is condensed elements per second of full Newton steps of the mixed mode.
 Beside the step: assemble + condense alone on three workloads (`condensation`), the
 relaxed Newton iteration with the pseudo-time CFL schedule run to convergence
-(`pseudo_transient`), a sample of the serving stream (`serving`) and the CPU oracle
-(`cpu_baseline`).
+(`pseudo_transient`), the hybridized adjoint at one degree more with the marking decisions
+(`adjoint`), a sample of the serving stream (`serving`) and the CPU oracle (`cpu_baseline`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -209,6 +209,64 @@ def newton_loop_report(name: str, rtol: float, restart: int, max_steps: int = 12
             "res_history": [float(x) for x in r["res_history"]], "cfl_history": [float(x) for x in r["cfl_history"]]}
 
 
+def adjoint_report(name: str, rtol: float, restart: int, reps: int = 3):
+    """The hybridized adjoint in the space of one degree more, as the paper solves it, for the
+    total mass J(w) = integral of rho (F~ has one entry per element: sqrt(2) det J on the
+    constant density mode), followed by the marking decisions (theta = 0.05, eps_S = 1e-6) on
+    the primal state with the adjoint's indicators. Timed with HIP events around the whole
+    sequence, median of `reps` after one warm-up."""
+    import torch
+    import hdg_inputs as hi
+    import paper_1308_3995_amd as hdg
+    case = hi.config_case(name)
+    p1 = int(case.degree.max()) + 1
+    npm = hi.n_modes(p1)
+    W = np.zeros((case.n_elements, 4, npm))
+    for e in range(case.n_elements):
+        n = hi.n_modes(int(case.degree[e]))
+        W[e, :, :n] = case.W[e, :, :n]
+    plan = hdg.HDGPlan(case.xy, case.tri, (case.degree + 1).astype(np.int8), physics=case.physics,
+                       mach=case.mach, aoa_deg=case.aoa_deg, precision="fp64")
+    dev = torch.device("cuda", 0)
+    fdeg = plan.face_degree
+    lam = np.zeros(plan.n_skel)
+    for f in range(len(fdeg)):     # the faces' coefficients up to their primal degree, zero above
+        o, pf = plan.face_offset[f], int(fdeg[f])
+        for a in range(4):
+            lam[o + a * (pf + 1): o + a * (pf + 1) + pf] = case.lam[f, a, :pf]
+    v = case.xy[case.tri]
+    area = 0.5 * np.abs((v[:, 1, 0] - v[:, 0, 0]) * (v[:, 2, 1] - v[:, 0, 1]) -
+                        (v[:, 2, 0] - v[:, 0, 0]) * (v[:, 1, 1] - v[:, 0, 1]))
+    fw = np.zeros_like(W)
+    fw[:, 0, 0] = np.sqrt(2.0) * area / 2.0
+    w_d = torch.tensor(W, device=dev)
+    lam_d = torch.tensor(lam, device=dev)
+    fw_d = torch.tensor(fw, device=dev)
+    primal = hdg.HDGPlan.from_case(case, precision="fp64", allocate=False)
+    primal.allocate()
+    w_p = torch.tensor(case.W, device=dev)
+    ts = []
+    for r in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lamt, wt, eta, it = plan.hdg_adjoint_solve(w_d, lam_d, fw_d, rtol=rtol, restart=restart)
+        flag, S, m = primal.hdg_mark_elements(w_p, eta, theta=0.05, eps_s=1e-6)
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    fl = flag.cpu().numpy()
+    log(f"[bench] adjoint {name} at p+1: {ms:.1f} ms, {it} GMRES iterations on K^T, {m} elements marked "
+        f"({int((fl == 1).sum())} p, {int((fl == 2).sum())} h)")
+    return {"workload": f"{name} state in the space of one degree more ({case.n_elements} elements, degrees "
+                        f"{sorted(set((case.degree + 1).tolist()))}, {plan.n_skel} skeleton dofs); J = total mass; "
+                        f"assemble + condense, K^T, E~, GMRES({restart}) on K^T to {rtol:g}, local adjoint solves "
+                        f"and indicators, marking (theta 0.05, eps_S 1e-6)",
+            "ms": ms, "gmres_iters": it, "marked": m, "p_enrich": int((fl == 1).sum()),
+            "h_refine": int((fl == 2).sum()), "elements_per_s": case.n_elements / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +285,8 @@ def main():
                     help="workloads whose assemble + condense time is reported beside the step ('' = none)")
     ap.add_argument("--newton-loop", default="c2",
                     help="workload of the pseudo-transient Newton iteration report ('' = none)")
+    ap.add_argument("--adjoint", default="c2",
+                    help="workload of the adjoint + marking report, solved at one degree more ('' = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -353,6 +413,8 @@ def main():
         out["condensation"] = condensation_report([c for c in args.condense_configs.split(",") if c])
     if args.newton_loop:
         out["pseudo_transient"] = newton_loop_report(args.newton_loop, args.rtol, args.restart)
+    if args.adjoint:
+        out["adjoint"] = adjoint_report(args.adjoint, args.rtol, args.restart)
     if args.serving_requests > 0:
         from paper_1308_3995_amd.serving import ServingEngine, stream_requests
         log(f"[bench] serving: generating {args.serving_requests} requests")
