@@ -266,16 +266,19 @@ hdg_status hdg_skeleton_transpose(hdg_plan* plan, const double* bsr_values_dev, 
 hdg_status hdg_adjoint_rhs(hdg_plan* plan, const void* local_store_dev, const double* fw_dev, const double* fq_dev,
                            double* etilde_dev, void* workspace_dev, hipStream_t stream);
 
-/* Local adjoint solves U~_K = A_K^-T (F~_K - C_K^T Lambda~_K) at the state (w_dev, lam_dev)
- * (A_K is assembled again, with the plan's CFL, and eliminated transposed with partial
- * pivoting), written to wt_dev in the padded w layout, and the element indicators of Sec. 4
- * with the skeleton adjoint dropped, eta_dev[ne] = |U~_K . R_K(x)| (R_K the element's
- * residual rows). Euler only: returns HDG_ERR_INVALID_ARG for a Navier-Stokes plan.
- * elem_status_dev (optional, int32[ne]) as in hdg_assemble_condense; when given the call
- * synchronises and returns the first failure. */
-hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* lam_dev, const double* fw_dev,
-                             const double* lamt_dev, double* wt_dev, double* eta_dev, void* workspace_dev,
-                             int32_t* elem_status_dev, hipStream_t stream);
+/* Local adjoint solves U~_K = A_K^-T (F~_K - C_K^T Lambda~_K) at the state (w_dev, q_dev,
+ * lam_dev) (A_K is assembled again, with the plan's CFL, and eliminated transposed with
+ * partial pivoting), written to wt_dev (padded w layout) and, for Navier-Stokes, qt_dev
+ * (padded q layout), and the element indicators of Sec. 4 with the skeleton adjoint dropped,
+ * eta_dev[ne] = |U~_K . R_K(x)| (R_K the element's residual rows, gradient rows included).
+ * q_dev, fq_dev (the q part of F~) and qt_dev are Navier-Stokes only (NULL for Euler).
+ * Navier-Stokes allocates a temporary device buffer for the uncondensed blocks of a chunk of
+ * elements (at most 1 GiB) and synchronises. elem_status_dev (optional, int32[ne]) as in
+ * hdg_assemble_condense; when given the call synchronises and returns the first failure. */
+hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* q_dev, const double* lam_dev,
+                             const double* fw_dev, const double* fq_dev, const double* lamt_dev, double* wt_dev,
+                             double* qt_dev, double* eta_dev, void* workspace_dev, int32_t* elem_status_dev,
+                             hipStream_t stream);
 
 /* Adaptation decisions of Sec. 4. Marking: the smallest set M of elements with
  * eta_M >= (1 - theta) eta_T, where eta_M^2 = sum_{K in M} eta_K^2 (Doerfler): the elements

@@ -183,28 +183,34 @@ class HDGPlan:
         check(self.lib.hdg_adjoint_rhs(self.handle, _vp(self.store), _vp(fw), _vp(fq), _vp(etilde), _vp(self.ws),
                                        _stream(stream)))
 
-    def hdg_adjoint_local(self, w, lam, fw, lamt, wt, eta, elem_status=None, stream=None):
-        check(self.lib.hdg_adjoint_local(self.handle, _vp(w), _vp(lam), _vp(fw), _vp(lamt), _vp(wt), _vp(eta),
-                                         _vp(self.ws), _vp(elem_status), _stream(stream)))
-
-    def hdg_adjoint_solve(self, w, lam, fw, rtol: float = 1e-12, restart: int = 30, max_iter: int = 200000,
+    def hdg_adjoint_local(self, w, lam, fw, lamt, wt, eta, q=None, fq=None, qt=None, elem_status=None,
                           stream=None):
-        """The whole hybridized adjoint at the state (w, lam) for the functional derivative fw
-        (Euler): returns (Lambda~, W~, eta, gmres iterations)."""
+        check(self.lib.hdg_adjoint_local(self.handle, _vp(w), _vp(q), _vp(lam), _vp(fw), _vp(fq), _vp(lamt),
+                                         _vp(wt), _vp(qt), _vp(eta), _vp(self.ws), _vp(elem_status),
+                                         _stream(stream)))
+
+    def hdg_adjoint_solve(self, w, lam, fw, q=None, fq=None, rtol: float = 1e-12, restart: int = 30,
+                          max_iter: int = 200000, stream=None):
+        """The whole hybridized adjoint at the state (w, lam[, q]) for the functional derivative
+        (fw[, fq]): returns (Lambda~, W~, eta, gmres iterations), and Q~ as a fifth entry for
+        Navier-Stokes."""
         import torch
-        self.hdg_assemble_condense(w, lam, stream=stream)
+        self.hdg_assemble_condense(w, lam, q=q, stream=stream)
         kt = torch.empty_like(self.bsr)
         self.hdg_skeleton_transpose(kt, stream=stream)
         et = torch.empty(max(1, self.n_skel), dtype=torch.float64, device=self.device)
-        self.hdg_adjoint_rhs(fw, et, stream=stream)
+        self.hdg_adjoint_rhs(fw, et, fq=fq, stream=stream)
         lamt = torch.zeros_like(et)
         it = C.c_int32(0)
         rr = C.c_double(0.0)
         check(self.lib.hdg_skeleton_solve(self.handle, _vp(kt), _vp(et), _vp(lamt), rtol, restart, max_iter,
                                           _vp(self.ws), _stream(stream), C.byref(it), C.byref(rr)))
         wt = torch.zeros_like(w)
+        qt = torch.zeros_like(q) if q is not None else None
         eta = torch.zeros(self.ne, dtype=torch.float64, device=self.device)
-        self.hdg_adjoint_local(w, lam, fw, lamt, wt, eta, stream=stream)
+        self.hdg_adjoint_local(w, lam, fw, lamt, wt, eta, q=q, fq=fq, qt=qt, stream=stream)
+        if q is not None:
+            return lamt, wt, eta, it.value, qt
         return lamt, wt, eta, it.value
 
     # ---- adaptation decisions

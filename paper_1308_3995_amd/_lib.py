@@ -86,7 +86,7 @@ def load(path: str = LIB_PATH):
                                                P(HdgNewtonReport), vp, vp, vp]
     lib.hdg_skeleton_transpose.argtypes = [vp, vp, vp, vp]
     lib.hdg_adjoint_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-    lib.hdg_adjoint_local.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hdg_adjoint_local.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_mark_elements.argtypes = [vp, vp, vp, dbl, dbl, vp, vp, P(i32), vp, vp]
     lib.hdg_last_error.argtypes = []
     lib.hdg_last_error.restype = C.c_char_p

@@ -517,16 +517,17 @@ hdg_status hdg_adjoint_rhs(hdg_plan* plan, const void* local_store_dev, const do
     return HDG_OK;
 }
 
-hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* lam_dev, const double* fw_dev,
-                             const double* lamt_dev, double* wt_dev, double* eta_dev, void* workspace_dev,
-                             int32_t* elem_status_dev, hipStream_t stream) {
+hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* q_dev, const double* lam_dev,
+                             const double* fw_dev, const double* fq_dev, const double* lamt_dev, double* wt_dev,
+                             double* qt_dev, double* eta_dev, void* workspace_dev, int32_t* elem_status_dev,
+                             hipStream_t stream) {
     if (!plan || !w_dev || !lam_dev || !fw_dev || !lamt_dev || !wt_dev || !eta_dev || !workspace_dev) {
         set_error("hdg_adjoint_local: null argument");
         return HDG_ERR_INVALID_ARG;
     }
     Plan& p = plan->p;
-    if (p.ns) {
-        set_error("hdg_adjoint_local: the local adjoint solve is built for the Euler equations only");
+    if (p.ns && (!q_dev || !fq_dev || !qt_dev)) {
+        set_error("hdg_adjoint_local: Navier-Stokes needs q, the q part of the functional derivative and qt");
         return HDG_ERR_INVALID_ARG;
     }
     char* ws = (char*)workspace_dev;
@@ -534,8 +535,26 @@ hdg_status hdg_adjoint_local(hdg_plan* plan, const double* w_dev, const double* 
     int32_t* flag = (int32_t*)(ws + p.ws_status) + p.ne;
     CHECK_HIP(hipSetDevice(p.device));
     hipError_t e = launch_clear_status(p, status, flag, stream);
-    if (e == hipSuccess) e = launch_adjoint_local(p, w_dev, lam_dev, fw_dev, lamt_dev, wt_dev, eta_dev, status, flag,
-                                                 stream);
+    if (p.ns) {
+        // uncondensed blocks of a chunk of elements: all of them, up to 1 GiB
+        int64_t need = 0, per_max = 0;
+        for (const Bucket& b : p.buckets) {
+            const int64_t per = ns_workspace_per_element(b.p, b.pf);
+            need = std::max(need, per * b.count);
+            per_max = std::max(per_max, per);
+        }
+        const int64_t cap = std::max<int64_t>(per_max, std::min<int64_t>(need, (int64_t)1 << 27));
+        double* buf = nullptr;
+        if (e == hipSuccess) e = hipMalloc((void**)&buf, cap * 8);
+        if (e == hipSuccess)
+            e = launch_ns_adjoint_local(p, w_dev, q_dev, lam_dev, fw_dev, fq_dev, lamt_dev, wt_dev, qt_dev, eta_dev,
+                                        status, flag, buf, cap, stream);
+        const hipError_t se = hipStreamSynchronize(stream);
+        if (buf) (void)hipFree(buf);
+        if (e == hipSuccess) e = se;
+    } else if (e == hipSuccess) {
+        e = launch_adjoint_local(p, w_dev, lam_dev, fw_dev, lamt_dev, wt_dev, eta_dev, status, flag, stream);
+    }
     if (e == hipErrorInvalidValue) {
         set_error("hdg_adjoint_local: element degree outside the built kernels");
         return HDG_ERR_INVALID_ARG;

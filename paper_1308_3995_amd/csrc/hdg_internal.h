@@ -193,6 +193,10 @@ hipError_t launch_adjoint_rhs(const Plan& p, const double* store, const double* 
                               double* etilde, hipStream_t s);
 hipError_t launch_adjoint_local(Plan& p, const double* w, const double* lam, const double* fw, const double* lamt,
                                 double* wt, double* eta, int32_t* status, int32_t* flag, hipStream_t s);
+// Navier-Stokes local adjoint (ns.hip); zbuf holds the uncondensed blocks of a chunk.
+hipError_t launch_ns_adjoint_local(Plan& p, const double* w, const double* q, const double* lam, const double* fw,
+                                   const double* fq, const double* lamt, double* wt, double* qt, double* eta,
+                                   int32_t* status, int32_t* flag, double* zbuf, int64_t zcap_doubles, hipStream_t s);
 int64_t ns_workspace_per_element(int p, int pf);   // Z, L, R of one element (block inspection)
 int64_t ns_chunk_per_element(int p, int pf);       // reduced system and factors (product path)
 hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol,

@@ -1230,4 +1230,198 @@ hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* la
     return err;
 }
 
+// ---------------------------------------------------------------------------
+// Local adjoint solve (Sec. 4.1) for the Navier-Stokes equations. The uncondensed element
+// blocks of a chunk are written by k_ns_assemble (Z, L = [A_wq; C_q], R = [G_qw | B_q | r_q]),
+// then one workgroup per element eliminates [A_K^T | F~_K - C_K^T Lambda~_K] over all 12 Np
+// element unknowns (gradient fields first) with the pivoted Gauss-Jordan of the condensation,
+// the unknowns grouped in four blocks of 3 Np columns. The element indicator is
+// eta_K = |U~_K . r_K| over the gradient and the conserved-variable rows.
+// ---------------------------------------------------------------------------
+template <int P>
+struct NsAdjShape {
+    static constexpr int NP3 = 3 * n_modes(P);      // four column groups of 3 Np
+    static constexpr int N = 4 * NP3;               // 12 Np element unknowns
+    static constexpr int RH = (N + 63) / 64;
+    static constexpr int WPF = P <= 2 ? 1 : (P == 3 ? 2 : 4);
+    static constexpr int NW = 4 * WPF;
+};
+
+struct NsAdjArgs {
+    const ElemInfo* einfo;
+    const int64_t* face_off;
+    const double* zbuf;     // Z, L, R of the chunk's elements
+    const double* fw;       // F~, w part (padded w layout)
+    const double* fq;       // F~, q part (padded q layout)
+    const double* lamt;     // Lambda~
+    double* wt;             // U~, w part
+    double* qt;             // U~, q part
+    double* eta;
+    int32_t* status;
+    int32_t* flag;
+    int start;              // first slot of the chunk
+    int npmax;
+};
+
+template <int P, int PF>
+__global__ __launch_bounds__(64 * NsAdjShape<P>::NW) void k_ns_adjoint(NsAdjArgs a) {
+    using D = NsDims<P, PF>;
+    using S = NsAdjShape<P>;
+    constexpr int NP = D::NP, NW4 = D::N, NQ = D::NQ, NPF = D::NPF, F = D::F, NR = D::NR, NCZ = D::NCZ;
+    constexpr int N = S::N, RH = S::RH, WPF = S::WPF, NP3 = S::NP3;
+    constexpr int NTH = 64 * S::NW;
+    constexpr int NPW = (NP3 + WPF - 1) / WPF;
+    __shared__ double sFm[2][64 * RH];
+    __shared__ double sPVk[N];
+    __shared__ double sRhs[N];   // F~ - C^T Lambda~, later U~
+    __shared__ double sR[N];     // r_K
+    __shared__ double sLt[F];    // Lambda~ on the element's faces, zero past p_e and on the boundary
+    __shared__ int sPiv[2];
+    __shared__ int sBad;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const ElemInfo* E = a.einfo + a.start + blockIdx.x;
+    const int e = E->elem;
+    const double* Z = a.zbuf + (int64_t)blockIdx.x * D::PER;
+    const double* L = Z + D::ZSZ;
+    const double* R = L + D::LSZ;
+    // A_K[r][c] in the unknown order (q fields 4 d + a, then w fields), from the blocks
+    auto aent = [&](int r, int c) -> double {
+        if (r < NQ && c < NQ) return r == c ? E->detj : 0.0;
+        if (r < NQ) return R[(int64_t)(c - NQ) * NQ + r];
+        if (c < NQ) return L[(int64_t)c * NR + (r - NQ)];
+        return Z[(int64_t)(c - NQ) * NR + (r - NQ)];
+    };
+    if (tid == 0) sBad = 0;
+    for (int t = tid; t < F; t += NTH) {
+        const int lf = t / (4 * NPF), b = (t / NPF) % 4, k = t % NPF;
+        const int f = E->face[lf], pe = E->pe[lf];
+        sLt[t] = (f >= 0 && k <= pe) ? a.lamt[a.face_off[f] + b * (pe + 1) + k] : 0.0;
+    }
+    __syncthreads();
+    for (int r = tid; r < N; r += NTH) {
+        // C_K^T Lambda~: C_K = [C_q | C_w] are the skeleton rows of L and Z
+        double ct = 0.0;
+        for (int fr = 0; fr < F; ++fr) {
+            const double lt = sLt[fr];
+            if (lt != 0.0) ct += (r < NQ ? L[(int64_t)r * NR + NW4 + fr] : Z[(int64_t)(r - NQ) * NR + NW4 + fr]) * lt;
+        }
+        const double fv = r < NQ ? a.fq[((int64_t)e * 8 + r / NP) * a.npmax + r % NP]
+                                 : a.fw[((int64_t)e * 4 + (r - NQ) / NP) * a.npmax + (r - NQ) % NP];
+        sRhs[r] = fv - ct;
+        sR[r] = r < NQ ? R[(int64_t)(NCZ - 1) * NQ + r] : Z[(int64_t)(NCZ - 1) * NR + (r - NQ)];
+    }
+    __syncthreads();
+    const int fld = wave / WPF, part = wave % WPF;
+    double mA[RH][NPW], mB[RH][1];
+#pragma unroll
+    for (int h = 0; h < RH; ++h) {
+        const int row = h * 64 + lane;
+        const int rr = row < N ? row : N - 1;
+#pragma unroll
+        for (int j = 0; j < NPW; ++j) {
+            const int jj = part * NPW + j;
+            mA[h][j] = jj < NP3 ? aent(fld * NP3 + jj, rr) : 0.0;   // A_K^T[rr][col] = A_K[col][rr]
+        }
+        mB[h][0] = wave == 0 ? sRhs[rr] : 0.0;
+    }
+    int mykk[RH];
+    gj_eliminate<NP3, 1, RH, WPF>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int h = 0; h < RH; ++h) {
+            if (h * 64 + lane >= N) continue;
+            const int kk = mykk[h];
+            const double pv = sPVk[kk];
+            const double x = mB[h][0] / pv;
+            sRhs[kk] = x;
+            if (!(fabs(pv) > 0.0)) sBad = 1;
+            else if (!isfinite(x) && sBad == 0) sBad = 2;
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < 4 * a.npmax; t += NTH) {
+        const int fa = t / a.npmax, i = t % a.npmax;
+        a.wt[(int64_t)e * 4 * a.npmax + t] = i < NP ? sRhs[NQ + fa * NP + i] : 0.0;
+    }
+    for (int t = tid; t < 8 * a.npmax; t += NTH) {
+        const int da = t / a.npmax, i = t % a.npmax;
+        a.qt[(int64_t)e * 8 * a.npmax + t] = i < NP ? sRhs[da * NP + i] : 0.0;
+    }
+    if (wave == 0) {
+        double s = 0.0;
+        for (int r = lane; r < N; r += 64) s += sRhs[r] * sR[r];
+        s = wave_sum_f64(s);
+        if (lane == 0) a.eta[e] = fabs(s);
+    }
+    if (tid == 0 && sBad != 0) {
+        a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+        a.flag[0] = 1;
+    }
+}
+
+hipError_t launch_ns_adjoint_local(Plan& p, const double* w, const double* q, const double* lam, const double* fw,
+                                   const double* fq, const double* lamt, double* wt, double* qt, double* eta,
+                                   int32_t* status, int32_t* flag, double* zbuf, int64_t zcap_doubles, hipStream_t s) {
+    NsArgs a{};
+    a.einfo = p.d_einfo;
+    a.leg = p.d_tab + p.tix.leg;
+    a.gw = p.d_tab + p.tix.gw;
+    a.bproj = p.d_bproj;
+    a.face_off = p.d_face_off;
+    a.diag_off = p.d_diag_off;
+    a.w = w;
+    a.q = q;
+    a.lam = lam;
+    a.npmax = p.npmax;
+    a.ne = p.ne;
+    for (int i = 0; i < 4; ++i) a.winf[i] = p.winf[i];
+    a.alpha = p.alpha;
+    a.gamma = p.prm.gamma;
+    a.mu = p.mu;
+    a.prandtl = p.prm.prandtl;
+    a.cfl = p.prm.cfl;
+    NsAdjArgs b{};
+    b.einfo = p.d_einfo;
+    b.face_off = p.d_face_off;
+    b.zbuf = zbuf;
+    b.fw = fw;
+    b.fq = fq;
+    b.lamt = lamt;
+    b.wt = wt;
+    b.qt = qt;
+    b.eta = eta;
+    b.status = status;
+    b.flag = flag;
+    b.npmax = p.npmax;
+    for (const Bucket& bk : p.buckets) {
+        bool done = false;
+#define HDG_CASE(PP, FF)                                                                                        \
+    if (!done && bk.p == PP && bk.pf == FF) {                                                                   \
+        done = true;                                                                                            \
+        a.vphi = p.d_tab + p.tix.vol_phi[PP];                                                                   \
+        a.vgrad = p.d_tab + p.tix.vol_grad[PP];                                                                 \
+        a.vw = p.d_tab + p.tix.vol_w[PP];                                                                       \
+        a.fphi = p.d_tab + p.tix.face_phi[PP];                                                                  \
+        a.zbuf = zbuf;                                                                                          \
+        a.bucket_start = bk.start;                                                                              \
+        const int64_t per = NsDims<PP, FF>::PER;                                                                \
+        if (zcap_doubles < per) return hipErrorInvalidValue;                                                    \
+        const int chunk = (int)std::min<int64_t>(bk.count, zcap_doubles / per);                                 \
+        for (int c0 = 0; c0 < bk.count; c0 += chunk) {                                                          \
+            const int cnt = std::min(chunk, bk.count - c0);                                                     \
+            a.start = bk.start + c0;                                                                            \
+            hipLaunchKernelGGL((k_ns_assemble<PP, FF>), dim3(cnt), dim3(256), 0, s, a);                         \
+            b.start = bk.start + c0;                                                                            \
+            hipLaunchKernelGGL((k_ns_adjoint<PP, FF>), dim3(cnt), dim3(64 * NsAdjShape<PP>::NW), 0, s, b);      \
+        }                                                                                                       \
+    }
+        HDG_NS_BUCKETS(HDG_CASE)
+#undef HDG_CASE
+        if (!done) return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace hdg

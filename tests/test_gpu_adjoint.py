@@ -25,6 +25,8 @@ def _case(which):
         return O.enrich(hi.config_case("c1"))
     if which == "hp":
         return hi.make_case("euler", 4, [1, 2, 3, 4], 0.6, 1.5, 2e-2, seed=3)
+    if which == "ns14":
+        return hi.make_case("ns", 3, [1, 2, 3, 4], 0.6, -2.0, 2e-2, seed=22, reynolds=500.0)
     return hi.make_case("ns", 3, [2, 3], 0.5, 1.0, 2e-2, seed=21, reynolds=200.0)
 
 
@@ -114,28 +116,36 @@ def test_adjoint_solve_matches_oracle(hdg, which):
     assert O.relative_error(eta.cpu().numpy(), O.element_indicators(step, Ut)) < 1e-9
 
 
-def test_navier_stokes_skeleton_adjoint_and_local_refusal(hdg):
-    """Navier-Stokes: K^T Lambda~ = E~ through the same solver; the local adjoint solve is
-    built for the Euler equations only and says so."""
+@pytest.mark.parametrize("which", ["ns23", "ns14"])
+def test_navier_stokes_adjoint_matches_oracle(hdg, which):
+    """Navier-Stokes: K^T Lambda~ = E~ through the same solver, then the local adjoint over
+    all 12 Np element unknowns (gradient fields included) and the indicators; also the local
+    solve alone from the oracle's Lambda~."""
     import torch
-    _say("adjoint ns23")
-    case, step, F, plan, w, lam, q, fw, fq = _setup(hdg, "ns23")
-    kt = torch.empty_like(plan.bsr)
-    plan.hdg_skeleton_transpose(kt)
-    et = torch.empty(plan.n_skel, dtype=torch.float64, device=plan.device)
-    plan.hdg_adjoint_rhs(fw, et, fq=fq)
-    lamt = torch.zeros_like(et)
-    import ctypes as C
-    it, rr = C.c_int32(0), C.c_double(0.0)
-    st = plan.lib.hdg_skeleton_solve(plan.handle, kt.data_ptr(), et.data_ptr(), lamt.data_ptr(), 1e-13, 30, 100000,
-                                     plan.ws.data_ptr(), None, C.byref(it), C.byref(rr))
-    assert st == 0
-    _, lt, _ = O.adjoint_hybridized(step, F)
+    _say(f"adjoint {which}")
+    case, step, F, plan, w, lam, q, fw, fq = _setup(hdg, which)
+    Ut, lt, _ = O.adjoint_hybridized(step, F)
+    lamt, wt, eta, it, qt = plan.hdg_adjoint_solve(w, lam, fw, q=q, fq=fq, rtol=1e-13)
+    _say(f"  gmres iterations on K^T: {it}")
     assert O.relative_error(lamt.cpu().numpy(), lt) < 1e-10
-    wt = torch.zeros_like(w)
-    eta = torch.zeros(case.n_elements, dtype=torch.float64, device=plan.device)
-    with pytest.raises(hdg.HdgError):
-        plan.hdg_adjoint_local(w, lam, fw, lamt, wt, eta)
+    npm = case.W.shape[2]
+    rw, rq = np.zeros((case.n_elements, 4, npm)), np.zeros((case.n_elements, 8, npm))
+    for e in range(case.n_elements):
+        npe = hi.n_modes(int(case.degree[e]))
+        rq[e, :, :npe] = Ut[e][: 8 * npe].reshape(8, npe)
+        rw[e, :, :npe] = Ut[e][8 * npe:].reshape(4, npe)
+    assert O.relative_error(wt.cpu().numpy(), rw) < 1e-10
+    assert O.relative_error(qt.cpu().numpy(), rq) < 1e-10
+    assert O.relative_error(eta.cpu().numpy(), O.element_indicators(step, Ut)) < 1e-9
+    # the local solves alone, from the oracle's skeleton adjoint
+    lt_d = torch.tensor(lt, device=plan.device)
+    wt2, qt2 = torch.zeros_like(w), torch.zeros_like(q)
+    eta2 = torch.zeros(case.n_elements, dtype=torch.float64, device=plan.device)
+    st = torch.zeros(case.n_elements, dtype=torch.int32, device=plan.device)
+    plan.hdg_adjoint_local(w, lam, fw, lt_d, wt2, eta2, q=q, fq=fq, qt=qt2, elem_status=st)
+    assert O.relative_error(wt2.cpu().numpy(), rw) < 1e-11
+    assert O.relative_error(qt2.cpu().numpy(), rq) < 1e-11
+    assert O.relative_error(eta2.cpu().numpy(), O.element_indicators(step, Ut)) < 1e-10
 
 
 @pytest.mark.parametrize("which", ["c1", "hp"])
