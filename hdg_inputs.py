@@ -70,6 +70,8 @@ class Case:
     prandtl: float = 0.72
     gamma: float = GAMMA
     cfl: float = 0.0                # pseudo-time CFL number; 0 = pure Newton
+    sc_eps0: float = 0.0            # shock-capturing factor epsilon_0; 0 = off
+    sc_beta: float = 0.0            # shock-capturing exponent beta
     W: Optional[np.ndarray] = None
     Q: Optional[np.ndarray] = None
     lam: Optional[np.ndarray] = None

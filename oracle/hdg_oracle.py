@@ -13,6 +13,8 @@ What it computes, in the paper's order (Woopen, Balan, May, Schuetz, 2013):
   * Sec. 3.3, eq. linearsystem: the Newton Jacobian, obtained here by
     complex-step differentiation of the element-local residual map (independent
     of any hand-derived Jacobian);
+  * Sec. 3.2, optional shock capturing: the volume term (grad phi, eps_K grad w_h)
+    with the element viscosity eps_K from the L1 norm of the strong residual;
   * Sec. 3.3, optional backward-Euler pseudo-time term: the element mass
     matrix over a local step dt_K (CFL number times |K| over the element's
     convective and viscous wave-speed sums at its mean state) added to the
@@ -46,6 +48,9 @@ written separately):
   * boundary term of the gradient equation with a minus sign, like the interior
     trace term, so that q = grad w is reproduced; q_bnd = q_h;
   * constant viscosity mu = rho_inf |v_inf| L / Re, heat flux (mu gamma/Pr) grad e.
+  * shock capturing (Euler): h_K the element's longest edge, h~ = h_K / p_K;
+    the strong residual div f_c(w_h) by the chain rule at the volume points;
+    eps_K held fixed in the Newton matrix (evaluated at the current state);
   * pseudo-time step: dt_K = CFL |K| / (lambda_c + 4 lambda_v) with
     lambda_c = sum_e (|v.n| + c)|e| and lambda_v = (mu gamma / (rho Pr))
     sum_e |e|^2 / |K|, both at the integral mean of w_h over K (the paper
@@ -163,6 +168,8 @@ class Physics:
     mu: float = 0.0
     prandtl: float = 0.72
     cfl: float = 0.0   # pseudo-time CFL number (Sec. 3.3); 0 = pure Newton
+    sc_eps0: float = 0.0   # shock-capturing factor epsilon_0 (Sec. 3.2); 0 = off
+    sc_beta: float = 0.0   # shock-capturing exponent beta
 
 
 def make_physics(case, alpha: Optional[float] = None) -> Physics:
@@ -175,7 +182,8 @@ def make_physics(case, alpha: Optional[float] = None) -> Physics:
     mu = 0.0
     if case.physics == "ns":
         mu = winf[0] * speed * 1.0 / case.reynolds
-    return Physics(case.physics, case.gamma, winf, alpha, mu, case.prandtl, getattr(case, "cfl", 0.0))
+    return Physics(case.physics, case.gamma, winf, alpha, mu, case.prandtl, getattr(case, "cfl", 0.0),
+                   getattr(case, "sc_eps0", 0.0), getattr(case, "sc_beta", 0.0))
 
 
 def euler_flux(w, gamma):
@@ -363,6 +371,28 @@ class Mesh:
 # Element-local residual (eq. hdg_ls1 .. hdg_cont), batched and complex-safe
 # ---------------------------------------------------------------------------
 
+def shock_viscosity(mesh: Mesh, e: int, W: np.ndarray) -> float:
+    """Artificial viscosity of Sec. 3.2 (shock capturing): eps_K = eps_0 h~^(2 - beta) / |K|
+    int_K d(w), with d(w) = sum over the components of |div f_c(w)| (the strong convective
+    residual, by the chain rule from the flux Jacobians and the gradient of w_h) and
+    h~ = h_K / p_K, h_K the element's longest edge. W: (4, Np) real coefficients."""
+    phys = mesh.phys
+    if phys.sc_eps0 <= 0.0:
+        return 0.0
+    g = mesh.geom(e)
+    wq = W @ g.phi                                   # (4, Q)
+    gw = np.einsum("an,dnq->dqa", W, g.dphi)         # (2, Q, 4) physical gradient
+    d = np.zeros(wq.shape[1])
+    for q in range(wq.shape[1]):
+        div = (normal_flux_jacobian(wq[:, q], (1.0, 0.0), phys.gamma) @ gw[0, q]
+               + normal_flux_jacobian(wq[:, q], (0.0, 1.0), phys.gamma) @ gw[1, q])
+        d[q] = np.sum(np.abs(div))
+    area = float(np.sum(g.wq))
+    h = max(sd.length for sd in g.sides)
+    ht = h / int(mesh.case.degree[e])
+    return phys.sc_eps0 * ht ** (2.0 - phys.sc_beta) / area * float(g.wq @ d)
+
+
 def element_residual(mesh: Mesh, e: int, W, Q, lam_faces):
     """Residual of element e.
 
@@ -381,6 +411,13 @@ def element_residual(mesh: Mesh, e: int, W, Q, lam_faces):
         F = F - viscous_flux(wq, qq, phys)
     # volume term: -(grad phi_i, F)
     Rw = -np.einsum("q,dnq,dbqa->ban", g.wq, g.dphi, F)
+    if phys.sc_eps0 > 0.0:
+        # shock capturing, volume term only: (grad phi_i, eps grad w_h). eps is evaluated at the
+        # real part of the state: the Newton matrix holds it fixed (the paper leaves the
+        # linearisation of the non-smooth |.| open)
+        eps = shock_viscosity(mesh, e, np.asarray(W[0]).real)
+        gw = np.einsum("ban,dnq->bdqa", W, g.dphi)
+        Rw = Rw + eps * np.einsum("q,dnq,bdqa->ban", g.wq, g.dphi, gw)
     Rq = None
     if ns:
         # (tau, q) + (div tau, w)
