@@ -37,7 +37,8 @@ class HDGPlan:
 
     def __init__(self, xy, tri, degree, physics: str = "euler", mach: float = 0.5, aoa_deg: float = 0.0,
                  reynolds: float = 0.0, prandtl: float = 0.72, gamma: float = 1.4, precision: str = "fp64",
-                 alpha: float = 0.0, device: int = 0, allocate: bool = True, cfl: float = 0.0):
+                 alpha: float = 0.0, device: int = 0, allocate: bool = True, cfl: float = 0.0,
+                 sc_eps0: float = 0.0, sc_beta: float = 0.0):
         import torch
         self.lib = load()
         self.device = torch.device("cuda", device)
@@ -47,7 +48,7 @@ class HDGPlan:
         self.physics = physics
         self.precision = precision
         prm = HdgParams(HDG_NS if physics == "ns" else HDG_EULER, HDG_MIXED if precision == "mixed" else HDG_FP64,
-                        gamma, mach, math.radians(aoa_deg), reynolds, prandtl, alpha, cfl)
+                        gamma, mach, math.radians(aoa_deg), reynolds, prandtl, alpha, cfl, sc_eps0, sc_beta)
         h = C.c_void_p()
         check(self.lib.hdg_plan_create(C.byref(h), xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],
                                        deg.ctypes.data, C.byref(prm), device))
@@ -85,7 +86,8 @@ class HDGPlan:
                   allocate: bool = True) -> "HDGPlan":
         return cls(case.xy, case.tri, case.degree, physics=case.physics, mach=case.mach, aoa_deg=case.aoa_deg,
                    reynolds=case.reynolds, prandtl=case.prandtl, gamma=case.gamma, precision=precision,
-                   alpha=alpha, device=device, allocate=allocate, cfl=getattr(case, "cfl", 0.0))
+                   alpha=alpha, device=device, allocate=allocate, cfl=getattr(case, "cfl", 0.0),
+                   sc_eps0=getattr(case, "sc_eps0", 0.0), sc_beta=getattr(case, "sc_beta", 0.0))
 
     def __del__(self):
         h = getattr(self, "handle", None)

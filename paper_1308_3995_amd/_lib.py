@@ -27,7 +27,7 @@ EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_patt
 class HdgParams(C.Structure):
     _fields_ = [("physics", C.c_int32), ("precision", C.c_int32), ("gamma", C.c_double), ("mach", C.c_double),
                 ("aoa_rad", C.c_double), ("reynolds", C.c_double), ("prandtl", C.c_double),
-                ("stab_alpha", C.c_double), ("cfl", C.c_double)]
+                ("stab_alpha", C.c_double), ("cfl", C.c_double), ("sc_eps0", C.c_double), ("sc_beta", C.c_double)]
 
 
 class HdgSizes(C.Structure):

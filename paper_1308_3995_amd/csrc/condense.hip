@@ -55,6 +55,8 @@ struct CondArgs {
     double winf[4];
     double alpha, gamma;
     double cfl;           // pseudo-time CFL number (0: pure Newton)
+    double sc_eps0;       // shock-capturing factor epsilon_0 (0: off)
+    double sc_beta;       // shock-capturing exponent beta
 };
 
 // Convective flux f_x, f_y and Jacobians A_x = df_x/dw, A_y = df_y/dw (row-major 4x4)
@@ -113,9 +115,17 @@ struct ElemShared {
     double sFH[3][QF][4];
 };
 
-template <int P, int PF>
-__device__ __forceinline__ void point_data(const CondArgs& a, const ElemInfo* E, ElemShared<P, PF>& sh, int tid,
-                                           int nth) {
+// Shock-capturing scratch of one element, 9 Q + 1 doubles in a kernel's staging area:
+// reference gradients of w at the volume points [q][r][field], the points' |J| w_q d(w), and
+// the element's artificial viscosity eps_K last (0 when the term is off).
+template <int P>
+constexpr int sc_scratch_doubles() { return 9 * n_vol_q(P) + 1; }
+
+// SC: the kernel carries the shock-capturing code (the plan's sc_eps0 > 0); without it the
+// kernels compile exactly as before the term existed.
+template <int P, int PF, bool SC>
+__device__ __forceinline__ void point_data(const CondArgs& a, const ElemInfo* E, ElemShared<P, PF>& sh,
+                                           double* scb, int tid, int nth) {
     constexpr int NP = n_modes(P);
     constexpr int NPF = PF + 1;
     constexpr int Q = n_vol_q(P);
@@ -230,7 +240,45 @@ __device__ __forceinline__ void point_data(const CondArgs& a, const ElemInfo* E,
         }
     }
     __syncthreads();
-
+    // shock capturing: eps_K = eps_0 (h_K / p_K)^(2 - beta) / |K| int_K d(w), h_K the longest
+    // edge, d(w) = sum_i |(A_x w_x + A_y w_y)_i| at the volume points. With the reference
+    // gradients g_r of w_h, |J| w_q (A_x w_x + A_y w_y) = sK[q][0] g_0 + sK[q][1] g_1. The
+    // points' contributions are summed in order by one thread.
+    if constexpr (SC) {
+      if (a.sc_eps0 > 0.0) {
+        for (int q = tid; q < Q; q += nth) {
+            double gr[2][4];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int fa = 0; fa < 4; ++fa) {
+                    double s = 0.0;
+                    for (int i = 0; i < NP; ++i) s += a.vgrad[(r * Q + q) * NP + i] * sW[fa * NP + i];
+                    gr[r][fa] = s;
+                    scb[(q * 2 + r) * 4 + fa] = s;
+                }
+            double d = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v += sK[q][0][i * 4 + c] * gr[0][c] + sK[q][1][i * 4 + c] * gr[1][c];
+                d += fabs(v);
+            }
+            scb[8 * Q + q] = d;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int q = 0; q < Q; ++q) s += scb[8 * Q + q];
+            const double h = fmax(E->len[0], fmax(E->len[1], E->len[2])) / P;
+            scb[9 * Q] = a.sc_eps0 * pow(h, 2.0 - a.sc_beta) / (2.0 * E->detj) * s;
+        }
+        __syncthreads();
+      } else if (tid == 0) {
+        scb[9 * Q] = 0.0;
+      }
+    }
 }
 
 // Face tables of one element for the skeleton rows, built once per element in LDS:
@@ -348,10 +396,10 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
 // linearised): volume term from the weighted flux Jacobians, face terms from the trace-flux
 // Jacobians in w, and the pseudo-time shift sig on the diagonal. Columns past Np stay zero.
 // sVg: basis gradients [r][q][i]; sFp: the element's basis at its face points [lf][g][i].
-template <int P, int PF, int NPW>
+template <int P, int PF, int NPW, bool SC>
 __device__ __forceinline__ void a_row_entries(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
-                                              const double* sVg, const double* sFp, int fa, int ii, int b, int j0,
-                                              double sig, double (&out)[NPW]) {
+                                              const double* sVg, const double* sFp, const double* scb, int fa,
+                                              int ii, int b, int j0, double sig, double (&out)[NPW]) {
     constexpr int NP = n_modes(P), Q = n_vol_q(P), QF = PF + 2;
 #pragma unroll
     for (int j = 0; j < NPW; ++j) out[j] = 0.0;
@@ -379,12 +427,31 @@ __device__ __forceinline__ void a_row_entries(const CondArgs& a, const ElemInfo*
         for (int j = 0; j < NPW; ++j)
             if (j0 + j == ii) out[j] += sig;
     }
+    // shock capturing with the viscosity held fixed: eps_K (grad phi_i, grad phi_j) in the
+    // field's own block; grad phi . grad phi through the metric G = J^-1 J^-T
+    if constexpr (SC) {
+      const double eps = scb[9 * Q];
+      if (eps > 0.0 && fa == b) {
+        const double* ji = E->jinv;
+        const double g00 = ji[0] * ji[0] + ji[1] * ji[1], g01 = ji[0] * ji[2] + ji[1] * ji[3];
+        const double g11 = ji[2] * ji[2] + ji[3] * ji[3];
+        for (int q = 0; q < Q; ++q) {
+            const double wgt = eps * a.vw[q] * E->detj;
+            const double a0 = sVg[q * NP + ii], a1 = sVg[(Q + q) * NP + ii];
+            const double t0 = wgt * (g00 * a0 + g01 * a1), t1 = wgt * (g01 * a0 + g11 * a1);
+#pragma unroll
+            for (int j = 0; j < NPW; ++j)
+                if (j0 + j < NP) out[j] += t0 * sVg[q * NP + j0 + j] + t1 * sVg[(Q + q) * NP + j0 + j];
+        }
+      }
+    }
 }
 
-// Entry (fa, ii) of the element right-hand side r_K = -R_K (eq. hdg_ls2).
-template <int P, int PF>
-__device__ __forceinline__ double r_entry(const ElemInfo* E, const ElemShared<P, PF>& sh, const double* sVg,
-                                          const double* sFp, int fa, int ii) {
+// Entry (fa, ii) of the element right-hand side r_K = -R_K (eq. hdg_ls2), with the
+// shock-capturing term -eps_K (grad phi_ii, grad w_fa) when it is on.
+template <int P, int PF, bool SC>
+__device__ __forceinline__ double r_entry(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
+                                          const double* sVg, const double* sFp, const double* scb, int fa, int ii) {
     constexpr int NP = n_modes(P), Q = n_vol_q(P), QF = PF + 2;
     double v = 0.0;
     for (int q = 0; q < Q; ++q) {
@@ -395,6 +462,20 @@ __device__ __forceinline__ double r_entry(const ElemInfo* E, const ElemShared<P,
     for (int l2 = 0; l2 < 3; ++l2) {
         const double* fp = sFp + l2 * QF * NP;
         for (int g = 0; g < E->pe[l2] + 2; ++g) v -= fp[g * NP + ii] * sh.sFH[l2][g][fa];
+    }
+    if constexpr (SC) {
+      const double eps = scb[9 * Q];
+      if (eps > 0.0) {
+        const double* ji = E->jinv;
+        const double g00 = ji[0] * ji[0] + ji[1] * ji[1], g01 = ji[0] * ji[2] + ji[1] * ji[3];
+        const double g11 = ji[2] * ji[2] + ji[3] * ji[3];
+        double s = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            const double a0 = sVg[q * NP + ii], a1 = sVg[(Q + q) * NP + ii];
+            s += a.vw[q] * ((g00 * a0 + g01 * a1) * scb[(q * 2) * 4 + fa] + (g01 * a0 + g11 * a1) * scb[(q * 2 + 1) * 4 + fa]);
+        }
+        v -= eps * E->detj * s;
+      }
     }
     return v;
 }
@@ -410,7 +491,7 @@ struct EulerShape {
 
 // MINW is the register budget's target in waves per SIMD (4: 128 VGPRs, 2: 256); both are
 // built and the faster one per bucket is picked by timing on the plan's first call.
-template <int P, int PF, bool DBG, int MINW>
+template <int P, int PF, bool DBG, int MINW, bool SC>
 __global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_condense_euler(CondArgs a) {
     constexpr int NP = n_modes(P);
@@ -440,13 +521,14 @@ void k_condense_euler(CondArgs a) {
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
     if (tid == 0) sBad = 0;
-    point_data<P, PF>(a, E, sh, tid, NTH);
     // reference tables staged in the (not yet used) sX area: basis gradients [r][q][i] and the
-    // element's basis at its face points [lf][g][i]
+    // element's basis at its face points [lf][g][i]; then the shock-capturing scratch
     constexpr int QF = PF + 2;
-    static_assert(2 * Q * NP + 3 * QF * NP <= (F + 1) * N, "table staging fits in sX");
+    static_assert(2 * Q * NP + 3 * QF * NP + sc_scratch_doubles<P>() <= (F + 1) * N, "table staging fits in sX");
     double* sVg = sX;
     double* sFp = sX + 2 * Q * NP;
+    double* sScb = sFp + 3 * QF * NP;
+    point_data<P, PF, SC>(a, E, sh, sScb, tid, NTH);
     for (int t = tid; t < 2 * Q * NP; t += NTH) sVg[t] = a.vgrad[t];
     for (int t = tid; t < 3 * QF * NP; t += NTH) {
         const int lf = t / (QF * NP), g = (t / NP) % QF, i = t % NP;
@@ -472,7 +554,7 @@ void k_condense_euler(CondArgs a) {
         const int rr = row < N ? row : N - 1;
         const int fa = rr / NP, ii = rr % NP;
         // ---- A_K columns (field fld, modes part NPW + jj); columns past Np are padding
-        a_row_entries<P, PF, NPW>(a, E, sh, sVg, sFp, fa, ii, fld, part * NPW, sig, mA[h]);
+        a_row_entries<P, PF, NPW, SC>(a, E, sh, sVg, sFp, sScb, fa, ii, fld, part * NPW, sig, mA[h]);
         // ---- B_K / r_K columns cb = wave * NBW + i (cb < F: face lf, field b, mode k; cb = F: r_K)
 #pragma unroll
         for (int i = 0; i < NBW; ++i) {
@@ -486,7 +568,7 @@ void k_condense_euler(CondArgs a) {
                     for (int g = 0; g < pe + 2; ++g) v += fp[g * NP + ii] * sJB[lf][g][fa * 4 + b] * ft.ps[lf][g][k];
                 }
             } else if (cb == F) {
-                v = r_entry<P, PF>(E, sh, sVg, sFp, fa, ii);
+                v = r_entry<P, PF, SC>(a, E, sh, sVg, sFp, sScb, fa, ii);
             }
             mB[h][i] = v;
         }
@@ -615,12 +697,19 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.fphi = p.d_tab + p.tix.face_phi[P];
     a.start = bk.start;
     constexpr int nth = 64 * EulerShape<P>::NW;
-    if (dbg)
-        hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4>), dim3(bk.count), dim3(nth), 0, s, a);
-    else if (variant == 1)
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2>), dim3(bk.count), dim3(nth), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4>), dim3(bk.count), dim3(nth), 0, s, a);
+    if (a.sc_eps0 > 0.0) {
+        // shock capturing on: one register budget (both tuning variants launch it)
+        if (dbg)
+            hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, true>), dim3(bk.count), dim3(nth), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, true>), dim3(bk.count), dim3(nth), 0, s, a);
+    } else if (dbg) {
+        hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, false>), dim3(bk.count), dim3(nth), 0, s, a);
+    } else if (variant == 1) {
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, false>), dim3(bk.count), dim3(nth), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, false>), dim3(bk.count), dim3(nth), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -720,6 +809,8 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
     a.alpha = p.alpha;
     a.gamma = p.prm.gamma;
     a.cfl = p.prm.cfl;
+    a.sc_eps0 = p.prm.sc_eps0;
+    a.sc_beta = p.prm.sc_beta;
     for (const Bucket& bk : p.buckets)
         if (!bucket_supported(bk)) return hipErrorInvalidValue;
     if (!debug && !p.tuned) {
@@ -849,7 +940,7 @@ __global__ __launch_bounds__(64 * EulerShape<P>::NW) void k_adjoint_euler(CondAr
     constexpr int NPW = (NP + WPF - 1) / WPF;
     constexpr int Q = n_vol_q(P);
     constexpr int QF = PF + 2;
-    constexpr int STAGE = 2 * Q * NP + 3 * QF * NP;
+    constexpr int STAGE = 2 * Q * NP + 3 * QF * NP + sc_scratch_doubles<P>();
     constexpr int SA = STAGE > N * N ? STAGE : N * N;
 
     __shared__ ElemShared<P, PF> sh;
@@ -868,9 +959,10 @@ __global__ __launch_bounds__(64 * EulerShape<P>::NW) void k_adjoint_euler(CondAr
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
     if (tid == 0) sBad = 0;
-    point_data<P, PF>(a, E, sh, tid, NTH);
     double* sVg = sT;
     double* sFp = sT + 2 * Q * NP;
+    double* sScb = sFp + 3 * QF * NP;
+    point_data<P, PF, true>(a, E, sh, sScb, tid, NTH);
     for (int t = tid; t < 2 * Q * NP; t += NTH) sVg[t] = a.vgrad[t];
     for (int t = tid; t < 3 * QF * NP; t += NTH) {
         const int lf = t / (QF * NP), g = (t / NP) % QF, i = t % NP;
@@ -894,7 +986,7 @@ __global__ __launch_bounds__(64 * EulerShape<P>::NW) void k_adjoint_euler(CondAr
     // r_K and the right-hand side; C_K = alpha T acts field by field (trace mass)
     for (int r = tid; r < N; r += NTH) {
         const int fa = r / NP, ii = r % NP;
-        sR[r] = r_entry<P, PF>(E, sh, sVg, sFp, fa, ii);
+        sR[r] = r_entry<P, PF, true>(a, E, sh, sVg, sFp, sScb, fa, ii);
         double ct = 0.0;
 #pragma unroll
         for (int lf = 0; lf < 3; ++lf)
@@ -908,7 +1000,7 @@ __global__ __launch_bounds__(64 * EulerShape<P>::NW) void k_adjoint_euler(CondAr
     for (int h = 0; h < RH; ++h) {
         const int row = h * 64 + lane;
         const int rr = row < N ? row : N - 1;
-        a_row_entries<P, PF, NPW>(a, E, sh, sVg, sFp, rr / NP, rr % NP, fld, part * NPW, sig, mA[h]);
+        a_row_entries<P, PF, NPW, true>(a, E, sh, sVg, sFp, sScb, rr / NP, rr % NP, fld, part * NPW, sig, mA[h]);
     }
     __syncthreads();   // the tables in sT are no longer read
 #pragma unroll
@@ -1018,6 +1110,8 @@ hipError_t launch_adjoint_local(Plan& p, const double* w, const double* lam, con
     a.alpha = p.alpha;
     a.gamma = p.prm.gamma;
     a.cfl = p.prm.cfl;
+    a.sc_eps0 = p.prm.sc_eps0;
+    a.sc_beta = p.prm.sc_beta;
     for (const Bucket& bk : p.buckets) {
         if (!bucket_supported(bk)) return hipErrorInvalidValue;
 #define HDG_CASE(PP, FF)                                                                                        \

@@ -215,6 +215,54 @@ def test_pseudo_time_step_matches_oracle(hdg, which):
     assert rel(dw.cpu().numpy(), ref) < 1e-10
 
 
+@pytest.mark.parametrize("which", ["hp", "hp5"])
+def test_shock_capturing_matches_oracle(hdg, which):
+    """Shock capturing of Sec. 3.2 (epsilon_0 = 0.2, beta = 0) on a strongly perturbed state:
+    element blocks, condensation and the full Newton update agree with the oracle."""
+    import torch
+    case = (hi.make_case("euler", 4, [1, 2, 3, 4], 0.8, 1.25, 8e-2, seed=43) if which == "hp"
+            else hi.make_case("euler", 3, [3, 4, 5], 0.8, 1.25, 8e-2, seed=44))
+    case.sc_eps0 = 0.2
+    _say(f"shock capturing {which}")
+    step = O.newton_step(case)
+    eps = [O.shock_viscosity(step.mesh, e, case.W[e, :, :hi.n_modes(int(case.degree[e]))])
+           for e in range(case.n_elements)]
+    assert max(eps) > 1e-4
+    plan = hdg.HDGPlan.from_case(case)
+    w, lam = _device_state(hdg, plan, case)
+    for e in range(0, case.n_elements, max(1, case.n_elements // 10)):
+        gb = plan.debug_element_blocks(e, w, lam)
+        ob = step.blocks[e]
+        assert rel(gb["A"], ob.A) < TOL, (e, rel(gb["A"], ob.A))
+        assert rel(gb["r"], ob.r) < tol_resid(ob.A), (e, rel(gb["r"], ob.r))
+    plan.hdg_assemble_condense(w, lam)
+    torch.cuda.synchronize()
+    for e in range(case.n_elements):
+        X, y = plan.debug_local_solution(e)
+        c = step.cond[e]
+        assert rel(y, c.y) < tol_resid(step.blocks[e].A), (e, rel(y, c.y))
+        if c.X.size:
+            assert rel(X, c.X) < TOL, (e, rel(X, c.X))
+    assert rel(plan.skeleton_matrix_dense(), step.K.toarray()) < TOL
+    assert rel(plan.rhs.cpu().numpy(), step.E) < tol_resid(np.eye(2))
+    dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=plan.device)
+    plan.hdg_skeleton_solve(dlam, rtol=1e-13, restart=30)
+    dw = torch.zeros_like(w)
+    plan.hdg_back_substitute(dlam, dw)
+    ref = np.zeros_like(case.W)
+    for e in range(case.n_elements):
+        ref[e], _ = O.unpack_local(step.mesh, e, step.du[e], case.W.shape[2])
+    assert rel(dlam.cpu().numpy(), step.dlam) < 1e-10
+    assert rel(dw.cpu().numpy(), ref) < 1e-10
+
+
+def test_shock_capturing_is_refused_for_navier_stokes(hdg):
+    case = hi.make_case("ns", 3, [2, 3], 0.5, 1.0, 2e-2, seed=21, reynolds=200.0)
+    case.sc_eps0 = 0.2
+    with pytest.raises(hdg.HdgError):
+        hdg.HDGPlan.from_case(case)
+
+
 def test_free_stream_gives_zero_rhs(hdg):
     """A uniform free stream is a discrete steady state: E = 0 and the local right-hand sides vanish."""
     import torch
