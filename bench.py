@@ -9,7 +9,8 @@ A step is the whole hot path: assemble + condense (hdg_assemble_condense), block
 GMRES on the skeleton (hdg_skeleton_solve) to a relative residual of 1e-10, and
 back-substitution (hdg_back_substitute). Both precision modes are timed; the reported
 `value` is condensed elements per second of full Newton steps of the mixed mode.
-Beside the step: assemble + condense alone on three workloads (`condensation`), the
+Beside the step: assemble + condense alone on three workloads (`condensation`), and with shock
+capturing on the transonic hp workload (`condensation_shock_capturing`), the
 relaxed Newton iteration with the pseudo-time CFL schedule run to convergence
 (`pseudo_transient`), the hybridized adjoint at one degree more with the marking decisions
 (`adjoint`), a sample of the serving stream (`serving`) and the CPU oracle (`cpu_baseline`).
@@ -135,15 +136,18 @@ def measured_copy_peak(reps: int = 5) -> float:
     return 2.0 * n * 8 / (best * 1e-3) / 1e9
 
 
-def condensation_report(names, warmup: int = 5, reps: int = 30):
+def condensation_report(names, warmup: int = 5, reps: int = 30, sc_eps0: float = 0.0):
     """Assemble + condense time of each named workload (float64 path), with its roofline:
-    `warmup` untimed calls, then the median and p99 of `reps` individually timed calls."""
+    `warmup` untimed calls, then the median and p99 of `reps` individually timed calls.
+    sc_eps0 > 0 switches shock capturing on (Euler workloads; its extra work is not counted
+    in the roofline's algorithmic figures)."""
     import torch
     import hdg_inputs as hi
     import paper_1308_3995_amd as hdg
     out = {}
     for name in names:
         case = hi.config_case(name)
+        case.sc_eps0 = sc_eps0
         plan = hdg.HDGPlan.from_case(case, precision="fp64")
         dev = plan.device
         w = torch.tensor(case.W, dtype=torch.float64, device=dev)
@@ -171,7 +175,10 @@ def condensation_report(names, warmup: int = 5, reps: int = 30):
                      "algorithmic_gflop": fl / 1e9, "algorithmic_gb": by / 1e9,
                      "achieved_tflops": fl / (ms * 1e-3) / 1e12, "achieved_gbs": by / (ms * 1e-3) / 1e9,
                      "bound": "fp64" if t_f >= t_b else "hbm", "roofline_frac": max(t_f, t_b) / (ms * 1e-3)}
-        log(f"[bench] condensation {name}: {ms:.3f} ms, {case.n_elements / ms / 1e3:.2f} M elements/s, "
+        tag = f" with shock capturing (eps_0 {sc_eps0:g})" if sc_eps0 > 0 else ""
+        if sc_eps0 > 0:
+            out[name]["shock_capturing_eps0"] = sc_eps0
+        log(f"[bench] condensation {name}{tag}: {ms:.3f} ms, {case.n_elements / ms / 1e3:.2f} M elements/s, "
             f"roofline {out[name]['roofline_frac']:.3f} ({out[name]['bound']})")
         del plan
         torch.cuda.synchronize()
@@ -283,6 +290,8 @@ def main():
                     help="GMRES iterations per serving request before it counts as not converged")
     ap.add_argument("--condense-configs", default="c2,c3,c4",
                     help="workloads whose assemble + condense time is reported beside the step ('' = none)")
+    ap.add_argument("--shock-configs", default="c3",
+                    help="workloads whose assemble + condense is also timed with shock capturing on ('' = none)")
     ap.add_argument("--newton-loop", default="c2",
                     help="workload of the pseudo-transient Newton iteration report ('' = none)")
     ap.add_argument("--adjoint", default="c2",
@@ -411,6 +420,9 @@ def main():
                        "bytes_per_launch": kb / max(1, kl)}
     if args.condense_configs:
         out["condensation"] = condensation_report([c for c in args.condense_configs.split(",") if c])
+    if args.shock_configs:
+        out["condensation_shock_capturing"] = condensation_report(
+            [c for c in args.shock_configs.split(",") if c], sc_eps0=0.2)
     if args.newton_loop:
         out["pseudo_transient"] = newton_loop_report(args.newton_loop, args.rtol, args.restart)
     if args.adjoint:

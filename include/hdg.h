@@ -84,7 +84,8 @@ typedef struct {
     double sc_eps0;       /* shock capturing (Sec. 3.2, Euler only): the volume term
                              (grad phi, eps_K grad w_h) with eps_K = sc_eps0 (h_K / p_K)^(2 - sc_beta)
                              / |K| int_K sum_i |(div f_c(w_h))_i|, h_K the longest edge; eps_K is
-                             held fixed in the Newton matrix. 0 = off (the paper: 0.2); >= 0. */
+                             held fixed in the Newton matrix. 0 = off (the paper: 0.2); >= 0.
+                             hdg_plan_create refuses sc_eps0 > 0 for Navier-Stokes. */
     double sc_beta;       /* shock-capturing exponent beta (the paper: 0) */
 } hdg_params;
 
