@@ -13,6 +13,9 @@
  * sums S_K and g_K into the skeleton system K dLambda = E, solves it with
  * block-Jacobi preconditioned restarted GMRES, and reconstructs
  *     dU_K = A_K^-1 (r_K - B_K dLambda_K).
+ * Around that step: optional shock capturing and pseudo-time terms in the element blocks
+ * (hdg_params), the relaxed Newton iteration with its CFL schedule (Sec. 3.3), the
+ * hybridized adjoint with element indicators and the marking decisions of Sec. 4.
  *
  * Conventions shared by every call:
  *   - Pointers named *_dev are device pointers owned by the caller; the library
