@@ -25,6 +25,11 @@ def _case(which):
         return O.enrich(hi.config_case("c1"))
     if which == "hp":
         return hi.make_case("euler", 4, [1, 2, 3, 4], 0.6, 1.5, 2e-2, seed=3)
+    if which == "hp_shock":             # shock capturing and a pseudo-time step in the matrices
+        c = hi.make_case("euler", 4, [1, 2, 3, 4], 0.8, 1.25, 8e-2, seed=43)
+        c.sc_eps0 = 0.2
+        c.cfl = 5.0
+        return c
     if which == "ns14":
         return hi.make_case("ns", 3, [1, 2, 3, 4], 0.6, -2.0, 2e-2, seed=22, reynolds=500.0)
     return hi.make_case("ns", 3, [2, 3], 0.5, 1.0, 2e-2, seed=21, reynolds=200.0)
@@ -99,7 +104,7 @@ def test_local_adjoint_matches_oracle(hdg, which):
     assert O.relative_error(eta.cpu().numpy(), O.element_indicators(step, Ut)) < 1e-11
 
 
-@pytest.mark.parametrize("which", ["c1", "hp", "c1_enriched"])
+@pytest.mark.parametrize("which", ["c1", "hp", "c1_enriched", "hp_shock"])
 def test_adjoint_solve_matches_oracle(hdg, which):
     _say(f"adjoint solve {which}")
     case, step, F, plan, w, lam, q, fw, fq = _setup(hdg, which)
