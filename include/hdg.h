@@ -114,8 +114,11 @@ typedef struct hdg_plan hdg_plan;
  * basis and quadrature tables, and far-field projectors. Host inputs:
  *   xy_host[nv][2] vertex coordinates, tri_host[ne][3] vertex ids (counter-clockwise),
  *   degree_host[ne] element degrees in 1..5.
- * Allocates device memory on `device`; the plan is immutable afterwards and may be
- * used from several streams. Errors: HDG_ERR_INVALID_ARG (bad sizes, ids, degrees,
+ * Allocates device memory on `device`. The mesh data of a plan never change; a plan does
+ * cache the kernel variants its first assembly picks, captured launch graphs and the CFL
+ * of hdg_set_cfl, so calls on one plan must not overlap one another; different plans may
+ * be used at the same time from different host threads and streams. Errors:
+ * HDG_ERR_INVALID_ARG (bad sizes, ids, degrees,
  * an edge shared by more than two triangles), HDG_ERR_SINGULAR_LOCAL (a triangle of
  * non-positive area), HDG_ERR_OOM, HDG_ERR_HIP. */
 hdg_status hdg_plan_create(hdg_plan** out, const double* xy_host, int32_t nv,
