@@ -147,9 +147,10 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 //                 first one cancelled, ||w||^2 = ||y||^2 - ||h||^2 < ||y||^2 / 2 (the
 //                 "twice is enough" test of Daniel, Gragg, Kaufman and Stewart, 1976), and
 //                 then block partials of V^T w
-//   k_reduce_h    h2, H(:, j) += h2                              (skipped without pass 2)
-//   k_update_norm w = w - V h2 and block partials of ||w||^2 (pass 2 only; without it
-//                 k_update_dots leaves the partials of ||w||^2)
+//   k_update_norm pass 2 only: h2 = the sum of those partials (each block sums them itself,
+//                 block 0 adds h2 to H(:, j)), w = w - V h2 and block partials of ||w||^2;
+//                 without pass 2 it returns at once and k_update_dots has left the
+//                 partials of ||w||^2
 // The next step's k_spmv_dots takes ||w_j|| from the partials (scale = 1/||w_j||) and its
 // block 0 applies the Givens rotation of column j and updates the residual estimate and
 // the flags; k_cycle_end rotates the cycle's last column.
@@ -384,12 +385,10 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
     if ((lane & 7) == 0 && i <= cnt) a.P1[(int64_t)i * a.B1 + blockIdx.x] = r;
 }
 
-// h_i = sum_b P[i * B + b] (block i); H(i, j) = h_i or += h_i
-__global__ __launch_bounds__(kThreads) void k_reduce_h(GmArgs a, const double* P, int B, int cnt, int j,
-                                                       int accumulate) {
+// h_i = sum_b P[i * B + b] (block i); H(i, j) = h_i
+__global__ __launch_bounds__(kThreads) void k_reduce_h(GmArgs a, const double* P, int B, int cnt, int j) {
     __shared__ double sh[8];
     if (a.scal[SC_DONE] != 0.0) return;
-    if (accumulate && a.scal[SC_REORTH] == 0.0) return;
     const int i = blockIdx.x;
     const double* Pi = P + (int64_t)i * B;
     double v = 0.0;
@@ -399,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_h(GmArgs a, const double* P
         a.h[i] = t;
         if (i < cnt) {
             double* hc = a.H + (int64_t)j * kMaxV;
-            hc[i] = accumulate ? hc[i] + t : t;
+            hc[i] = t;
         }
     }
 }
@@ -471,15 +470,27 @@ __global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
     }
 }
 
-// w -= V h2, partials of ||w||^2
+// Second pass: h2 = sum of the blocks' partials of V^T w (every block sums them itself, in the
+// same fixed order, so all get the same bits; block 0 adds h2 to H(:, j)), w -= V h2, and the
+// partials of ||w||^2. Without a second pass the kernel returns at once.
 template <int CNT>
-__global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a) {
+__global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a, int j) {
     constexpr int cnt = CNT;
     __shared__ double sh[8];
     __shared__ double h[kMaxV];
     if (a.scal[SC_DONE] != 0.0 || a.scal[SC_REORTH] == 0.0) return;
-    if ((int)threadIdx.x < cnt) h[threadIdx.x] = a.h[threadIdx.x];
+    for (int i = 0; i < cnt; ++i) {
+        const double* Pi = a.P2 + (int64_t)i * a.B2;
+        double v = 0.0;
+        for (int b = threadIdx.x; b < a.B2; b += blockDim.x) v += Pi[b];
+        const double t = block_sum1(v, sh);
+        if (threadIdx.x == 0) h[i] = t;
+    }
     __syncthreads();
+    if (blockIdx.x == 0 && (int)threadIdx.x < cnt) {
+        double* hc = a.H + (int64_t)j * kMaxV;
+        hc[threadIdx.x] += h[threadIdx.x];
+    }
     const int64_t lo = (int64_t)blockIdx.x * a.chunk;
     const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     double nacc = 0.0;
@@ -649,10 +660,9 @@ static void launch_step(const GmArgs& a, const VT* hat, const double* src, int c
         if (e0) (void)hipEventRecord(e0, s);
         hipLaunchKernelGGL((k_spmv_dots<VT, C>), g1, blk, 0, s, a, hat, src);
         if (e1) (void)hipEventRecord(e1, s);
-        hipLaunchKernelGGL(k_reduce_h, dim3(C < kMaxRestart ? C + 1 : C), blk, 0, s, a, a.P1, a.B1, C, j, 0);
+        hipLaunchKernelGGL(k_reduce_h, dim3(C < kMaxRestart ? C + 1 : C), blk, 0, s, a, a.P1, a.B1, C, j);
         hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
-        hipLaunchKernelGGL(k_reduce_h, dim3(C), blk, 0, s, a, a.P2, a.B2, C, j, 1);
-        hipLaunchKernelGGL((k_update_norm<C>), g2, blk, 0, s, a);
+        hipLaunchKernelGGL((k_update_norm<C>), g2, blk, 0, s, a, j);
     }
 }
 
