@@ -855,6 +855,10 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
     double enorm = 0.0;
     hdg_status st = true_residual(p, S, bsr, rhs, dlam, s, &enorm);
     if (st != HDG_OK) return st;
+    if (!std::isfinite(enorm)) {
+        set_error("non-finite skeleton right-hand side");
+        return HDG_ERR_NONFINITE;
+    }
     if (enorm == 0.0) {
         if (iters_out) *iters_out = 0;
         if (relres_out) *relres_out = 0.0;
@@ -911,7 +915,7 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
                                S.u, dlam, 1);
             if (it == 0) break;
         }
-        if (relres > rtol) {
+        if (!(relres <= rtol)) {
             double tr = 0.0;
             st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
             if (st != HDG_OK) return st;
@@ -920,7 +924,11 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
     }
     if (iters_out) *iters_out = total;
     if (relres_out) *relres_out = relres;
-    if (relres > rtol) {
+    if (!std::isfinite(relres)) {
+        set_error("non-finite skeleton residual (non-finite skeleton matrix or a breakdown of the inner solve)");
+        return HDG_ERR_NONFINITE;
+    }
+    if (!(relres <= rtol)) {
         set_error("GMRES reached max_iter with relative residual " + std::to_string(relres));
         return HDG_ERR_NOT_CONVERGED;
     }

@@ -21,6 +21,9 @@ from typing import Callable, List, Optional
 
 import numpy as np
 
+# status of a request whose failure was not reported by the library (host-side exception)
+STATUS_HOST_FAILURE = -1
+
 
 @dataclass
 class ServeRequest:
@@ -44,6 +47,7 @@ class ServeResult:
     footprint_bytes: int
     dw: Optional[np.ndarray] = None
     dlam: Optional[np.ndarray] = None
+    phases: dict = field(default_factory=dict)   # seconds per phase: queue, condense, solve, back_substitute
 
     @property
     def latency_s(self) -> float:
@@ -58,17 +62,27 @@ class ServeStats:
     max_bytes_in_use: int = 0
 
     def summary(self) -> dict:
+        # latency percentiles over every request, failed ones included (a failure is a
+        # response too); the completed-only figures are reported beside them
         ok = [r for r in self.results if r.status == 0]
-        lat = np.array([r.latency_s for r in ok]) if ok else np.zeros(1)
+        lat_all = np.array([r.latency_s for r in self.results]) if self.results else np.zeros(1)
+        lat_ok = np.array([r.latency_s for r in ok]) if ok else np.zeros(1)
         ne = sum(r.elements for r in ok)
         nd = sum(r.skel_dofs for r in ok)
         failed = {}
         for r in self.results:
             if r.status != 0:
                 failed[r.status] = failed.get(r.status, 0) + 1
+        phase = {}
+        for name in ("queue", "condense", "solve", "back_substitute"):
+            v = np.array([r.phases.get(name, 0.0) for r in self.results]) if self.results else np.zeros(1)
+            phase[name] = {"p50_s": float(np.percentile(v, 50)), "p99_s": float(np.percentile(v, 99))}
         return {"requests": len(self.results), "completed": len(ok),
                 "failed_by_status": {int(k): v for k, v in sorted(failed.items())},
-                "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "p50_latency_s": float(np.percentile(lat_all, 50)), "p99_latency_s": float(np.percentile(lat_all, 99)),
+                "p50_latency_completed_s": float(np.percentile(lat_ok, 50)),
+                "p99_latency_completed_s": float(np.percentile(lat_ok, 99)),
+                "phase_latency": phase,
                 "elements_per_s": ne / self.wall_s if self.wall_s > 0 else 0.0,
                 "skeleton_dof_per_s": nd / self.wall_s if self.wall_s > 0 else 0.0,
                 "wall_s": self.wall_s, "max_concurrent": self.max_concurrent,
@@ -104,13 +118,14 @@ class ServingEngine:
         import torch
         from . import _lib
         case = req.case
-        stream = torch.cuda.Stream(device=self.device)
         dev = plan.device
-        plan.allocate()
+        phases = {"queue": admitted - req.arrival_s}
         status = 0
         it, rr = 0, float("nan")
         dw_h = dl_h = None
         try:
+            stream = torch.cuda.Stream(device=self.device)
+            plan.allocate()
             with torch.cuda.stream(stream):
                 w = torch.tensor(case.W, dtype=torch.float64, device=dev)
                 q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
@@ -118,19 +133,30 @@ class ServingEngine:
                 dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=dev)
                 dw = torch.zeros_like(w)
                 dq = torch.zeros_like(q) if q is not None else None
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                ev[0].record(stream)
                 plan.hdg_assemble_condense(w, lam, q=q, stream=stream)
+                ev[1].record(stream)
                 it, rr, status = plan.hdg_skeleton_solve(dlam, rtol=req.rtol, restart=self.restart,
                                                          max_iter=self.max_iter, stream=stream, raise_on_fail=False)
+                ev[2].record(stream)
                 plan.hdg_back_substitute(dlam, dw, dq, stream=stream)
+                ev[3].record(stream)
                 stream.synchronize()
+                phases = {"queue": admitted - req.arrival_s,
+                          "condense": ev[0].elapsed_time(ev[1]) * 1e-3,
+                          "solve": ev[1].elapsed_time(ev[2]) * 1e-3,
+                          "back_substitute": ev[2].elapsed_time(ev[3]) * 1e-3}
                 if self.keep:
                     dw_h = dw.cpu().numpy()
                     dl_h = dlam.cpu().numpy()
         except _lib.HdgError as e:      # a failed request is isolated: its slot is freed
             status = e.status
+        except Exception:               # e.g. a device allocation of the request's buffers failed
+            status = STATUS_HOST_FAILURE
         done = time.perf_counter() - t0
         return ServeResult(req.index, req.arrival_s, admitted, done, plan.ne, plan.n_skel, it, rr, status, fp,
-                           dw_h, dl_h)
+                           dw_h, dl_h, phases)
 
     def run(self, requests: List[ServeRequest], on_result: Optional[Callable[[ServeResult], None]] = None
             ) -> ServeStats:
@@ -170,8 +196,15 @@ class ServingEngine:
                 admitted = time.perf_counter() - t0
 
                 def job(req=req, plan=plan, admitted=admitted, fp=fp):
-                    res = self._solve(req, plan, t0, admitted, fp)
-                    finish(res, fp, plan)
+                    res = None
+                    try:
+                        res = self._solve(req, plan, t0, admitted, fp)
+                    finally:
+                        # the slot and its memory are released whatever happened to the request
+                        if res is None:
+                            res = ServeResult(req.index, req.arrival_s, admitted, time.perf_counter() - t0,
+                                              plan.ne, plan.n_skel, 0, float("nan"), STATUS_HOST_FAILURE, fp)
+                        finish(res, fp, plan)
                     return res
 
                 futures.append(pool.submit(job))
