@@ -171,11 +171,18 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
  * with right block-Jacobi preconditioning on the face-diagonal blocks and classical
  * Gram-Schmidt (a second pass when the first one cancels), all in float64 (HDG_MIXED: inner
  * solves on a float32 preconditioned matrix inside float64 iterative refinement).
- * Stops when ||E - K dLambda||_2 <= rtol ||E||_2 or after max_iter inner iterations.
- * Outputs dlambda_dev[n_skel_dof]; iters_out (total inner iterations) and relres_out
- * (true relative residual, recomputed in float64) may be NULL. Returns
+ * With a polynomial degree d >= 2 (hdg_set_poly_degree, default 20) the first restart cycle
+ * has d steps; the harmonic Ritz values of its Hessenberg matrix are the roots of a GMRES
+ * residual polynomial 1 - Khat p(Khat) of degree d (Khat = K M^-1, M the block-Jacobi
+ * matrix), and the later cycles run GMRES on Khat p(Khat) (a flexible update keeps
+ * p(Khat) v_j), d matrix applications per Arnoldi step. If the roots are unusable (a cycle
+ * converged or broke down first, a root at zero) the solve continues as plain GMRES.
+ * Stops when ||E - K dLambda||_2 <= rtol ||E||_2 or after max_iter applications of the
+ * preconditioned matrix. Outputs dlambda_dev[n_skel_dof]; iters_out (those applications)
+ * and relres_out (true relative residual, recomputed in float64) may be NULL. Returns
  * HDG_ERR_NOT_CONVERGED with the best iterate when max_iter is reached,
- * HDG_ERR_SINGULAR_LOCAL when a face-diagonal block is singular. Synchronises. */
+ * HDG_ERR_SINGULAR_LOCAL when a face-diagonal block is singular, HDG_ERR_NONFINITE when
+ * the right-hand side or the final residual is not finite. Synchronises. */
 hdg_status hdg_skeleton_solve(hdg_plan* plan, const double* bsr_values_dev, const double* rhs_dev,
                               double* dlambda_dev, double rtol, int32_t restart, int32_t max_iter,
                               void* workspace_dev, hipStream_t stream, int32_t* iters_out,
@@ -323,15 +330,30 @@ hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const doubl
 hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev, int64_t element,
                                     double* X_host, double* y_host, int32_t* n_out, int32_t* f_out);
 
-/* Profiling hook for benchmarks: when enabled, hdg_skeleton_solve brackets every launch
- * of its dominant kernel (the preconditioned SpMV fused with the first Gram-Schmidt dot
- * products) with HIP events on the caller's stream and accumulates the launch count, the
- * summed event time and the algorithmic bytes of those launches (matrix values, the
- * source, output and new basis vector, and the basis vectors read by the dot products).
- * hdg_kernel_timing returns and, if reset != 0, clears the totals. */
+/* Degree d of the GMRES polynomial preconditioner of hdg_skeleton_solve on this plan
+ * (0 or 1: plain block-Jacobi GMRES; at most 32). Errors: HDG_ERR_INVALID_ARG. */
+hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree);
+
+/* Profiling hook for benchmarks: when enabled, hdg_skeleton_solve launches its restart cycles
+ * directly (not from captured graphs) and brackets every launch of its two SpMV kernels with
+ * HIP events on the caller's stream, accumulating per kernel the launch count, the summed
+ * event time and the algorithmic bytes of those launches. kernel 0: the polynomial
+ * preconditioner's SpMV (matrix values, the source, the previous iterate for the second
+ * factor of a complex pair, the output vector and the running p(Khat) v_j); kernel 1: the
+ * SpMV fused with the first Gram-Schmidt dot products (matrix values, source, output, and the
+ * basis vectors the dot products read; plain GMRES also writes the new basis vector).
+ * hdg_kernel_timing returns kernel `kernel`'s totals and, if reset != 0, clears them. */
 hdg_status hdg_set_kernel_timing(hdg_plan* plan, int32_t enable);
-hdg_status hdg_kernel_timing(hdg_plan* plan, int64_t* launches, double* total_ms, double* total_bytes,
-                             int32_t reset);
+hdg_status hdg_kernel_timing(hdg_plan* plan, int32_t kernel, int64_t* launches, double* total_ms,
+                             double* total_bytes, int32_t reset);
+
+/* Inspection entry for tests, host only (no device work): the eigenvalues wr + i wi of a real
+ * upper Hessenberg matrix h_host[n][n] (row-major; entries below the subdiagonal are
+ * ignored), by the implicit double-shift QR iteration the polynomial preconditioner uses for
+ * its roots. Complex eigenvalues come in conjugate pairs, +imaginary part first. Errors:
+ * HDG_ERR_INVALID_ARG (n outside 1..64, null pointer), HDG_ERR_NOT_CONVERGED. */
+hdg_status hdg_debug_hessenberg_eigenvalues(int32_t n, const double* h_host, double* wr_host,
+                                            double* wi_host);
 
 /* Thread-local description of the last error of the calling thread. */
 const char* hdg_last_error(void);

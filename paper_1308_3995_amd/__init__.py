@@ -227,13 +227,20 @@ class HDGPlan:
                                          C.byref(m), _vp(self.ws), _stream(stream)))
         return flag[: self.ne], sensor[: self.ne], m.value
 
-    # ---- dominant-kernel timing (benchmarks)
+    # ---- skeleton-solver options and kernel timing (benchmarks)
+    def hdg_set_poly_degree(self, degree: int):
+        """Degree of the GMRES polynomial preconditioner (0 or 1: plain block-Jacobi GMRES)."""
+        check(self.lib.hdg_set_poly_degree(self.handle, int(degree)))
+
     def hdg_set_kernel_timing(self, enable: bool):
         check(self.lib.hdg_set_kernel_timing(self.handle, 1 if enable else 0))
 
-    def hdg_kernel_timing(self, reset: bool = True):
+    def hdg_kernel_timing(self, kernel: int = 0, reset: bool = True):
+        """(launches, total ms, algorithmic bytes) of kernel 0 (the polynomial preconditioner's
+        SpMV) or 1 (the SpMV fused with the Gram-Schmidt dots)."""
         n, ms, by = C.c_int64(0), C.c_double(0.0), C.c_double(0.0)
-        check(self.lib.hdg_kernel_timing(self.handle, C.byref(n), C.byref(ms), C.byref(by), 1 if reset else 0))
+        check(self.lib.hdg_kernel_timing(self.handle, int(kernel), C.byref(n), C.byref(ms), C.byref(by),
+                                         1 if reset else 0))
         return n.value, ms.value, by.value
 
     # ---- inspection (tests)
@@ -275,3 +282,14 @@ class HDGPlan:
                 blk = vals[voff[b]: voff[b] + sf * sg].reshape(sg, sf).T
                 K[self.face_offset[f]: self.face_offset[f + 1], self.face_offset[g]: self.face_offset[g + 1]] = blk
         return K
+
+
+def hessenberg_eigenvalues(h):
+    """Eigenvalues of a real upper Hessenberg matrix by the library's host QR iteration
+    (inspection entry for tests; no device work)."""
+    lib = load()
+    h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
+    n = h.shape[0]
+    wr, wi = np.zeros(n), np.zeros(n)
+    check(lib.hdg_debug_hessenberg_eigenvalues(n, h.ctypes.data, wr.ctypes.data, wi.ctypes.data))
+    return wr + 1j * wi

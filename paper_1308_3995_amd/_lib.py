@@ -21,7 +21,8 @@ EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_patt
            "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
            "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_set_cfl", "hdg_residual_norm", "hdg_apply_update",
            "hdg_cfl_schedule", "hdg_pseudo_transient_solve", "hdg_skeleton_transpose", "hdg_adjoint_rhs",
-           "hdg_adjoint_local", "hdg_mark_elements", "hdg_last_error", "hdg_plan_destroy"]
+           "hdg_adjoint_local", "hdg_mark_elements", "hdg_set_poly_degree", "hdg_debug_hessenberg_eigenvalues",
+           "hdg_last_error", "hdg_plan_destroy"]
 
 
 class HdgParams(C.Structure):
@@ -76,7 +77,9 @@ def load(path: str = LIB_PATH):
     lib.hdg_debug_element_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32)]
     lib.hdg_debug_local_solution.argtypes = [vp, vp, i64, vp, vp, P(i32), P(i32)]
     lib.hdg_set_kernel_timing.argtypes = [vp, i32]
-    lib.hdg_kernel_timing.argtypes = [vp, P(i64), P(dbl), P(dbl), i32]
+    lib.hdg_kernel_timing.argtypes = [vp, i32, P(i64), P(dbl), P(dbl), i32]
+    lib.hdg_set_poly_degree.argtypes = [vp, i32]
+    lib.hdg_debug_hessenberg_eigenvalues.argtypes = [i32, vp, vp, vp]
     lib.hdg_set_cfl.argtypes = [vp, dbl]
     lib.hdg_residual_norm.argtypes = [vp, vp, vp, P(dbl), vp]
     lib.hdg_apply_update.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]

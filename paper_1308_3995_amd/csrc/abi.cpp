@@ -713,20 +713,44 @@ hdg_status hdg_set_kernel_timing(hdg_plan* plan, int32_t enable) {
     return HDG_OK;
 }
 
-hdg_status hdg_kernel_timing(hdg_plan* plan, int64_t* launches, double* total_ms, double* total_bytes,
-                             int32_t reset) {
-    if (!plan) {
-        set_error("hdg_kernel_timing: null plan");
+hdg_status hdg_kernel_timing(hdg_plan* plan, int32_t kernel, int64_t* launches, double* total_ms,
+                             double* total_bytes, int32_t reset) {
+    if (!plan || kernel < 0 || kernel > 1) {
+        set_error("hdg_kernel_timing: null plan or kernel not 0 or 1");
         return HDG_ERR_INVALID_ARG;
     }
     Plan& p = plan->p;
-    if (launches) *launches = p.t_launches;
-    if (total_ms) *total_ms = p.t_ms;
-    if (total_bytes) *total_bytes = p.t_bytes;
+    if (launches) *launches = p.t_launches[kernel];
+    if (total_ms) *total_ms = p.t_ms[kernel];
+    if (total_bytes) *total_bytes = p.t_bytes[kernel];
     if (reset) {
-        p.t_launches = 0;
-        p.t_ms = 0.0;
-        p.t_bytes = 0.0;
+        p.t_launches[kernel] = 0;
+        p.t_ms[kernel] = 0.0;
+        p.t_bytes[kernel] = 0.0;
+    }
+    return HDG_OK;
+}
+
+hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree) {
+    if (!plan || degree < 0 || degree > 32) {
+        set_error("hdg_set_poly_degree: null plan or degree outside 0..32");
+        return HDG_ERR_INVALID_ARG;
+    }
+    plan->p.poly_degree = degree;
+    return HDG_OK;
+}
+
+hdg_status hdg_debug_hessenberg_eigenvalues(int32_t n, const double* h_host, double* wr_host, double* wi_host) {
+    if (n < 1 || n > 64 || !h_host || !wr_host || !wi_host) {
+        set_error("hdg_debug_hessenberg_eigenvalues: n outside 1..64 or a null pointer");
+        return HDG_ERR_INVALID_ARG;
+    }
+    std::vector<double> H(h_host, h_host + (size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j + 1 < i; ++j) H[(size_t)i * n + j] = 0.0;
+    if (!hessenberg_eigenvalues(n, H, wr_host, wi_host)) {
+        set_error("hdg_debug_hessenberg_eigenvalues: QR iteration did not converge");
+        return HDG_ERR_NOT_CONVERGED;
     }
     return HDG_OK;
 }

@@ -17,7 +17,7 @@ constexpr int kMaxFaceQ = 8;          // face Gauss points stored per rule (p_f 
 constexpr int kMinFaceQ = 2;
 constexpr int kNumFaceRules = kMaxFaceQ - kMinFaceQ + 1;
 constexpr int kResPartials = 1024;    // blocks of the residual-norm reduction (fixed: deterministic)
-constexpr int kMaxRestart = 32;       // GMRES restart length limit (Krylov basis kept in registers per element)
+constexpr int kMaxRestart = 32;       // GMRES restart length limit (dot-product accumulators kept in registers)
 
 __host__ __device__ constexpr int n_modes(int p) { return (p + 1) * (p + 2) / 2; }
 __host__ __device__ constexpr int n_vol_q(int p) { return (p + 2) * (p + 2); }
@@ -130,16 +130,20 @@ struct Plan {
     int64_t ws_ns = 0, ns_zcap = 0;       // Navier-Stokes assembly chunk workspace (doubles)
     int64_t hat_values = 0;
     int solver_restart_max = 0;
-    // dominant-kernel timing (benchmarks)
+    // skeleton-solver kernel timing (benchmarks): [0] the polynomial-preconditioner SpMV
+    // kernel, [1] the SpMV fused with the first Gram-Schmidt dots
     bool timing = false;
-    int64_t t_launches = 0;
-    double t_ms = 0.0, t_bytes = 0.0;
+    int64_t t_launches[2] = {0, 0};
+    double t_ms[2] = {0.0, 0.0}, t_bytes[2] = {0.0, 0.0};
+    // degree of the GMRES polynomial preconditioner (< 2: plain block-Jacobi GMRES)
+    int poly_degree = 20;
     std::vector<hipEvent_t> t_events;
-    // captured GMRES restart cycles (one per matrix precision), replayed with hipGraphLaunch
+    // captured GMRES restart cycles (per matrix precision, plain or polynomial-preconditioned),
+    // replayed with hipGraphLaunch
     hipStream_t capture_stream = nullptr;
-    hipGraphExec_t cycle_exec[2] = {nullptr, nullptr};
-    hipGraph_t cycle_graph[2] = {nullptr, nullptr};
-    uint64_t cycle_key[2] = {0, 0};
+    hipGraphExec_t cycle_exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t cycle_graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t cycle_key[4] = {0, 0, 0, 0};
     bool use_graphs = true;
     // condensation: register-budget variant per bucket (chosen by timing on the first call)
     // and the captured launch sequence replayed on later calls
@@ -152,7 +156,7 @@ struct Plan {
 
 // Workspace carving for the skeleton solver (offsets in bytes from ws_solver).
 struct SolverLayout {
-    int64_t minv, hat, hat32, V, w, w2, x, y, r, partial, hess, scal, total;
+    int64_t minv, hat, hat32, V, Z, pvec, ops, w, w2, x, y, r, partial, hess, scal, total;
 };
 SolverLayout solver_layout(const Plan& p, int restart);
 
@@ -201,6 +205,8 @@ int64_t ns_workspace_per_element(int p, int pf);   // Z, L, R of one element (bl
 int64_t ns_chunk_per_element(int p, int pf);       // reduced system and factors (product path)
 hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double* dlam, double rtol,
                           int restart, int max_iter, char* ws, hipStream_t s, int* iters, double* relres);
+// Eigenvalues (wr + i wi) of a real upper Hessenberg matrix, n x n row-major (skeleton.hip).
+bool hessenberg_eigenvalues(int n, std::vector<double> H, double* wr, double* wi);
 
 void set_error(const std::string& msg);
 

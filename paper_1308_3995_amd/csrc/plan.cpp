@@ -592,7 +592,7 @@ void free_plan(Plan& P) {
     for (hipEvent_t e : P.t_events)
         if (e) (void)hipEventDestroy(e);
     P.t_events.clear();
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 4; ++i) {
         if (P.cycle_exec[i]) (void)hipGraphExecDestroy(P.cycle_exec[i]);
         if (P.cycle_graph[i]) (void)hipGraphDestroy(P.cycle_graph[i]);
         P.cycle_exec[i] = nullptr;

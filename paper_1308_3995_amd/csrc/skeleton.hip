@@ -46,6 +46,9 @@ SolverLayout solver_layout(const Plan& p, int restart) {
     L.hat = carve(p.hat_values * 8);
     L.hat32 = carve(p.hat_values * 4);
     L.V = carve(kmv * n * 8);
+    L.Z = carve((int64_t)restart * n * 8);
+    L.pvec = carve(3 * n * 8);
+    L.ops = carve((int64_t)restart * 64);
     L.w = carve(n * 8);
     L.w2 = carve(n * 8);
     L.x = carve(n * 8);
@@ -138,7 +141,7 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 }
 
 // ---------------------------------------------------------------------------
-// Krylov kernels. Per Arnoldi step j (cnt = j + 1 basis vectors):
+// Krylov kernels. Per Arnoldi step j (cnt = j + 1 basis vectors), plain GMRES:
 //   k_spmv_dots   y = Khat v_j, v_j = scale * src written on the fly (one wave per face
 //                 row at a time, kRowsPerBlock rows per block), block partials of V^T y
 //                 and of ||y||^2
@@ -154,6 +157,13 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
 // The next step's k_spmv_dots takes ||w_j|| from the partials (scale = 1/||w_j||) and its
 // block 0 applies the Givens rotation of column j and updates the residual estimate and
 // the flags; k_cycle_end rotates the cycle's last column.
+//
+// With a polynomial preconditioner p (GMRES on Khat p(Khat) u = r, see PolyOp) a step is
+//   k_vnorm       v_j = w_{j-1} / ||w_{j-1}|| into V (block 0: the Givens rotation of column j-1)
+//   k_poly_op x (d - 1)   z_j = p(Khat) v_j, one SpMV each with the vector work of the
+//                 polynomial's factor fused
+//   k_spmv_dots   y = Khat z_j and the dots with V, then the same reductions as above;
+// the cycle's update uses the z_j (flexible form: u += Z coef).
 // All sums are fixed-order, so every run gives the same bits.
 // ---------------------------------------------------------------------------
 constexpr int kMaxV = kMaxRestart + 1;   // Krylov vectors per cycle
@@ -166,21 +176,22 @@ enum { SC_DONE = 0, SC_RES = 1, SC_JDONE = 2, SC_TOL = 3, SC_BETA = 5, SC_SCALE 
 struct GmArgs {
     int nf;
     int64_t n;
-    int B1;           // blocks of the row kernels (4 face rows each)
+    int B1;           // blocks of the row kernels (kRowsPerBlock face rows each)
     int B2;           // blocks of the vector kernels
     int64_t chunk;    // vector entries per vector-kernel block
     const int64_t* face_off;
-    const int64_t* rp;      // block pattern of the matrix (row pointers, columns, value offsets)
-    const int32_t* col;
-    const int64_t* voff;
+    const int64_t* rb;      // row slabs of the matrix: value offset of each face row's slab,
+    const int64_t* cb;      // its first column in xi, and
+    const int32_t* xi;      // the skeleton index of every slab column
     double* V;        // (m+1) x n
+    double* Z;        // m x n: z_j = p(Khat) v_j (polynomial preconditioning)
     double* y;        // SpMV output
     double* w;        // orthogonalised vector
     double* P1;       // [B1][kMaxV]
     double* P2;       // [B2][kMaxV]
     double* P3;       // [max(B1, B2)]
     double* h;        // [kMaxV] last reduced coefficients
-    double* H;        // [m][kMaxV]
+    double* H;        // [m][kMaxV] Hessenberg columns (subdiagonal entry included)
     double* R;        // [m][kMaxV] rotated columns
     double* cs;
     double* sn;
@@ -235,34 +246,88 @@ __device__ __forceinline__ double wave_reduce_many(double (&v)[NV]) {
     return r;
 }
 
-// One face row of y = src_scaled + Khat src_scaled (IDENT) or K src (no identity) by one wave.
-// Returns this lane's output (valid for lane < s).
-template <typename VT, bool IDENT>
-__device__ __forceinline__ double row_spmv(const GmArgs& a, const VT* val, const double* src, double scale, int f,
-                                           int lane, double* red, double& xv) {
-    const int64_t fo = a.face_off[f];
-    const int s = (int)(a.face_off[f + 1] - fo);
-    const int nslots = 64 / s;
-    const int r = lane % s, slot = lane / s;
-    double sum = 0.0;
-    if (slot < nslots) {
-        for (int64_t b = a.rp[f]; b < a.rp[f + 1]; ++b) {
-            const int64_t go = a.face_off[a.col[b]];
-            const int sg = (int)(a.face_off[a.col[b] + 1] - go);
-            const VT* vb = val + a.voff[b] + r;
-#pragma unroll 4
-            for (int c = slot; c < sg; c += nslots) sum += (double)vb[(int64_t)c * s] * src[go + c];
+// 16-byte vector of matrix values: CH consecutive rows of one slab column.
+template <typename VT> struct Vec16;
+template <> struct Vec16<float> { using T = float4; static constexpr int CH = 4; };
+template <> struct Vec16<double> { using T = double2; static constexpr int CH = 2; };
+
+template <typename T>
+__device__ __forceinline__ double comp(const T& v, int k);
+template <> __device__ __forceinline__ double comp<float4>(const float4& v, int k) {
+    return (double)(k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w);
+}
+template <> __device__ __forceinline__ double comp<double2>(const double2& v, int k) { return k == 0 ? v.x : v.y; }
+
+constexpr int kSlabIt = 8;   // 16-byte loads per lane issued back to back
+
+// One face row of t = (row slab of f) src by one wave: the slab is s x W column-major (s the
+// face's unknowns, W the summed widths of the row's stored blocks), read in 16-byte chunks of
+// CH rows; lane l takes chunk row l % G (G = s / CH) of the columns l / G + k L (L = 64 / G),
+// so every load of the wave reads consecutive memory. The lanes' partial row sums are added
+// in a fixed order through LDS (red: 64 CH doubles of this wave). Lane r < s returns row r.
+template <typename VT>
+__device__ __forceinline__ double slab_row(const GmArgs& a, const VT* val, const double* src, int f, int lane,
+                                           double* red) {
+    using VV = typename Vec16<VT>::T;
+    constexpr int CH = Vec16<VT>::CH;
+    const int s = (int)(a.face_off[f + 1] - a.face_off[f]);
+    const int G = s / CH, L = 64 / G;
+    const int g = lane % G, c0 = lane / G;
+    const int64_t cbase = a.cb[f];
+    const int W = (int)(a.cb[f + 1] - cbase);
+    const VT* slab = val + a.rb[f] + g * CH;
+    const int32_t* xi = a.xi + cbase;
+    double acc[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) acc[k] = 0.0;
+    if (c0 < L) {
+        for (int cs = c0; cs < W; cs += kSlabIt * L) {
+            VV v[kSlabIt];
+            double x[kSlabIt];
+#pragma unroll
+            for (int it = 0; it < kSlabIt; ++it) {
+                const int c = cs + it * L;
+                if (c < W) {
+                    v[it] = *(const VV*)(slab + (int64_t)c * s);
+                    x[it] = src[xi[c]];
+                } else {
+                    v[it] = VV{};
+                    x[it] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < kSlabIt; ++it)
+#pragma unroll
+                for (int k = 0; k < CH; ++k) acc[k] += comp(v[it], k) * x[it];
         }
     }
-    red[lane] = sum;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) red[lane * CH + k] = acc[k];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double out = 0.0;
-    xv = 0.0;
+    double t = 0.0;
     if (lane < s) {
-        double t = 0.0;
-        for (int k = 0; k < nslots; ++k) t += red[k * s + lane];
+        const int gg = lane / CH, k = lane % CH;
+        for (int m = 0; m < L; ++m) t += red[(gg + m * G) * CH + k];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return t;
+}
+
+// One face row of y = scale (src + Khat src) (IDENT: Khat's identity diagonal is not stored)
+// or y = K src (no identity). Returns this lane's output (valid for lane < s); xv = scale src.
+template <typename VT, bool IDENT>
+__device__ __forceinline__ double row_spmv(const GmArgs& a, const VT* val, const double* src, double scale, int f,
+                                           int lane, double* red, double& xv) {
+    const double t = slab_row<VT>(a, val, src, f, lane, red);
+    const int64_t fo = a.face_off[f];
+    const int s = (int)(a.face_off[f + 1] - fo);
+    xv = 0.0;
+    double out = 0.0;
+    if (lane < s) {
         xv = scale * src[fo + lane];
         out = IDENT ? scale * t + xv : t;
     }
@@ -272,7 +337,8 @@ __device__ __forceinline__ double row_spmv(const GmArgs& a, const VT* val, const
 // Givens rotation of Hessenberg column j with ||w_j|| = nrm, by one thread: the column H(:, j)
 // rotated by the previous rotations into col[0..j] (R(:, j)), the new rotation (c, s), the
 // rotated residual vector entries gb[j] = c ga[j], ga[j + 1] = -s ga[j], and the residual
-// estimate |s ga[j]|. With `store` the results go to the solver arrays and flags.
+// estimate |s ga[j]|. With `store` the results go to the solver arrays and flags, and nrm to
+// the subdiagonal entry H(j + 1, j).
 __device__ double givens_column(const GmArgs& a, int j, double nrm, double* col, bool store) {
     for (int i = 0; i <= j; ++i) col[i] = a.H[(int64_t)j * kMaxV + i];
     col[j + 1] = nrm;
@@ -290,6 +356,7 @@ __device__ double givens_column(const GmArgs& a, int j, double nrm, double* col,
     const double gbj = c * gj;
     const double res = fabs(s * gj);
     if (store) {
+        a.H[(int64_t)j * kMaxV + j + 1] = nrm;
         for (int i = 0; i <= j; ++i) a.R[(int64_t)j * kMaxV + i] = col[i];
         a.cs[j] = c;
         a.sn[j] = s;
@@ -309,11 +376,14 @@ __device__ __forceinline__ double norm_from_partials(const GmArgs& a, double* sh
     return sqrt(block_sum1(v, sh));
 }
 
-template <typename VT, int CNT>
+// Plain step (POLY false): y = Khat v_j with v_j = scale src written to V on the fly.
+// Polynomial step (POLY true): src = z_j, y = Khat z_j; v_j is already in V.
+template <typename VT, int CNT, bool POLY>
 __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val, const double* src) {
     constexpr int cnt = CNT;
     constexpr int kPerWave = kMaxRestart / 4;   // Krylov vectors per wave in the dot phase
-    __shared__ double red[4][64];
+    constexpr int CH = Vec16<VT>::CH;
+    __shared__ double red[4][64 * CH];
     __shared__ double yf[kRowsPerBlock * 4 * (kMaxDegree + 1)];
     __shared__ double xf[kRowsPerBlock * 4 * (kMaxDegree + 1)];
     __shared__ double sh[8];
@@ -324,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
     // partial sum of the ||w_{j-1}||^2 block partials, loaded before the SpMV so that the
     // reduction below overlaps with it
     double npart = 0.0;
-    if constexpr (CNT > 1)
+    if constexpr (CNT > 1 && !POLY)
         for (int b = threadIdx.x; b < a.B2; b += blockDim.x) npart += a.P3[b];
     const int j = cnt - 1;
     double* vj = a.V + (int64_t)j * a.n;
@@ -339,8 +409,10 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
         tout[rr] = tsrc[rr] = 0.0;
         if (f < a.nf) tout[rr] = row_spmv<VT, false>(a, val, src, 1.0, f, lane, red[wave], tsrc[rr]);
     }
-    double scale;
-    if constexpr (CNT == 1) {
+    double scale = 1.0;
+    if constexpr (POLY) {
+        scale = 1.0;
+    } else if constexpr (CNT == 1) {
         scale = a.scal[SC_SCALE];
     } else {
         // v_j = w_{j-1} / ||w_{j-1}|| (fixed-order sum: every block gets the same bits); block 0
@@ -359,9 +431,11 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
                 const double xv = scale * tsrc[rr];
                 const double out = scale * tout[rr] + xv;
                 a.y[fo + lane] = out;
-                vj[fo + lane] = xv;
+                if constexpr (!POLY) {
+                    vj[fo + lane] = xv;
+                    xf[fo - e0 + lane] = xv;
+                }
                 yf[fo - e0 + lane] = out;
-                xf[fo - e0 + lane] = xv;
             }
         }
     }
@@ -375,14 +449,76 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
 #pragma unroll
         for (int k = 0; k < kPerWave; ++k) {
             const int i = wave + 4 * k;
-            if (i <= cnt)   // i == cnt: ||y||^2
-                acc[k] += ye * ((i == cnt) ? ye : (i == j) ? xf[e] : a.V[(int64_t)i * a.n + e0 + e]);
+            if (i <= cnt) {   // i == cnt: ||y||^2
+                const double o = (i == cnt) ? ye : (!POLY && i == j) ? xf[e] : a.V[(int64_t)i * a.n + e0 + e];
+                acc[k] += ye * o;
+            }
         }
     }
     const double r = wave_reduce_many<kPerWave>(acc);
     const int k = lane >> 3;              // 64 / kPerWave lanes share one value index
     const int i = wave + 4 * k;
     if ((lane & 7) == 0 && i <= cnt) a.P1[(int64_t)i * a.B1 + blockIdx.x] = r;
+}
+
+// Polynomial step, first kernel: v_j = scale src into V (plain scale 1/beta for j = 0, else
+// 1/||w_{j-1}|| from the partials, block 0 rotating column j - 1).
+template <int CNT>
+__global__ __launch_bounds__(kThreads) void k_vnorm(GmArgs a, const double* src) {
+    __shared__ double sh[8];
+    __shared__ double gcol[kMaxV + 1];
+    if (a.scal[SC_DONE] != 0.0) return;
+    double scale;
+    if constexpr (CNT == 1) {
+        scale = a.scal[SC_SCALE];
+    } else {
+        const double nrm = norm_from_partials(a, sh);
+        scale = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) (void)givens_column(a, CNT - 2, nrm, gcol, true);
+    }
+    double* vj = a.V + (int64_t)(CNT - 1) * a.n;
+    const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+    const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
+    for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) vj[k] = scale * src[k];
+}
+
+// One factor of the polynomial preconditioner (device copy of the host's op list): with
+// t = Khat src = src + (stored off-diagonal blocks) src,
+//     out = b0 base + b1 src + b2 t        (written when wout)
+//     y   = [y +] a1 src + gam out          (y starts at 0 in the first op)
+// Real root theta: b1 = 1, b2 = -1/theta (the next residual-polynomial factor), a1 = 1/theta.
+// Complex pair theta, conj(theta): q = (2 Re theta src - t) / |theta|^2 (first op, y += q),
+// then base - Khat q (second op). gam = 1/theta' folds a last real root into the op before it.
+struct PolyOp {
+    double a1, b0, b1, b2, gam;
+    int32_t wout, first, src_id, base_id, out_id, pad;
+};
+constexpr int kMaxPolyOps = kMaxRestart;
+
+template <typename VT>
+__global__ __launch_bounds__(kThreads) void k_poly_op(GmArgs a, const VT* val, const PolyOp* ops, int op,
+                                                      const double* src, const double* base, double* out, double* y) {
+    constexpr int CH = Vec16<VT>::CH;
+    __shared__ double red[4][64 * CH];
+    if (a.scal[SC_DONE] != 0.0) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const PolyOp o = ops[op];
+#pragma unroll
+    for (int rr = 0; rr < kRowsPerWave; ++rr) {
+        const int f = blockIdx.x * kRowsPerBlock + rr * 4 + wave;
+        if (f >= a.nf) continue;
+        double xv;
+        const double t = row_spmv<VT, true>(a, val, src, 1.0, f, lane, red[wave], xv);
+        const int64_t fo = a.face_off[f];
+        const int s = (int)(a.face_off[f + 1] - fo);
+        if (lane < s) {
+            const int64_t e = fo + lane;
+            const double ov = (o.b0 != 0.0 ? o.b0 * base[e] : 0.0) + o.b1 * xv + o.b2 * t;
+            if (o.wout) out[e] = ov;
+            const double yv = (o.first ? 0.0 : y[e]) + o.a1 * xv + o.gam * ov;
+            y[e] = yv;
+        }
+    }
 }
 
 // h_i = sum_b P[i * B + b] (block i); H(i, j) = h_i
@@ -507,9 +643,10 @@ __global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a, int j) {
 }
 
 // End of a cycle: the Givens rotation of the cycle's last column (if the cycle did not stop
-// earlier), coef = R^-1 gb over the completed columns, u += V coef. Every block rotates the
-// last column itself (same bits); block 0 stores the flags the host reads.
-__global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u, int steps) {
+// earlier), coef = R^-1 gb over the completed columns, u += basis coef (basis: V, or Z for the
+// polynomial-preconditioned cycle). Every block rotates the last column itself (same bits);
+// block 0 stores the flags the host reads and the last subdiagonal entry of H.
+__global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u, int steps, const double* basis) {
     __shared__ double coef[kMaxV];
     __shared__ double Rl[kMaxRestart * kMaxV];
     __shared__ double sh[8];
@@ -530,6 +667,7 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u, int
                 const double r = lastcol[steps - 1];
                 const double s = r > 0.0 ? nrm / r : 0.0;
                 const double res = fabs(s * gj);
+                a.H[(int64_t)(steps - 1) * kMaxV + steps] = nrm;
                 a.scal[SC_RES] = res;
                 a.scal[SC_JDONE] = (double)steps;
                 if (res <= a.scal[SC_TOL] || !(nrm > 0.0) || !isfinite(res)) a.scal[SC_DONE] = 1.0;
@@ -558,7 +696,7 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u, int
     const int64_t hi = lo + a.chunk < a.n ? lo + a.chunk : a.n;
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
         double v = u[k];
-        for (int i = 0; i < jd; ++i) v += coef[i] * a.V[(int64_t)i * a.n + k];
+        for (int i = 0; i < jd; ++i) v += coef[i] * basis[(int64_t)i * a.n + k];
         u[k] = v;
     }
 }
@@ -567,8 +705,9 @@ __global__ __launch_bounds__(kThreads) void k_cycle_end(GmArgs a, double* u, int
 template <typename VT, bool IDENT>
 __global__ __launch_bounds__(kThreads) void k_resid(GmArgs a, const VT* val, const double* r0, const double* u,
                                                     double* r) {
+    constexpr int CH = Vec16<VT>::CH;
     __shared__ double sh[8];
-    __shared__ double red[4][64];
+    __shared__ double red[4][64 * CH];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double nacc = 0.0;
 #pragma unroll
@@ -590,7 +729,7 @@ __global__ __launch_bounds__(kThreads) void k_resid(GmArgs a, const VT* val, con
     if (threadIdx.x == 0) a.P3[blockIdx.x] = t;
 }
 
-// Start of a cycle: beta = ||r|| (one block); v_0 = r / beta is written by the first SpMV.
+// Start of a cycle: beta = ||r|| (one block); v_0 = r / beta is written by the first step.
 __global__ __launch_bounds__(kThreads) void k_cycle_start(GmArgs a, int B) {
     __shared__ double sh[8];
     double v = 0.0;
@@ -626,11 +765,17 @@ __global__ void k_fill(int64_t n, double* x, double v) {
     if (k < n) x[k] = v;
 }
 
-__global__ void k_set_scalars(double* scal, double tol) {
+// Clears the solver's scalars except the tolerance (set by k_set_tol before each cycle, so a
+// captured cycle serves every tolerance).
+__global__ void k_set_scalars(double* scal) {
     if (threadIdx.x == 0) {
-        for (int i = 0; i < 16; ++i) scal[i] = 0.0;
-        scal[SC_TOL] = tol;
+        for (int i = 0; i < 16; ++i)
+            if (i != SC_TOL) scal[i] = 0.0;
     }
+}
+
+__global__ void k_set_tol(double* scal, double tol) {
+    if (threadIdx.x == 0) scal[SC_TOL] = tol;
 }
 
 // ---------------------------------------------------------------------------
@@ -645,33 +790,312 @@ __global__ void k_set_scalars(double* scal, double tol) {
         }                                                            \
     } while (0)
 
-// The Arnoldi kernels are instantiated for every basis size so that their loops over the
-// Krylov vectors are branch-free and all loads issue back to back.
-template <typename VT, int C>
-static void launch_step(const GmArgs& a, const VT* hat, const double* src, int cnt, hipStream_t s, hipEvent_t e0,
-                        hipEvent_t e1) {
-    if constexpr (C <= kMaxRestart) {
-        if (cnt != C) {
-            launch_step<VT, C + 1>(a, hat, src, cnt, s, e0, e1);
-            return;
+// Host side of the polynomial preconditioner. From the Hessenberg matrix of d Arnoldi steps
+// on Khat, the roots of the GMRES residual polynomial of degree d are the harmonic Ritz values,
+// the eigenvalues of H_d + h^2 f e_d^T with H_d^T f = e_d (h the subdiagonal entry below H_d).
+// p(Khat) is then defined by 1 - Khat p(Khat) = prod_i (1 - Khat / theta_i) and applied factor
+// by factor in a Leja order of the roots (complex conjugate pairs together, in real arithmetic),
+// the method of Loe and Morgan's polynomial preconditioning for GMRES.
+
+// Eigenvalues of a real upper Hessenberg matrix (n x n, row-major) by the implicit double-shift
+// QR iteration of Francis: bulge chasing with 3-element Householder reflectors, deflation at a
+// negligible subdiagonal entry, 1x1 and 2x2 diagonal blocks read off directly. Returns false if
+// an eigenvalue takes more than 60 iterations.
+bool hessenberg_eigenvalues(int n, std::vector<double> H, double* wr, double* wi) {
+    auto h = [&](int i, int j) -> double& { return H[(size_t)i * n + j]; };
+    double anorm = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = std::max(0, i - 1); j < n; ++j) anorm += std::fabs(h(i, j));
+    const double eps = 2.220446049250313e-16;
+    int hi = n - 1, its = 0;
+    while (hi >= 0) {
+        int l = hi;
+        for (; l > 0; --l) {
+            double s = std::fabs(h(l - 1, l - 1)) + std::fabs(h(l, l));
+            if (s == 0.0) s = anorm;
+            if (std::fabs(h(l, l - 1)) <= eps * s) {
+                h(l, l - 1) = 0.0;
+                break;
+            }
         }
-        const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
-        const int j = C - 1;
-        if (e0) (void)hipEventRecord(e0, s);
-        hipLaunchKernelGGL((k_spmv_dots<VT, C>), g1, blk, 0, s, a, hat, src);
-        if (e1) (void)hipEventRecord(e1, s);
-        hipLaunchKernelGGL(k_reduce_h, dim3(C < kMaxRestart ? C + 1 : C), blk, 0, s, a, a.P1, a.B1, C, j);
-        hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
-        hipLaunchKernelGGL((k_update_norm<C>), g2, blk, 0, s, a, j);
+        if (l == hi) {
+            wr[hi] = h(hi, hi);
+            wi[hi] = 0.0;
+            --hi;
+            its = 0;
+            continue;
+        }
+        if (l == hi - 1) {
+            const double a = h(hi - 1, hi - 1), b = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+            const double p = 0.5 * (a - d), q = p * p + b * c;
+            if (q >= 0.0) {
+                const double z = p + std::copysign(std::sqrt(q), p);
+                wr[hi - 1] = d + z;
+                wr[hi] = z != 0.0 ? d - b * c / z : d + z;
+                wi[hi - 1] = wi[hi] = 0.0;
+            } else {
+                wr[hi - 1] = wr[hi] = d + p;
+                wi[hi - 1] = std::sqrt(-q);
+                wi[hi] = -wi[hi - 1];
+            }
+            hi -= 2;
+            its = 0;
+            continue;
+        }
+        if (its >= 60) return false;
+        ++its;
+        double t, det;
+        if (its % 10 == 0) {   // exceptional shift
+            const double s = std::fabs(h(hi, hi - 1)) + std::fabs(h(hi - 1, hi - 2));
+            t = 1.5 * s;
+            det = s * s;
+        } else {
+            const double x = h(hi, hi), y = h(hi - 1, hi - 1), w = h(hi, hi - 1) * h(hi - 1, hi);
+            t = x + y;
+            det = x * y - w;
+        }
+        // first column of H^2 - t H + det I in rows l .. l + 2
+        double p1 = h(l, l) * h(l, l) + h(l, l + 1) * h(l + 1, l) - t * h(l, l) + det;
+        double p2 = h(l + 1, l) * (h(l, l) + h(l + 1, l + 1) - t);
+        double p3 = h(l + 1, l) * h(l + 2, l + 1);
+        for (int k = l; k <= hi - 1; ++k) {
+            const int nr = k <= hi - 2 ? 3 : 2;
+            if (k > l) {
+                p1 = h(k, k - 1);
+                p2 = h(k + 1, k - 1);
+                p3 = nr == 3 ? h(k + 2, k - 1) : 0.0;
+            }
+            const double xn = std::sqrt(p1 * p1 + p2 * p2 + p3 * p3);
+            if (xn == 0.0) continue;
+            const double v0 = p1 + std::copysign(xn, p1), v1 = p2, v2 = p3;
+            const double beta = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+            for (int j = std::max(l, k - 1); j <= hi; ++j) {
+                const double s = beta * (v0 * h(k, j) + v1 * h(k + 1, j) + (nr == 3 ? v2 * h(k + 2, j) : 0.0));
+                h(k, j) -= s * v0;
+                h(k + 1, j) -= s * v1;
+                if (nr == 3) h(k + 2, j) -= s * v2;
+            }
+            if (k > l) {
+                h(k + 1, k - 1) = 0.0;
+                if (nr == 3) h(k + 2, k - 1) = 0.0;
+            }
+            for (int i = l; i <= std::min(k + 3, hi); ++i) {
+                const double s = beta * (v0 * h(i, k) + v1 * h(i, k + 1) + (nr == 3 ? v2 * h(i, k + 2) : 0.0));
+                h(i, k) -= s * v0;
+                h(i, k + 1) -= s * v1;
+                if (nr == 3) h(i, k + 2) -= s * v2;
+            }
+        }
     }
+    return true;
 }
+
+struct Poly {
+    int degree = 0;
+    std::vector<PolyOp> ops;
+};
+
+// Ops of p(Khat) from the roots (wr, wi) of the residual polynomial. Buffer ids: 0 = v_j,
+// 1 and 2 = the running residual-polynomial vector (ping-pong), 3 = q of a complex pair.
+static bool poly_from_roots(int d, const double* wr, const double* wi, Poly& P) {
+    struct Root { double re, im; };   // im > 0: the pair (re +- i im)
+    std::vector<Root> pool;
+    double big = 0.0;
+    for (int i = 0; i < d; ++i) {
+        if (!std::isfinite(wr[i]) || !std::isfinite(wi[i])) return false;
+        big = std::max(big, std::hypot(wr[i], wi[i]));
+        if (wi[i] == 0.0) pool.push_back({wr[i], 0.0});
+        else if (wi[i] > 0.0) pool.push_back({wr[i], wi[i]});
+    }
+    if (!(big > 0.0)) return false;
+    for (const Root& r : pool)
+        if (std::hypot(r.re, r.im) < 1e-12 * big) return false;
+    // Leja order: the largest root first, then each root maximising the product of its distances
+    // to those already taken (a pair counts with both members)
+    std::vector<Root> ord;
+    std::vector<bool> used(pool.size(), false);
+    for (size_t step = 0; step < pool.size(); ++step) {
+        int best = -1;
+        double bv = -HUGE_VAL;
+        for (size_t i = 0; i < pool.size(); ++i) {
+            if (used[i]) continue;
+            double v = 0.0;
+            if (ord.empty()) {
+                v = std::hypot(pool[i].re, pool[i].im);
+            } else {
+                for (const Root& o : ord) {
+                    v += std::log(std::hypot(pool[i].re - o.re, pool[i].im - o.im) + 1e-300);
+                    if (o.im > 0.0) v += std::log(std::hypot(pool[i].re - o.re, pool[i].im + o.im) + 1e-300);
+                }
+            }
+            if (v > bv) {
+                bv = v;
+                best = (int)i;
+            }
+        }
+        used[best] = true;
+        ord.push_back(pool[best]);
+    }
+    if (ord.size() == 1 && ord[0].im == 0.0) return false;   // degree 1: a scaled identity
+    P.ops.clear();
+    int prod = 0;       // id of the running vector (v_j at the start)
+    int nextbuf = 1;
+    bool first = true;
+    for (size_t k = 0; k < ord.size(); ++k) {
+        const Root& r = ord[k];
+        const bool last = k + 1 == ord.size();
+        const bool fold = k + 2 == ord.size() && ord[k + 1].im == 0.0;   // next is a last real root
+        const double gam = fold ? 1.0 / ord[k + 1].re : 0.0;
+        if (r.im == 0.0) {
+            if (last) break;   // folded into the op before it
+            PolyOp o{};
+            o.a1 = 1.0 / r.re;
+            o.b1 = 1.0;
+            o.b2 = -1.0 / r.re;
+            o.gam = gam;
+            o.wout = fold ? 0 : 1;
+            o.first = first;
+            o.src_id = prod;
+            o.base_id = 0;
+            o.out_id = nextbuf;
+            P.ops.push_back(o);
+            prod = nextbuf;
+            nextbuf = 3 - nextbuf;
+        } else {
+            const double m2 = r.re * r.re + r.im * r.im;
+            PolyOp o{};
+            o.b1 = 2.0 * r.re / m2;
+            o.b2 = -1.0 / m2;
+            o.gam = 1.0;
+            o.wout = last ? 0 : 1;
+            o.first = first;
+            o.src_id = prod;
+            o.base_id = 0;
+            o.out_id = 3;
+            P.ops.push_back(o);
+            if (!last) {
+                PolyOp o2{};
+                o2.b0 = 1.0;
+                o2.b2 = -1.0;
+                o2.gam = gam;
+                o2.wout = fold ? 0 : 1;
+                o2.first = 0;
+                o2.src_id = 3;
+                o2.base_id = prod;
+                o2.out_id = nextbuf;
+                P.ops.push_back(o2);
+                prod = nextbuf;
+                nextbuf = 3 - nextbuf;
+            }
+        }
+        first = false;
+        if (fold) break;
+    }
+    P.degree = d;
+    return !P.ops.empty() && (int)P.ops.size() <= kMaxPolyOps && (int)P.ops.size() == d - 1;
+}
+
+// Harmonic Ritz values of the d-step Hessenberg matrix (column-major with leading dimension
+// kMaxV, the subdiagonal entries included) and the polynomial built from them.
+static bool poly_from_hessenberg(const std::vector<double>& Hc, int d, Poly& P) {
+    std::vector<double> Hd((size_t)d * d, 0.0);
+    for (int j = 0; j < d; ++j)
+        for (int i = 0; i <= std::min(j + 1, d - 1); ++i) Hd[(size_t)i * d + j] = Hc[(size_t)j * kMaxV + i];
+    const double hsub = Hc[(size_t)(d - 1) * kMaxV + d];
+    // f = H_d^-T e_d by Gaussian elimination with partial pivoting on H_d^T
+    std::vector<double> M((size_t)d * (d + 1));
+    for (int i = 0; i < d; ++i) {
+        for (int j = 0; j < d; ++j) M[(size_t)i * (d + 1) + j] = Hd[(size_t)j * d + i];
+        M[(size_t)i * (d + 1) + d] = i == d - 1 ? 1.0 : 0.0;
+    }
+    for (int k = 0; k < d; ++k) {
+        int pv = k;
+        for (int i = k + 1; i < d; ++i)
+            if (std::fabs(M[(size_t)i * (d + 1) + k]) > std::fabs(M[(size_t)pv * (d + 1) + k])) pv = i;
+        if (!(std::fabs(M[(size_t)pv * (d + 1) + k]) > 0.0)) return false;
+        if (pv != k)
+            for (int j = 0; j <= d; ++j) std::swap(M[(size_t)k * (d + 1) + j], M[(size_t)pv * (d + 1) + j]);
+        for (int i = k + 1; i < d; ++i) {
+            const double m = M[(size_t)i * (d + 1) + k] / M[(size_t)k * (d + 1) + k];
+            for (int j = k; j <= d; ++j) M[(size_t)i * (d + 1) + j] -= m * M[(size_t)k * (d + 1) + j];
+        }
+    }
+    std::vector<double> f(d);
+    for (int i = d - 1; i >= 0; --i) {
+        double v = M[(size_t)i * (d + 1) + d];
+        for (int j = i + 1; j < d; ++j) v -= M[(size_t)i * (d + 1) + j] * f[j];
+        f[i] = v / M[(size_t)i * (d + 1) + i];
+    }
+    for (int i = 0; i < d; ++i) Hd[(size_t)i * d + d - 1] += hsub * hsub * f[i];
+    std::vector<double> wr(d), wi(d);
+    if (!hessenberg_eigenvalues(d, Hd, wr.data(), wi.data())) return false;
+    return poly_from_roots(d, wr.data(), wi.data(), P);
+}
+
+// Kernel-time accounting of the benchmarks: launch pairs of events per cycle, per kernel class.
+struct TimedLaunch {
+    int cls;          // 0: k_poly_op, 1: k_spmv_dots
+    double bytes;
+};
 
 struct Solver {
     GmArgs ga;        // preconditioned matrix (identity diagonal not stored)
     GmArgs gk;        // skeleton matrix K (true residual)
     double *minv, *hat, *x, *u, *r;
     float* hat32;
+    double* pbuf[4];  // polynomial vectors: [0] unused (v_j), [1], [2] ping-pong, [3] q
+    PolyOp* ops;
 };
+
+// The Arnoldi kernels are instantiated for every basis size so that their loops over the
+// Krylov vectors are branch-free and all loads issue back to back.
+template <typename VT, int C>
+static void launch_step(Plan& p, const GmArgs& a, const Solver& S, const VT* hat, const double* src, int cnt,
+                        const Poly* poly, hipStream_t s, std::vector<TimedLaunch>* tl) {
+    if constexpr (C <= kMaxRestart) {
+        if (cnt != C) {
+            launch_step<VT, C + 1>(p, a, S, hat, src, cnt, poly, s, tl);
+            return;
+        }
+        const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
+        const int j = C - 1;
+        const double nval = (double)p.hat_values, n = (double)a.n;
+        auto ev = [&](int k) { return p.t_events[k]; };
+        auto mark_begin = [&]() {
+            if (tl) (void)hipEventRecord(ev(2 * (int)tl->size()), s);
+        };
+        auto mark_end = [&](int cls, double bytes) {
+            if (tl) {
+                (void)hipEventRecord(ev(2 * (int)tl->size() + 1), s);
+                tl->push_back({cls, bytes});
+            }
+        };
+        if (poly) {
+            hipLaunchKernelGGL((k_vnorm<C>), g2, blk, 0, s, a, src);
+            double* z = a.Z + (int64_t)j * a.n;
+            const double* vj = a.V + (int64_t)j * a.n;
+            for (size_t k = 0; k < poly->ops.size(); ++k) {
+                const PolyOp& o = poly->ops[k];
+                auto buf = [&](int id) -> double* { return id == 0 ? const_cast<double*>(vj) : S.pbuf[id]; };
+                mark_begin();
+                hipLaunchKernelGGL((k_poly_op<VT>), g1, blk, 0, s, a, hat, S.ops, (int)k, buf(o.src_id),
+                                   buf(o.base_id), buf(o.out_id), z);
+                mark_end(0, nval * sizeof(VT) +
+                                n * 8.0 * (1.0 + (o.b0 != 0.0 ? 1.0 : 0.0) + (o.first ? 1.0 : 2.0) + (o.wout ? 1.0 : 0.0)));
+            }
+            mark_begin();
+            hipLaunchKernelGGL((k_spmv_dots<VT, C, true>), g1, blk, 0, s, a, hat, z);
+            mark_end(1, nval * sizeof(VT) + n * 8.0 * 2.0 + (double)(j + 1) * n * 8.0);
+        } else {
+            mark_begin();
+            hipLaunchKernelGGL((k_spmv_dots<VT, C, false>), g1, blk, 0, s, a, hat, src);
+            mark_end(1, nval * sizeof(VT) + n * 8.0 * 3.0 + (double)j * n * 8.0);
+        }
+        hipLaunchKernelGGL(k_reduce_h, dim3(C < kMaxRestart ? C + 1 : C), blk, 0, s, a, a.P1, a.B1, C, j);
+        hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
+        hipLaunchKernelGGL((k_update_norm<C>), g2, blk, 0, s, a, j);
+    }
+}
 
 static Solver make_solver(Plan& p, char* ws) {
     SolverLayout L = solver_layout(p, kMaxRestart);
@@ -683,6 +1107,9 @@ static Solver make_solver(Plan& p, char* ws) {
     S.x = (double*)(base + L.x);
     S.u = (double*)(base + L.y);
     S.r = (double*)(base + L.r);
+    S.pbuf[0] = nullptr;
+    for (int k = 1; k < 4; ++k) S.pbuf[k] = (double*)(base + L.pvec) + (int64_t)(k - 1) * p.face_off.back();
+    S.ops = (PolyOp*)(base + L.ops);
     GmArgs a{};
     a.nf = p.nf;
     a.n = p.face_off.back();
@@ -691,6 +1118,7 @@ static Solver make_solver(Plan& p, char* ws) {
     a.chunk = (a.n + a.B2 - 1) / a.B2;
     a.face_off = p.d_face_off;
     a.V = (double*)(base + L.V);
+    a.Z = (double*)(base + L.Z);
     a.y = (double*)(base + L.w);
     a.w = (double*)(base + L.w2);
     double* part = (double*)(base + L.partial);
@@ -707,13 +1135,13 @@ static Solver make_solver(Plan& p, char* ws) {
     a.gb = a.ga + (kMaxV + 1);
     a.scal = (double*)(base + L.scal);
     S.gk = a;
-    S.gk.rp = p.d_row_ptr;
-    S.gk.col = p.d_col;
-    S.gk.voff = p.d_val_off;
+    S.gk.rb = p.d_k_rowbase;
+    S.gk.cb = p.d_k_colbase;
+    S.gk.xi = p.d_k_xidx;
     S.ga = a;
-    S.ga.rp = p.d_hat_row_ptr;
-    S.ga.col = p.d_hat_col;
-    S.ga.voff = p.d_hat_val_off;
+    S.ga.rb = p.d_hat_rowbase;
+    S.ga.cb = p.d_hat_colbase;
+    S.ga.xi = p.d_hat_xidx;
     return S;
 }
 
@@ -730,13 +1158,17 @@ static hdg_status true_residual(const Plan& p, Solver& S, const double* bsr, con
     return HDG_OK;
 }
 
-// Restarted GMRES(m) on Khat u = r0, accumulating into u, until ||r0 - Khat u|| <= abs_tol
-// (recursive estimate) or max_iter inner iterations. One host synchronisation per cycle.
+// Restarted GMRES(m) on Khat u = r0 (poly: on Khat p(Khat) u' = r0 with u += p(Khat) u' by the
+// flexible update), accumulating into u, until ||r0 - Khat u|| <= abs_tol (recursive estimate)
+// or max_iter operator applications (a polynomial step counts its degree). One host
+// synchronisation per cycle.
 template <typename VT>
 static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0, int m, int max_iter,
-                             double abs_tol, hipStream_t s, int* iters, double* est) {
-    if (p.timing && (int)p.t_events.size() < 2 * kMaxRestart) {
-        p.t_events.resize(2 * kMaxRestart, nullptr);
+                             double abs_tol, const Poly* poly, hipStream_t s, int* iters, double* est) {
+    const int deg = poly ? poly->degree : 1;
+    const int per_cycle_events = 2 * m * (poly ? (int)poly->ops.size() + 1 : 1);
+    if (p.timing && (int)p.t_events.size() < per_cycle_events) {
+        p.t_events.resize(per_cycle_events, nullptr);
         for (auto& e : p.t_events)
             if (!e) HIPCHK(hipEventCreate(&e));
     }
@@ -744,20 +1176,21 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
     const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
     int total = 0;
     double res = 0.0;
-    // one restart cycle: reset flags, r = r0 - Khat u, beta, m Arnoldi steps, u += V coef
-    auto enqueue_cycle = [&](hipStream_t q, int steps) {
-        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, q, a.scal, abs_tol);
+    std::vector<TimedLaunch> tl;
+    // one restart cycle: reset flags, r = r0 - Khat u, beta, m Arnoldi steps, u += basis coef
+    auto enqueue_cycle = [&](hipStream_t q, int steps, std::vector<TimedLaunch>* t) {
+        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, q, a.scal);
         hipLaunchKernelGGL((k_resid<VT, true>), g1, blk, 0, q, a, hat, r0, S.u, S.r);
         hipLaunchKernelGGL(k_cycle_start, dim3(1), blk, 0, q, a, a.B1);
         for (int j = 0; j < steps; ++j)
-            launch_step<VT, 1>(a, hat, j == 0 ? S.r : a.w, j + 1, q, p.timing ? p.t_events[2 * j] : nullptr,
-                               p.timing ? p.t_events[2 * j + 1] : nullptr);
-        hipLaunchKernelGGL(k_cycle_end, g2, blk, 0, q, a, S.u, steps);
+            launch_step<VT, 1>(p, a, S, hat, j == 0 ? S.r : a.w, j + 1, poly, q, t);
+        hipLaunchKernelGGL(k_cycle_end, g2, blk, 0, q, a, S.u, steps, poly ? (const double*)a.Z : (const double*)a.V);
     };
-    const int gi = sizeof(VT) == 8 ? 0 : 1;
+    const int gi = (sizeof(VT) == 8 ? 0 : 1) + (poly ? 2 : 0);
     while (total < max_iter) {
-        const int steps = std::min(m, max_iter - total);
+        const int steps = std::min(m, (max_iter - total + deg - 1) / deg);
         bool launched = false;
+        hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(64), 0, s, a.scal, abs_tol);
         // per-launch event timing needs direct launches (events are not recorded inside replays)
         if (p.use_graphs && !p.timing && steps == m) {
             // key: every pointer and size baked into the captured kernels
@@ -769,7 +1202,11 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
             mix((uint64_t)(uintptr_t)a.V);
             mix((uint64_t)(uintptr_t)a.scal);
             mix((uint64_t)m);
-            mix((uint64_t)std::hash<double>{}(abs_tol));
+            if (poly) {
+                mix((uint64_t)poly->ops.size());
+                for (const PolyOp& o : poly->ops)
+                    mix((uint64_t)(o.src_id | o.base_id << 4 | o.out_id << 8 | o.wout << 12 | o.first << 13));
+            }
             if (!p.cycle_exec[gi] || p.cycle_key[gi] != key) {
                 if (p.cycle_exec[gi]) (void)hipGraphExecDestroy(p.cycle_exec[gi]);
                 if (p.cycle_graph[gi]) (void)hipGraphDestroy(p.cycle_graph[gi]);
@@ -779,7 +1216,7 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
                 if (!p.capture_stream) HIPCHK(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
                 hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeRelaxed);
                 if (e == hipSuccess) {
-                    enqueue_cycle(p.capture_stream, steps);
+                    enqueue_cycle(p.capture_stream, steps, nullptr);
                     e = hipStreamEndCapture(p.capture_stream, &p.cycle_graph[gi]);
                 }
                 if (e == hipSuccess) e = hipGraphInstantiate(&p.cycle_exec[gi], p.cycle_graph[gi], nullptr, nullptr, 0);
@@ -795,30 +1232,55 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
                 launched = true;
             }
         }
-        if (!launched) enqueue_cycle(s, steps);
+        tl.clear();
+        if (!launched) enqueue_cycle(s, steps, p.timing ? &tl : nullptr);
         HIPCHK(hipGetLastError());
         double sc[8];
         HIPCHK(hipMemcpyAsync(sc, a.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const int jd = (int)sc[SC_JDONE];
-        total += jd;
+        total += jd * deg;
         res = sc[SC_RES];
         if (p.timing) {
-            // launches that did work: steps 0..jd-1 (later ones saw the converged flag)
-            const int worked = std::min(steps, jd);
-            for (int j = 0; j < worked; ++j) {
+            // launches that did work: those of steps 0..jd-1 (later ones saw the converged flag)
+            const size_t per_step = poly ? poly->ops.size() + 1 : 1;
+            const size_t worked = std::min(tl.size(), (size_t)std::min(steps, jd) * per_step);
+            for (size_t k = 0; k < worked; ++k) {
                 float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, p.t_events[2 * j], p.t_events[2 * j + 1]));
-                p.t_ms += ms;
-                p.t_launches += 1;
-                const double nval = (double)p.hat_values, n = (double)a.n;
-                p.t_bytes += nval * sizeof(VT) + n * 8.0 * 3.0 + (double)(j + 1) * n * 8.0;
+                HIPCHK(hipEventElapsedTime(&ms, p.t_events[2 * k], p.t_events[2 * k + 1]));
+                const int c = tl[k].cls;
+                p.t_ms[c] += ms;
+                p.t_launches[c] += 1;
+                p.t_bytes[c] += tl[k].bytes;
             }
         }
         if (jd == 0 || res <= abs_tol || jd < steps) break;
     }
     *iters = total;
     *est = res;
+    return HDG_OK;
+}
+
+// One plain GMRES cycle of `d` steps (it advances u like any cycle), then the polynomial of
+// degree d from its Hessenberg matrix. Returns the operator applications used; `ok` tells
+// whether a polynomial was built (not when the cycle converged or broke down first, or the
+// roots were unusable).
+template <typename VT>
+static hdg_status build_poly(Plan& p, Solver& S, const VT* hat, const double* r0, int d, int max_iter,
+                             double abs_tol, hipStream_t s, Poly& poly, bool& ok, int* used, double* est) {
+    ok = false;
+    int it = 0;
+    hdg_status st = gmres_khat<VT>(p, S, hat, r0, d, std::min(d, max_iter), abs_tol, nullptr, s, &it, est);
+    if (st != HDG_OK) return st;
+    *used = it;
+    if (it < d || *est <= abs_tol) return HDG_OK;
+    std::vector<double> Hc((size_t)d * kMaxV);
+    HIPCHK(hipMemcpyAsync(Hc.data(), S.ga.H, Hc.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!poly_from_hessenberg(Hc, d, poly)) return HDG_OK;
+    HIPCHK(hipMemcpyAsync(S.ops, poly.ops.data(), poly.ops.size() * sizeof(PolyOp), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ok = true;
     return HDG_OK;
 }
 
@@ -837,9 +1299,11 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
     Solver S = make_solver(p, ws);
     const bool mixed = p.prm.precision == HDG_MIXED;
     const unsigned vblocks = (unsigned)((n + 255) / 256);
+    const int pdeg = p.poly_degree;
 
     // preconditioner: invert the face-diagonal blocks, form Khat = K M^-1
-    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, S.ga.scal, 0.0);
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, S.ga.scal);
+    hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(64), 0, s, S.ga.scal, 0.0);
     hipLaunchKernelGGL(k_bj_invert, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_row_ptr, p.d_val_off,
                        p.d_diag_off, bsr, S.minv, S.ga.scal);
     hipLaunchKernelGGL(k_hat_build, dim3(p.nf), dim3(256), 0, s, p.nf, p.d_face_off, p.d_hat_row_ptr, p.d_hat_col,
@@ -867,15 +1331,28 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
     const double tol = rtol * enorm;
     int total = 0;
     double relres = 1.0;
+    Poly poly;
+    bool have_poly = false, tried_poly = pdeg < 2;
     if (!mixed) {
         // GMRES on Khat u = E, dLambda = M^-1 u; continue until the true residual meets tol
         hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, S.u, 0.0);
         for (int outer = 0; outer < 50 && total < max_iter; ++outer) {
             int it = 0;
             double est = 0.0;
-            st = gmres_khat<double>(p, S, S.hat, rhs, restart, max_iter - total, tol, s, &it, &est);
-            if (st != HDG_OK) return st;
-            total += it;
+            if (!tried_poly) {
+                tried_poly = true;
+                st = build_poly<double>(p, S, S.hat, rhs, pdeg, max_iter - total, tol, s, poly, have_poly, &it, &est);
+                if (st != HDG_OK) return st;
+                total += it;
+            }
+            if (total < max_iter && !(est <= tol && it > 0)) {
+                int it2 = 0;
+                st = gmres_khat<double>(p, S, S.hat, rhs, restart, max_iter - total, tol, have_poly ? &poly : nullptr,
+                                        s, &it2, &est);
+                if (st != HDG_OK) return st;
+                total += it2;
+                it += it2;
+            }
             hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv,
                                S.u, dlam, 0);
             double tr = 0.0;
@@ -902,15 +1379,31 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
             hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, S.u, 0.0);
             int it = 0;
             double est = 0.0;
-            if (fp64_inner) {
-                st = gmres_khat<double>(p, S, S.hat, S.x, restart, max_iter - total, tol, s, &it, &est);
-            } else {
-                // the float32 matrix bounds what one refinement step can gain; ask for 1e-6
-                const double inner_tol = std::max(tol, 1e-6 * tr);
-                st = gmres_khat<float>(p, S, S.hat32, S.x, restart, max_iter - total, inner_tol, s, &it, &est);
+            // the float32 matrix bounds what one refinement step can gain; ask for 1e-6
+            const double inner_tol = fp64_inner ? tol : std::max(tol, 1e-6 * tr);
+            if (!tried_poly) {
+                tried_poly = true;
+                if (fp64_inner)
+                    st = build_poly<double>(p, S, S.hat, S.x, pdeg, max_iter - total, inner_tol, s, poly, have_poly,
+                                            &it, &est);
+                else
+                    st = build_poly<float>(p, S, S.hat32, S.x, pdeg, max_iter - total, inner_tol, s, poly, have_poly,
+                                           &it, &est);
+                if (st != HDG_OK) return st;
+                total += it;
             }
-            if (st != HDG_OK) return st;
-            total += it;
+            if (total < max_iter && !(est <= inner_tol && it > 0)) {
+                int it2 = 0;
+                if (fp64_inner)
+                    st = gmres_khat<double>(p, S, S.hat, S.x, restart, max_iter - total, inner_tol,
+                                            have_poly ? &poly : nullptr, s, &it2, &est);
+                else
+                    st = gmres_khat<float>(p, S, S.hat32, S.x, restart, max_iter - total, inner_tol,
+                                           have_poly ? &poly : nullptr, s, &it2, &est);
+                if (st != HDG_OK) return st;
+                total += it2;
+                it += it2;
+            }
             hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv,
                                S.u, dlam, 1);
             if (it == 0) break;

@@ -66,3 +66,35 @@ def test_cfl_schedule_matches_the_oracle():
         else:
             assert abs(got - ref) <= 1e-15 * abs(ref), (n, got, ref)
     assert lib.hdg_set_cfl(None, 1.0) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_hessenberg_eigenvalues_match_numpy():
+    """The host QR iteration behind the polynomial preconditioner's roots against LAPACK (numpy)
+    on random upper Hessenberg matrices: real and complex spectra, a split (zero subdiagonal),
+    wide scaling, and the 1x1 and 2x2 cases."""
+    import numpy as np
+    import scipy.linalg
+    from scipy.optimize import linear_sum_assignment
+    import paper_1308_3995_amd as hdg
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for trial in range(400):
+        n = int(rng.integers(1, 41))
+        A = rng.standard_normal((n, n)) * 10.0 ** rng.uniform(-3, 3)
+        H = scipy.linalg.hessenberg(A)
+        if trial % 5 == 0 and n > 3:
+            H[n // 2, n // 2 - 1] = 0.0
+        ev = hdg.hessenberg_eigenvalues(H)
+        ref = np.linalg.eigvals(H)
+        C = np.abs(ev[:, None] - ref[None, :])
+        r, c = linear_sum_assignment(C)
+        worst = max(worst, C[r, c].max() / np.abs(ref).max())
+        # conjugate pairs: +imaginary part first
+        for k in range(n - 1):
+            if ev[k].imag > 0:
+                assert ev[k + 1] == np.conj(ev[k])
+    assert worst < 1e-11, worst
+    # a rotation block [[0, -1], [1, 0]]: eigenvalues +-i
+    ev = hdg.hessenberg_eigenvalues(np.array([[0.0, -1.0], [1.0, 0.0]]))
+    assert np.allclose(sorted(ev, key=lambda z: z.imag), [-1j, 1j], atol=1e-15)
