@@ -38,26 +38,103 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(ng: int = 16):
-    """The CPU oracle, untouched, on the same recipe at a bounded size (full Newton step)."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_worker_init(name: str):
+    """Each oracle worker process runs its BLAS on one thread (fail loudly if that cannot be set)
+    and builds the workload's oracle state before any timing."""
+    from threadpoolctl import threadpool_limits, threadpool_info
+    threadpool_limits(limits=1)
+    for info in threadpool_info():
+        if info.get("num_threads", 1) != 1:
+            raise RuntimeError(f"could not limit {info.get('internal_api')} to one thread")
+    _oracle_state(name)
+
+
+_ORACLE_STATE = {}
+
+
+def _oracle_state(name: str):
+    """The oracle's mesh and state of a workload, built once per worker process."""
+    if name not in _ORACLE_STATE:
+        import hdg_inputs as hi
+        from oracle import hdg_oracle as O
+        case = hi.config_case(name)
+        mesh = O.Mesh(case, O.make_physics(case))
+        _ORACLE_STATE[name] = O.State(mesh, case.W, case.lam, case.Q)
+    return _ORACLE_STATE[name]
+
+
+def _oracle_condense(args):
+    """Oracle blocks (complex-step) and condensation of a list of elements of a workload; returns
+    the seconds spent (the state is built beforehand, outside the timing)."""
+    name, elems = args
+    from oracle import hdg_oracle as O
+    st = _oracle_state(name)
+    t0 = time.perf_counter()
+    for e in elems:
+        O.condense(O.element_blocks(st, int(e)))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(multi_elements: int = 1024, single_elements: int = 48, lu_ng: int = 16):
+    """The CPU oracle, untouched, on the 64x64 p=3 workload (same seeds as the GPU step): the
+    per-element path (complex-step Jacobian blocks, LU condensation) over a seeded sample of the
+    mesh's elements spread over every core by multiprocessing with BLAS on one thread per
+    process, the same on one core, and SuperLU on the skeleton system of the same recipe at
+    lu_ng x lu_ng (the 64x64 skeleton needs every element's blocks), timed separately."""
+    import multiprocessing as mp
     import hdg_inputs as hi
     from oracle import hdg_oracle as O
+    # the host's CPU share: the affinity mask, at most 16 processes (one GPU's share of the box)
     try:
-        from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=1)
-    except Exception:
-        limiter = None
-    case = hi.config_case("c2", ng=ng)
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(avail, 16))
+    case = hi.config_case("c2")
+    rng = np.random.default_rng(1308)
+    sample = np.sort(rng.choice(case.n_elements, size=min(multi_elements, case.n_elements), replace=False))
+    chunks = [("c2", sample[i::cores]) for i in range(cores)]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores, initializer=_oracle_worker_init, initargs=("c2",)) as pool:
+        # every worker has imported the oracle and built the workload's state (initializer)
+        pool.map(_oracle_condense, [("c2", [])] * cores, chunksize=1)
+        t0 = time.perf_counter()
+        pool.map(_oracle_condense, chunks, chunksize=1)
+        t_multi = time.perf_counter() - t0
+    with ctx.Pool(1, initializer=_oracle_worker_init, initargs=("c2",)) as pool:
+        t_single = pool.map(_oracle_condense, [("c2", sample[:single_elements])])[0]
+    rate_multi = len(sample) / t_multi
+    rate_single = single_elements / t_single
+    # SuperLU on the skeleton system of the same recipe at lu_ng x lu_ng
+    small = hi.config_case("c2", ng=lu_ng)
+    mesh = O.Mesh(small, O.make_physics(small))
+    st = O.State(mesh, small.W, small.lam, small.Q)
+    blocks = [O.element_blocks(st, e) for e in range(mesh.ne)]
+    cond = [O.condense(b) for b in blocks]
+    K, E = O.assemble_skeleton(mesh, blocks, cond)
+    import scipy.sparse.linalg as spla
     t0 = time.perf_counter()
-    step = O.newton_step(case)
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {"value": case.n_elements / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"same recipe at {ng}x{ng} (p=3, {case.n_elements} elements, {step.mesh.n_skel} skeleton dofs): "
-                      f"one full oracle Newton step (complex-step blocks, LU condensation, direct skeleton solve, "
-                      f"reconstruction) took {dt:.2f} s on 1 thread",
-            "seconds": dt}
+    spla.splu(K.tocsc()).solve(E)
+    t_lu = time.perf_counter() - t0
+    return {"value": rate_multi, "unit": "elements/s", "cores": cores, "kind": "oracle",
+            "sample": (f"64x64 p=3 workload, same seeds: oracle assemble + condense (complex-step blocks, LU, "
+                       f"Schur) of {len(sample)} seeded elements of the 8192 in {t_multi:.2f} s over {cores} "
+                       f"processes with BLAS on one thread each; the skeleton solve is not included (it only "
+                       f"adds time); one core: {rate_single:.1f} elements/s ({single_elements} elements); "
+                       f"SuperLU on the {lu_ng}x{lu_ng} skeleton ({K.shape[0]} dofs) {t_lu:.3f} s"),
+            "single_core_elements_per_s": rate_single, "superlu_seconds": t_lu, "superlu_dofs": int(K.shape[0]),
+            "superlu_mesh": f"{lu_ng}x{lu_ng}", "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+            "cpu_affinity": avail}
 
 
 def measured_traffic(kernel_source: str, summary: str):
@@ -307,6 +384,10 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--poly-degree", type=int, default=20,
+                    help="degree of the GMRES polynomial preconditioner (0: plain block-Jacobi GMRES)")
+    ap.add_argument("--poly-fp32", action="store_true",
+                    help="mixed mode: the polynomial's products read the float32 matrix, not a float16 copy")
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--serving-requests", type=int, default=24,
                     help="requests of the Poisson serving stream to run (0 = skip; 512 = the full stream)")
@@ -348,6 +429,7 @@ def main():
     for mode in args.modes.split(","):
         log(f"[bench] mode {mode}: plan")
         plan = hdg.HDGPlan.from_case(case, precision=mode)
+        plan.hdg_set_poly_degree(args.poly_degree, fp16_matrix=not args.poly_fp32)
         w = torch.tensor(case.W, dtype=torch.float64, device=dev).contiguous()
         lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
         dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=dev)
@@ -481,8 +563,7 @@ def main():
             f"{sm['elements_per_s']:.0f} elements/s")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        cb = cpu_baseline()
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

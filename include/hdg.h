@@ -331,8 +331,13 @@ hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev,
                                     double* X_host, double* y_host, int32_t* n_out, int32_t* f_out);
 
 /* Degree d of the GMRES polynomial preconditioner of hdg_skeleton_solve on this plan
- * (0 or 1: plain block-Jacobi GMRES; at most 32). Errors: HDG_ERR_INVALID_ARG. */
-hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree);
+ * (0 or 1: plain block-Jacobi GMRES; at most 32; default 20) and, for HDG_MIXED, the storage
+ * of the preconditioned matrix its products read: fp16_matrix = 1 (default) a float16 copy,
+ * 0 the float32 copy of the inner solve. The polynomial is only a preconditioner (the outer
+ * Arnoldi products and the float64 refinement residual are unchanged), so its storage changes
+ * the iteration count, not the gate. HDG_FP64 always uses the float64 matrix. Errors:
+ * HDG_ERR_INVALID_ARG. */
+hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree, int32_t fp16_matrix);
 
 /* Profiling hook for benchmarks: when enabled, hdg_skeleton_solve launches its restart cycles
  * directly (not from captured graphs) and brackets every launch of its two SpMV kernels with

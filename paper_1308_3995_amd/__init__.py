@@ -228,9 +228,10 @@ class HDGPlan:
         return flag[: self.ne], sensor[: self.ne], m.value
 
     # ---- skeleton-solver options and kernel timing (benchmarks)
-    def hdg_set_poly_degree(self, degree: int):
-        """Degree of the GMRES polynomial preconditioner (0 or 1: plain block-Jacobi GMRES)."""
-        check(self.lib.hdg_set_poly_degree(self.handle, int(degree)))
+    def hdg_set_poly_degree(self, degree: int, fp16_matrix: bool = True):
+        """Degree of the GMRES polynomial preconditioner (0 or 1: plain block-Jacobi GMRES) and, in
+        the mixed mode, whether its products read a float16 copy of the preconditioned matrix."""
+        check(self.lib.hdg_set_poly_degree(self.handle, int(degree), 1 if fp16_matrix else 0))
 
     def hdg_set_kernel_timing(self, enable: bool):
         check(self.lib.hdg_set_kernel_timing(self.handle, 1 if enable else 0))

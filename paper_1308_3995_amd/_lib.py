@@ -78,7 +78,7 @@ def load(path: str = LIB_PATH):
     lib.hdg_debug_local_solution.argtypes = [vp, vp, i64, vp, vp, P(i32), P(i32)]
     lib.hdg_set_kernel_timing.argtypes = [vp, i32]
     lib.hdg_kernel_timing.argtypes = [vp, i32, P(i64), P(dbl), P(dbl), i32]
-    lib.hdg_set_poly_degree.argtypes = [vp, i32]
+    lib.hdg_set_poly_degree.argtypes = [vp, i32, i32]
     lib.hdg_debug_hessenberg_eigenvalues.argtypes = [i32, vp, vp, vp]
     lib.hdg_set_cfl.argtypes = [vp, dbl]
     lib.hdg_residual_norm.argtypes = [vp, vp, vp, P(dbl), vp]

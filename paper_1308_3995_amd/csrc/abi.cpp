@@ -731,12 +731,13 @@ hdg_status hdg_kernel_timing(hdg_plan* plan, int32_t kernel, int64_t* launches, 
     return HDG_OK;
 }
 
-hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree) {
-    if (!plan || degree < 0 || degree > 32) {
-        set_error("hdg_set_poly_degree: null plan or degree outside 0..32");
+hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree, int32_t fp16_matrix) {
+    if (!plan || degree < 0 || degree > 32 || fp16_matrix < 0 || fp16_matrix > 1) {
+        set_error("hdg_set_poly_degree: null plan, degree outside 0..32 or fp16_matrix not 0 or 1");
         return HDG_ERR_INVALID_ARG;
     }
     plan->p.poly_degree = degree;
+    plan->p.poly_half = fp16_matrix;
     return HDG_OK;
 }
 

@@ -62,6 +62,21 @@ struct Bucket {
     int64_t store_off;  // offset (doubles) of the bucket's local-store region
 };
 
+// Row slab of a skeleton matrix (the stored blocks of one face row, contiguous and column-major
+// with s rows): everything a wave needs to multiply it, in one 64-byte record. Slab column c
+// belongs to block b with bcol[b] <= c < bcol[b + 1] (bcol[nblk] = W) and gathers the source
+// entry boff[b] + c - bcol[b].
+struct SlabDesc {
+    int64_t rb;           // value offset of the slab
+    int32_t fo;           // skeleton offset of the face row
+    int32_t s;            // rows (unknowns of the face)
+    int32_t W;            // columns
+    int32_t nblk;         // stored blocks (<= 5)
+    int32_t boff[5];      // skeleton offset of each block's column face
+    int32_t bcol[5];      // first slab column of each block
+};
+static_assert(sizeof(SlabDesc) == 64, "one 64-byte record per face row");
+
 struct Plan {
     int device = 0;
     hdg_params prm{};
@@ -91,8 +106,7 @@ struct Plan {
     std::vector<int64_t> hat_val_off;     // [nhat+1]; blocks of a row are contiguous (a row slab)
     std::vector<int64_t> hat_src;         // value offset of the corresponding block of K
     // row slabs (values of a face row are contiguous, column-major with s_f rows)
-    std::vector<int64_t> k_rowbase, k_colbase, hat_rowbase, hat_colbase;
-    std::vector<int32_t> k_xidx, hat_xidx;    // skeleton index of every slab column
+    std::vector<SlabDesc> k_desc, hat_desc;
     std::vector<int32_t> kb_rows;             // face-row partition over the Krylov kernel blocks
     int kblocks = 1;
     TableIndex tix{};
@@ -115,12 +129,8 @@ struct Plan {
     int32_t* d_hat_col = nullptr;
     int64_t* d_hat_val_off = nullptr;
     int64_t* d_hat_src = nullptr;
-    int64_t* d_k_rowbase = nullptr;
-    int64_t* d_k_colbase = nullptr;
-    int32_t* d_k_xidx = nullptr;
-    int64_t* d_hat_rowbase = nullptr;
-    int64_t* d_hat_colbase = nullptr;
-    int32_t* d_hat_xidx = nullptr;
+    SlabDesc* d_k_desc = nullptr;
+    SlabDesc* d_hat_desc = nullptr;
     int32_t* d_kb_rows = nullptr;
 
     // workspace layout (offsets in bytes)
@@ -135,8 +145,10 @@ struct Plan {
     bool timing = false;
     int64_t t_launches[2] = {0, 0};
     double t_ms[2] = {0.0, 0.0}, t_bytes[2] = {0.0, 0.0};
-    // degree of the GMRES polynomial preconditioner (< 2: plain block-Jacobi GMRES)
+    // degree of the GMRES polynomial preconditioner (< 2: plain block-Jacobi GMRES) and its
+    // matrix storage in the mixed mode (1: float16 copy of Khat, 0: the float32 copy)
     int poly_degree = 20;
+    int poly_half = 1;
     std::vector<hipEvent_t> t_events;
     // captured GMRES restart cycles (per matrix precision, plain or polynomial-preconditioned),
     // replayed with hipGraphLaunch
@@ -156,7 +168,7 @@ struct Plan {
 
 // Workspace carving for the skeleton solver (offsets in bytes from ws_solver).
 struct SolverLayout {
-    int64_t minv, hat, hat32, V, Z, pvec, ops, w, w2, x, y, r, partial, hess, scal, total;
+    int64_t minv, hat, hat32, hat16, V, Z, pvec, ops, w, w2, x, y, r, partial, hess, scal, total;
 };
 SolverLayout solver_layout(const Plan& p, int restart);
 

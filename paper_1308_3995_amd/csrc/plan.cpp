@@ -377,22 +377,34 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
                 return HDG_ERR_INVALID_ARG;
             }
         }
-    // row slabs: value base of each row and the gather index of every slab column
+    // row slabs: one descriptor per face row (value base, width, gather base of every block)
     auto slabs = [&](const std::vector<int64_t>& rp, const std::vector<int32_t>& cl, const std::vector<int64_t>& vo,
-                     std::vector<int64_t>& rowbase, std::vector<int64_t>& colbase, std::vector<int32_t>& xidx) {
-        rowbase.assign(P.nf + 1, 0);
-        colbase.assign(P.nf + 1, 0);
-        xidx.clear();
+                     std::vector<SlabDesc>& desc) {
+        desc.assign(P.nf, SlabDesc{});
         for (int f = 0; f < P.nf; ++f) {
-            rowbase[f] = rp[f] < rp[f + 1] ? vo[rp[f]] : (f > 0 ? rowbase[f - 1] : 0);
-            for (int64_t b = rp[f]; b < rp[f + 1]; ++b)
-                for (int64_t c = 0; c < fsize(cl[b]); ++c) xidx.push_back((int32_t)(P.face_off[cl[b]] + c));
-            colbase[f + 1] = (int64_t)xidx.size();
+            SlabDesc& d = desc[f];
+            d.rb = rp[f] < rp[f + 1] ? vo[rp[f]] : 0;
+            d.fo = (int32_t)P.face_off[f];
+            d.s = (int32_t)fsize(f);
+            d.nblk = (int32_t)(rp[f + 1] - rp[f]);
+            int32_t c = 0;
+            for (int b = 0; b < 5; ++b) {
+                d.bcol[b] = c;
+                d.boff[b] = 0;
+                if (b < d.nblk) {
+                    d.boff[b] = (int32_t)P.face_off[cl[rp[f] + b]];
+                    c += (int32_t)fsize(cl[rp[f] + b]);
+                }
+            }
+            d.W = c;
         }
-        rowbase[P.nf] = vo.empty() ? 0 : vo.back();
     };
-    slabs(P.row_ptr, P.col, P.val_off, P.k_rowbase, P.k_colbase, P.k_xidx);
-    slabs(P.hat_row_ptr, P.hat_col, P.hat_val_off, P.hat_rowbase, P.hat_colbase, P.hat_xidx);
+    if (P.face_off.back() >= ((int64_t)1 << 31)) {
+        set_error("skeleton larger than 2^31 unknowns");
+        return HDG_ERR_INVALID_ARG;
+    }
+    slabs(P.row_ptr, P.col, P.val_off, P.k_desc);
+    slabs(P.hat_row_ptr, P.hat_col, P.hat_val_off, P.hat_desc);
     // partition of the face rows over the blocks of the Krylov kernels (about equal dofs)
     {
         const int B = std::max(1, std::min(256, P.nf));
@@ -569,12 +581,8 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     if (err == hipSuccess) err = upload(&P.d_hat_col, P.hat_col, up);
     if (err == hipSuccess) err = upload(&P.d_hat_val_off, P.hat_val_off, up);
     if (err == hipSuccess) err = upload(&P.d_hat_src, P.hat_src, up);
-    if (err == hipSuccess) err = upload(&P.d_k_rowbase, P.k_rowbase, up);
-    if (err == hipSuccess) err = upload(&P.d_k_colbase, P.k_colbase, up);
-    if (err == hipSuccess) err = upload(&P.d_k_xidx, P.k_xidx, up);
-    if (err == hipSuccess) err = upload(&P.d_hat_rowbase, P.hat_rowbase, up);
-    if (err == hipSuccess) err = upload(&P.d_hat_colbase, P.hat_colbase, up);
-    if (err == hipSuccess) err = upload(&P.d_hat_xidx, P.hat_xidx, up);
+    if (err == hipSuccess) err = upload(&P.d_k_desc, P.k_desc, up);
+    if (err == hipSuccess) err = upload(&P.d_hat_desc, P.hat_desc, up);
     if (err == hipSuccess) err = upload(&P.d_kb_rows, P.kb_rows, up);
     if (up) {
         if (err == hipSuccess) err = hipStreamSynchronize(up);
@@ -606,7 +614,7 @@ void free_plan(Plan& P) {
     P.capture_stream = nullptr;
     void* ptrs[] = {P.d_einfo, P.d_tab, P.d_bproj, P.d_face_off, P.d_face_deg, P.d_row_ptr, P.d_col,
                     P.d_val_off, P.d_diag_off, P.d_hat_row_ptr, P.d_hat_col, P.d_hat_val_off, P.d_hat_src,
-                    P.d_k_rowbase, P.d_k_colbase, P.d_k_xidx, P.d_hat_rowbase, P.d_hat_colbase, P.d_hat_xidx,
+                    P.d_k_desc, P.d_hat_desc,
                     P.d_kb_rows, P.d_blk_row, P.d_blk_mirror};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);

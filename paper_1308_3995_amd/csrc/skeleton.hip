@@ -16,6 +16,8 @@
 // host round trip per iteration; the host reads the flag once per cycle. Reductions
 // are two-stage and fixed-order (per-block partials, then a redundant reduction by the
 // consumer blocks), so results are deterministic.
+#include <hip/hip_fp16.h>
+
 #include <cmath>
 #include <functional>
 #include <vector>
@@ -45,6 +47,7 @@ SolverLayout solver_layout(const Plan& p, int restart) {
     L.minv = carve(p.diag_off.back() / 2 * 8);
     L.hat = carve(p.hat_values * 8);
     L.hat32 = carve(p.hat_values * 4);
+    L.hat16 = carve(p.hat_values * 2);
     L.V = carve(kmv * n * 8);
     L.Z = carve((int64_t)restart * n * 8);
     L.pvec = carve(3 * n * 8);
@@ -118,10 +121,10 @@ __global__ void k_bj_invert(int nf, const int64_t* face_off, const int64_t* row_
     }
 }
 
-// Khat_fg = K_fg M_g^-1 for every off-diagonal block; optional float32 copy.
+// Khat_fg = K_fg M_g^-1 for every off-diagonal block; optional float32 and float16 copies.
 __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_row_ptr, const int32_t* hat_col,
                             const int64_t* hat_val_off, const int64_t* hat_src, const int64_t* diag_off,
-                            const double* bsr, const double* minv, double* hat, float* hat32) {
+                            const double* bsr, const double* minv, double* hat, float* hat32, __half* hat16) {
     const int f = blockIdx.x;
     if (f >= nf) return;
     const int sf = (int)(face_off[f + 1] - face_off[f]);
@@ -136,6 +139,7 @@ __global__ void k_hat_build(int nf, const int64_t* face_off, const int64_t* hat_
             for (int k = 0; k < sg; ++k) acc += Kb[(int64_t)k * sf + r] * Mi[(int64_t)c * sg + k];
             hat[hat_val_off[b] + t] = acc;
             if (hat32) hat32[hat_val_off[b] + t] = (float)acc;
+            if (hat16) hat16[hat_val_off[b] + t] = __float2half((float)acc);
         }
     }
 }
@@ -180,9 +184,7 @@ struct GmArgs {
     int B2;           // blocks of the vector kernels
     int64_t chunk;    // vector entries per vector-kernel block
     const int64_t* face_off;
-    const int64_t* rb;      // row slabs of the matrix: value offset of each face row's slab,
-    const int64_t* cb;      // its first column in xi, and
-    const int32_t* xi;      // the skeleton index of every slab column
+    const SlabDesc* sd;     // row slabs of the matrix (one descriptor per face row)
     double* V;        // (m+1) x n
     double* Z;        // m x n: z_j = p(Khat) v_j (polynomial preconditioning)
     double* y;        // SpMV output
@@ -246,89 +248,157 @@ __device__ __forceinline__ double wave_reduce_many(double (&v)[NV]) {
     return r;
 }
 
-// 16-byte vector of matrix values: CH consecutive rows of one slab column.
+// Chunk of matrix values: CH consecutive rows of one slab column (16 bytes for float and
+// double; 8 bytes of float16, since a face's row count 4 (p + 1) need not be a multiple of 8).
+struct half4 {
+    __half2 lo, hi;
+};
 template <typename VT> struct Vec16;
 template <> struct Vec16<float> { using T = float4; static constexpr int CH = 4; };
 template <> struct Vec16<double> { using T = double2; static constexpr int CH = 2; };
+template <> struct Vec16<__half> { using T = half4; static constexpr int CH = 4; };
 
-template <typename T>
-__device__ __forceinline__ double comp(const T& v, int k);
-template <> __device__ __forceinline__ double comp<float4>(const float4& v, int k) {
+__device__ __forceinline__ double comp(const float4& v, int k) {
     return (double)(k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w);
 }
-template <> __device__ __forceinline__ double comp<double2>(const double2& v, int k) { return k == 0 ? v.x : v.y; }
+__device__ __forceinline__ double comp(const double2& v, int k) { return k == 0 ? v.x : v.y; }
+__device__ __forceinline__ double comp(const half4& v, int k) {
+    const __half2 h = k < 2 ? v.lo : v.hi;
+    return (double)__half2float((k & 1) ? __high2half(h) : __low2half(h));
+}
 
-constexpr int kSlabIt = 8;   // 16-byte loads per lane issued back to back
-
-// One face row of t = (row slab of f) src by one wave: the slab is s x W column-major (s the
-// face's unknowns, W the summed widths of the row's stored blocks), read in 16-byte chunks of
-// CH rows; lane l takes chunk row l % G (G = s / CH) of the columns l / G + k L (L = 64 / G),
-// so every load of the wave reads consecutive memory. The lanes' partial row sums are added
-// in a fixed order through LDS (red: 64 CH doubles of this wave). Lane r < s returns row r.
-template <typename VT>
-__device__ __forceinline__ double slab_row(const GmArgs& a, const VT* val, const double* src, int f, int lane,
-                                           double* red) {
+// Rows of the slab SpMV t = (row slab of f) src, NR face rows per wave with every load in flight
+// together. The slab is s x W column-major, read in chunks of CH rows: lane l takes chunk row
+// l % G (G = s / CH) of the columns l / G + k L (L = 64 / G), so every load of the wave reads
+// consecutive memory; the gather index of column c comes from the row's descriptor (no index
+// array). NI chunks per lane and row are loaded in one batch (a row wider than NI L columns
+// takes further, serial batches). The lanes' partial row sums are added in a fixed order
+// through LDS (red: 64 CH doubles of this wave).
+template <typename VT, int NR>
+struct SlabRows {
     using VV = typename Vec16<VT>::T;
-    constexpr int CH = Vec16<VT>::CH;
-    const int s = (int)(a.face_off[f + 1] - a.face_off[f]);
-    const int G = s / CH, L = 64 / G;
-    const int g = lane % G, c0 = lane / G;
-    const int64_t cbase = a.cb[f];
-    const int W = (int)(a.cb[f + 1] - cbase);
-    const VT* slab = val + a.rb[f] + g * CH;
-    const int32_t* xi = a.xi + cbase;
-    double acc[CH];
+    static constexpr int CH = Vec16<VT>::CH;
+    static constexpr int NI = sizeof(VT) == 8 ? 8 : 4;
+    VV v[NR][NI];
+    double x[NR][NI];
+    // descriptor fields (wave-uniform) and this lane's place in the slab
+    int64_t rb[NR];
+    int fo[NR], s[NR], W[NR], G[NR], L[NR], c0[NR], g[NR];
+    int bo0[NR], bo1[NR], bo2[NR], bo3[NR], bo4[NR], bc1[NR], bc2[NR], bc3[NR], bc4[NR];
+    bool live[NR];
+
+    // skeleton index of slab column c: the block is the last one starting at or before c (the
+    // block starts increase; absent blocks start at W > c), selected without branches
+    __device__ __forceinline__ int gather(int r, int c) const {
+        int bo = bo0[r], bc = 0;
+        bo = c >= bc1[r] ? bo1[r] : bo;
+        bc = c >= bc1[r] ? bc1[r] : bc;
+        bo = c >= bc2[r] ? bo2[r] : bo;
+        bc = c >= bc2[r] ? bc2[r] : bc;
+        bo = c >= bc3[r] ? bo3[r] : bo;
+        bc = c >= bc3[r] ? bc3[r] : bc;
+        bo = c >= bc4[r] ? bo4[r] : bo;
+        bc = c >= bc4[r] ? bc4[r] : bc;
+        return bo + c - bc;
+    }
+
+    // f[r] < 0: no row (its products are zero; loads go to row 0 and are discarded)
+    __device__ __forceinline__ void load_desc(const GmArgs& a, const int (&f)[NR], int lane) {
 #pragma unroll
-    for (int k = 0; k < CH; ++k) acc[k] = 0.0;
-    if (c0 < L) {
-        for (int cs = c0; cs < W; cs += kSlabIt * L) {
-            VV v[kSlabIt];
-            double x[kSlabIt];
-#pragma unroll
-            for (int it = 0; it < kSlabIt; ++it) {
-                const int c = cs + it * L;
-                if (c < W) {
-                    v[it] = *(const VV*)(slab + (int64_t)c * s);
-                    x[it] = src[xi[c]];
-                } else {
-                    v[it] = VV{};
-                    x[it] = 0.0;
-                }
-            }
-#pragma unroll
-            for (int it = 0; it < kSlabIt; ++it)
-#pragma unroll
-                for (int k = 0; k < CH; ++k) acc[k] += comp(v[it], k) * x[it];
+        for (int r = 0; r < NR; ++r) {
+            const SlabDesc* d = a.sd + (f[r] >= 0 ? f[r] : 0);
+            rb[r] = d->rb;
+            fo[r] = d->fo;
+            s[r] = d->s;
+            W[r] = d->W;
+            bo0[r] = d->boff[0];
+            bo1[r] = d->boff[1];
+            bo2[r] = d->boff[2];
+            bo3[r] = d->boff[3];
+            bo4[r] = d->boff[4];
+            bc1[r] = d->bcol[1];
+            bc2[r] = d->bcol[2];
+            bc3[r] = d->bcol[3];
+            bc4[r] = d->bcol[4];
+            live[r] = f[r] >= 0 && W[r] > 0;
+            G[r] = s[r] / CH;
+            L[r] = 64 / G[r];
+            g[r] = lane % G[r];
+            c0[r] = lane / G[r];
         }
     }
+
+    // every chunk load is unconditional (clamped to the row's last column) and a chunk outside the
+    // row gets a zero source value
+    __device__ __forceinline__ void issue(const VT* val, const double* src) {
 #pragma unroll
-    for (int k = 0; k < CH; ++k) red[lane * CH + k] = acc[k];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double t = 0.0;
-    if (lane < s) {
-        const int gg = lane / CH, k = lane % CH;
-        for (int m = 0; m < L; ++m) t += red[(gg + m * G) * CH + k];
+        for (int r = 0; r < NR; ++r) {
+            const VT* slab = val + rb[r] + g[r] * CH;
+            const int wl = W[r] > 0 ? W[r] - 1 : 0;
+#pragma unroll
+            for (int it = 0; it < NI; ++it) {
+                const int c = c0[r] + it * L[r];
+                const bool ok = live[r] && c0[r] < L[r] && c < W[r];
+                const int cc = c < wl ? c : wl;
+                v[r][it] = *(const VV*)(slab + (int64_t)cc * s[r]);
+                const double xv = src[gather(r, cc)];
+                x[r][it] = ok ? xv : 0.0;
+            }
+        }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    return t;
-}
+
+    // row r's product; lane q < s returns row q (fixed-order sum through red, 64 CH doubles).
+    // r is a template argument so that the row arrays stay in registers.
+    template <int r>
+    __device__ __forceinline__ double finish(const VT* val, const double* src, int lane, double* red) {
+        double acc[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) acc[k] = 0.0;
+#pragma unroll
+        for (int it = 0; it < NI; ++it)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) acc[k] += comp(v[r][it], k) * x[r][it];
+        if (live[r] && W[r] > NI * L[r] && c0[r] < L[r]) {
+            const VT* slab = val + rb[r] + g[r] * CH;
+            for (int c = c0[r] + NI * L[r]; c < W[r]; c += L[r]) {
+                const VV vv = *(const VV*)(slab + (int64_t)c * s[r]);
+                const double xx = src[gather(r, c)];
+#pragma unroll
+                for (int k = 0; k < CH; ++k) acc[k] += comp(vv, k) * xx;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) red[lane * CH + k] = acc[k];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double t = 0.0;
+        if (lane < s[r]) {
+            const int gg = lane / CH, k = lane % CH;
+            for (int m = 0; m < L[r]; ++m) t += red[(gg + m * G[r]) * CH + k];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        return t;
+    }
+};
 
 // One face row of y = scale (src + Khat src) (IDENT: Khat's identity diagonal is not stored)
 // or y = K src (no identity). Returns this lane's output (valid for lane < s); xv = scale src.
 template <typename VT, bool IDENT>
 __device__ __forceinline__ double row_spmv(const GmArgs& a, const VT* val, const double* src, double scale, int f,
                                            int lane, double* red, double& xv) {
-    const double t = slab_row<VT>(a, val, src, f, lane, red);
-    const int64_t fo = a.face_off[f];
-    const int s = (int)(a.face_off[f + 1] - fo);
+    SlabRows<VT, 1> sr;
+    const int ff[1] = {f};
+    sr.load_desc(a, ff, lane);
+    sr.issue(val, src);
+    const double t = sr.template finish<0>(val, src, lane, red);
+    const int s = sr.s[0];
     xv = 0.0;
     double out = 0.0;
     if (lane < s) {
-        xv = scale * src[fo + lane];
+        xv = scale * src[sr.fo[0] + lane];
         out = IDENT ? scale * t + xv : t;
     }
     return out;
@@ -388,27 +458,45 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
     __shared__ double xf[kRowsPerBlock * 4 * (kMaxDegree + 1)];
     __shared__ double sh[8];
     __shared__ double gcol[kMaxV + 1];
-    if (a.scal[SC_DONE] != 0.0) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int f0 = blockIdx.x * kRowsPerBlock;
-    // partial sum of the ||w_{j-1}||^2 block partials, loaded before the SpMV so that the
-    // reduction below overlaps with it
-    double npart = 0.0;
-    if constexpr (CNT > 1 && !POLY)
-        for (int b = threadIdx.x; b < a.B2; b += blockDim.x) npart += a.P3[b];
+    const double done = a.scal[SC_DONE];
     const int j = cnt - 1;
     double* vj = a.V + (int64_t)j * a.n;
     const int flast = f0 + kRowsPerBlock < a.nf ? f0 + kRowsPerBlock : a.nf;
     const int64_t e0 = a.face_off[f0];
     const int ne = (int)(a.face_off[flast] - e0);
-    // unscaled rows: t = Khat src and src itself (y = scale t + scale src below)
+    // unscaled rows: t = Khat src and src itself (y = scale t + scale src below); the flag and
+    // both rows' descriptors are read together, then every load of both rows is issued
     double tout[kRowsPerWave], tsrc[kRowsPerWave];
+    int fo[kRowsPerWave], fs[kRowsPerWave];
+    int f[kRowsPerWave];
 #pragma unroll
-    for (int rr = 0; rr < kRowsPerWave; ++rr) {
-        const int f = f0 + rr * 4 + wave;
-        tout[rr] = tsrc[rr] = 0.0;
-        if (f < a.nf) tout[rr] = row_spmv<VT, false>(a, val, src, 1.0, f, lane, red[wave], tsrc[rr]);
+    for (int r = 0; r < kRowsPerWave; ++r) {
+        const int ff = f0 + r * 4 + wave;
+        f[r] = ff < a.nf ? ff : -1;
     }
+    static_assert(kRowsPerWave == 2, "two rows per wave");
+    SlabRows<VT, 1> sr0, sr1;
+    const int f0a[1] = {f[0]}, f1a[1] = {f[1]};
+    sr0.load_desc(a, f0a, lane);
+    sr1.load_desc(a, f1a, lane);
+    asm volatile("" ::: "memory");
+    if (done != 0.0) return;
+    sr0.issue(val, src);
+    sr1.issue(val, src);
+    fo[0] = f[0] >= 0 ? sr0.fo[0] : 0;
+    fs[0] = f[0] >= 0 ? sr0.s[0] : 0;
+    fo[1] = f[1] >= 0 ? sr1.fo[0] : 0;
+    fs[1] = f[1] >= 0 ? sr1.s[0] : 0;
+    tsrc[0] = lane < fs[0] ? src[fo[0] + lane] : 0.0;
+    tsrc[1] = lane < fs[1] ? src[fo[1] + lane] : 0.0;
+    // the ||w_{j-1}||^2 block partials, summed while the SpMV loads are in flight
+    double npart = 0.0;
+    if constexpr (CNT > 1 && !POLY)
+        for (int b = threadIdx.x; b < a.B2; b += blockDim.x) npart += a.P3[b];
+    tout[0] = f[0] >= 0 ? sr0.template finish<0>(val, src, lane, red[wave]) : 0.0;
+    tout[1] = f[1] >= 0 ? sr1.template finish<0>(val, src, lane, red[wave]) : 0.0;
     double scale = 1.0;
     if constexpr (POLY) {
         scale = 1.0;
@@ -423,20 +511,15 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dots(GmArgs a, const VT* val,
     }
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWave; ++rr) {
-        const int f = f0 + rr * 4 + wave;
-        if (f < a.nf) {
-            const int64_t fo = a.face_off[f];
-            const int s = (int)(a.face_off[f + 1] - fo);
-            if (lane < s) {
-                const double xv = scale * tsrc[rr];
-                const double out = scale * tout[rr] + xv;
-                a.y[fo + lane] = out;
-                if constexpr (!POLY) {
-                    vj[fo + lane] = xv;
-                    xf[fo - e0 + lane] = xv;
-                }
-                yf[fo - e0 + lane] = out;
+        if (lane < fs[rr]) {
+            const double xv = scale * tsrc[rr];
+            const double out = scale * tout[rr] + xv;
+            a.y[fo[rr] + lane] = out;
+            if constexpr (!POLY) {
+                vj[fo[rr] + lane] = xv;
+                xf[fo[rr] - e0 + lane] = xv;
             }
+            yf[fo[rr] - e0 + lane] = out;
         }
     }
     __syncthreads();
@@ -495,29 +578,38 @@ struct PolyOp {
 };
 constexpr int kMaxPolyOps = kMaxRestart;
 
+// One face row per wave, four per workgroup (grid: ceil(nf / 4) workgroups).
+constexpr int kPolyRowsPerBlock = 4;
+
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_poly_op(GmArgs a, const VT* val, const PolyOp* ops, int op,
                                                       const double* src, const double* base, double* out, double* y) {
     constexpr int CH = Vec16<VT>::CH;
     __shared__ double red[4][64 * CH];
-    if (a.scal[SC_DONE] != 0.0) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int ff = blockIdx.x * kPolyRowsPerBlock + wave;
+    const int f[1] = {ff < a.nf ? ff : -1};
+    // the flag, the op and the row's descriptor are read together (scalar loads): the compiler
+    // barrier keeps the descriptor loads ahead of the early return
+    const double done = a.scal[SC_DONE];
     const PolyOp o = ops[op];
-#pragma unroll
-    for (int rr = 0; rr < kRowsPerWave; ++rr) {
-        const int f = blockIdx.x * kRowsPerBlock + rr * 4 + wave;
-        if (f >= a.nf) continue;
-        double xv;
-        const double t = row_spmv<VT, true>(a, val, src, 1.0, f, lane, red[wave], xv);
-        const int64_t fo = a.face_off[f];
-        const int s = (int)(a.face_off[f + 1] - fo);
-        if (lane < s) {
-            const int64_t e = fo + lane;
-            const double ov = (o.b0 != 0.0 ? o.b0 * base[e] : 0.0) + o.b1 * xv + o.b2 * t;
-            if (o.wout) out[e] = ov;
-            const double yv = (o.first ? 0.0 : y[e]) + o.a1 * xv + o.gam * ov;
-            y[e] = yv;
-        }
+    SlabRows<VT, 1> sr;
+    sr.load_desc(a, f, lane);
+    asm volatile("" ::: "memory");
+    if (done != 0.0 || f[0] < 0) return;
+    sr.issue(val, src);
+    // the entries of this lane's output row: own source value, previous iterate, y
+    double xs = 0.0, bs = 0.0, ys = 0.0;
+    const bool mine = lane < sr.s[0];
+    const int64_t e = sr.fo[0] + (mine ? lane : 0);
+    xs = src[e];
+    if (o.b0 != 0.0) bs = base[e];
+    if (!o.first) ys = y[e];
+    const double t = xs + sr.template finish<0>(val, src, lane, red[wave]);
+    if (mine) {
+        const double ov = o.b0 * bs + o.b1 * xs + o.b2 * t;
+        if (o.wout) out[e] = ov;
+        y[e] = ys + o.a1 * xs + o.gam * ov;
     }
 }
 
@@ -893,6 +985,8 @@ bool hessenberg_eigenvalues(int n, std::vector<double> H, double* wr, double* wi
 struct Poly {
     int degree = 0;
     std::vector<PolyOp> ops;
+    const void* mat = nullptr;   // the matrix its SpMVs read: Khat in float64, float32 or float16
+    int mat_bytes = 8;
 };
 
 // Ops of p(Khat) from the roots (wr, wi) of the residual polynomial. Buffer ids: 0 = v_j,
@@ -1043,6 +1137,7 @@ struct Solver {
     GmArgs gk;        // skeleton matrix K (true residual)
     double *minv, *hat, *x, *u, *r;
     float* hat32;
+    __half* hat16;
     double* pbuf[4];  // polynomial vectors: [0] unused (v_j), [1], [2] ping-pong, [3] q
     PolyOp* ops;
 };
@@ -1077,10 +1172,18 @@ static void launch_step(Plan& p, const GmArgs& a, const Solver& S, const VT* hat
             for (size_t k = 0; k < poly->ops.size(); ++k) {
                 const PolyOp& o = poly->ops[k];
                 auto buf = [&](int id) -> double* { return id == 0 ? const_cast<double*>(vj) : S.pbuf[id]; };
+                const dim3 gp((a.nf + kPolyRowsPerBlock - 1) / kPolyRowsPerBlock);
                 mark_begin();
-                hipLaunchKernelGGL((k_poly_op<VT>), g1, blk, 0, s, a, hat, S.ops, (int)k, buf(o.src_id),
-                                   buf(o.base_id), buf(o.out_id), z);
-                mark_end(0, nval * sizeof(VT) +
+                if (poly->mat_bytes == 2)
+                    hipLaunchKernelGGL((k_poly_op<__half>), gp, blk, 0, s, a, (const __half*)poly->mat, S.ops, (int)k,
+                                       buf(o.src_id), buf(o.base_id), buf(o.out_id), z);
+                else if (poly->mat_bytes == 4)
+                    hipLaunchKernelGGL((k_poly_op<float>), gp, blk, 0, s, a, (const float*)poly->mat, S.ops, (int)k,
+                                       buf(o.src_id), buf(o.base_id), buf(o.out_id), z);
+                else
+                    hipLaunchKernelGGL((k_poly_op<double>), gp, blk, 0, s, a, (const double*)poly->mat, S.ops, (int)k,
+                                       buf(o.src_id), buf(o.base_id), buf(o.out_id), z);
+                mark_end(0, nval * poly->mat_bytes +
                                 n * 8.0 * (1.0 + (o.b0 != 0.0 ? 1.0 : 0.0) + (o.first ? 1.0 : 2.0) + (o.wout ? 1.0 : 0.0)));
             }
             mark_begin();
@@ -1104,6 +1207,7 @@ static Solver make_solver(Plan& p, char* ws) {
     S.minv = (double*)(base + L.minv);
     S.hat = (double*)(base + L.hat);
     S.hat32 = (float*)(base + L.hat32);
+    S.hat16 = (__half*)(base + L.hat16);
     S.x = (double*)(base + L.x);
     S.u = (double*)(base + L.y);
     S.r = (double*)(base + L.r);
@@ -1135,13 +1239,9 @@ static Solver make_solver(Plan& p, char* ws) {
     a.gb = a.ga + (kMaxV + 1);
     a.scal = (double*)(base + L.scal);
     S.gk = a;
-    S.gk.rb = p.d_k_rowbase;
-    S.gk.cb = p.d_k_colbase;
-    S.gk.xi = p.d_k_xidx;
+    S.gk.sd = p.d_k_desc;
     S.ga = a;
-    S.ga.rb = p.d_hat_rowbase;
-    S.ga.cb = p.d_hat_colbase;
-    S.ga.xi = p.d_hat_xidx;
+    S.ga.sd = p.d_hat_desc;
     return S;
 }
 
@@ -1203,6 +1303,7 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
             mix((uint64_t)(uintptr_t)a.scal);
             mix((uint64_t)m);
             if (poly) {
+                mix((uint64_t)(uintptr_t)poly->mat);
                 mix((uint64_t)poly->ops.size());
                 for (const PolyOp& o : poly->ops)
                     mix((uint64_t)(o.src_id | o.base_id << 4 | o.out_id << 8 | o.wout << 12 | o.first << 13));
@@ -1307,7 +1408,8 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
     hipLaunchKernelGGL(k_bj_invert, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_row_ptr, p.d_val_off,
                        p.d_diag_off, bsr, S.minv, S.ga.scal);
     hipLaunchKernelGGL(k_hat_build, dim3(p.nf), dim3(256), 0, s, p.nf, p.d_face_off, p.d_hat_row_ptr, p.d_hat_col,
-                       p.d_hat_val_off, p.d_hat_src, p.d_diag_off, bsr, S.minv, S.hat, mixed ? S.hat32 : nullptr);
+                       p.d_hat_val_off, p.d_hat_src, p.d_diag_off, bsr, S.minv, S.hat, mixed ? S.hat32 : nullptr,
+                       mixed && p.poly_half ? S.hat16 : nullptr);
     double sing = 0.0;
     HIPCHK(hipMemcpyAsync(&sing, S.ga.scal + SC_SINGULAR, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1344,6 +1446,8 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
                 st = build_poly<double>(p, S, S.hat, rhs, pdeg, max_iter - total, tol, s, poly, have_poly, &it, &est);
                 if (st != HDG_OK) return st;
                 total += it;
+                poly.mat = S.hat;
+                poly.mat_bytes = 8;
             }
             if (total < max_iter && !(est <= tol && it > 0)) {
                 int it2 = 0;
@@ -1391,6 +1495,9 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
                                            &it, &est);
                 if (st != HDG_OK) return st;
                 total += it;
+                // the polynomial is a preconditioner: its products may read a float16 copy of Khat
+                poly.mat = p.poly_half ? (const void*)S.hat16 : (const void*)S.hat32;
+                poly.mat_bytes = p.poly_half ? 2 : 4;
             }
             if (total < max_iter && !(est <= inner_tol && it > 0)) {
                 int it2 = 0;
