@@ -314,6 +314,19 @@ hdg_status hdg_mark_elements(hdg_plan* plan, const double* w_dev, const double* 
                              int32_t* flag_dev, double* sensor_dev, int32_t* n_marked_host, void* workspace_dev,
                              hipStream_t stream);
 
+/* hdg_mark_elements without a workspace, for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with the count, the sort buffers, the radix-sort scratch and (when
+ * sensor_dev is NULL) the sensor in a static device array of 16 MiB that each GPU the library
+ * runs on holds until the process ends; the call allocates nothing. That bounds the mesh:
+ * 256 + 8 ne (no sensor_dev) + 24 ne + the radix sort's scratch bytes must fit, about 400k
+ * elements; larger meshes get HDG_ERR_INVALID_ARG. Every call on one GPU shares the array:
+ * calls that overlap on the same GPU (several streams or threads) race and must be serialised
+ * by the caller. Other arguments and errors as hdg_mark_elements. */
+hdg_status hdg_mark_elements_noalloc(hdg_plan* plan, const double* w_dev, const double* eta_dev, double theta,
+                                     double eps_s, int32_t* flag_dev, double* sensor_dev, int32_t* n_marked_host,
+                                     hipStream_t stream);
+
 /* Inspection entry for tests: the uncondensed element blocks of one element in the
  * unknown order documented above (element: Navier-Stokes gradient fields 4d+a first,
  * then w fields, each mode-minor; faces: interior local faces in order, each

@@ -227,6 +227,15 @@ class HDGPlan:
                                          C.byref(m), _vp(self.ws), _stream(stream)))
         return flag[: self.ne], sensor[: self.ne], m.value
 
+    def hdg_mark_elements_noalloc(self, w, eta, flag, sensor=None, theta: float = 0.05, eps_s: float = 1e-6,
+                                  stream=None):
+        """hdg_mark_elements on the library's static device scratch (no workspace, nothing
+        allocated): fills the caller's flag (and sensor, if given) tensors, returns n_marked."""
+        m = C.c_int32(0)
+        check(self.lib.hdg_mark_elements_noalloc(self.handle, _vp(w), _vp(eta), theta, eps_s, _vp(flag),
+                                                 _vp(sensor), C.byref(m), _stream(stream)))
+        return m.value
+
     # ---- skeleton-solver options and kernel timing (benchmarks)
     def hdg_set_poly_degree(self, degree: int, fp16_matrix: bool = True):
         """Degree of the GMRES polynomial preconditioner (0 or 1: plain block-Jacobi GMRES) and, in

@@ -21,7 +21,7 @@ EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_patt
            "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
            "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_set_cfl", "hdg_residual_norm", "hdg_apply_update",
            "hdg_cfl_schedule", "hdg_pseudo_transient_solve", "hdg_skeleton_transpose", "hdg_adjoint_rhs",
-           "hdg_adjoint_local", "hdg_mark_elements", "hdg_set_poly_degree", "hdg_debug_hessenberg_eigenvalues",
+           "hdg_adjoint_local", "hdg_mark_elements", "hdg_mark_elements_noalloc", "hdg_set_poly_degree", "hdg_debug_hessenberg_eigenvalues",
            "hdg_last_error", "hdg_plan_destroy"]
 
 
@@ -91,6 +91,7 @@ def load(path: str = LIB_PATH):
     lib.hdg_adjoint_rhs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_adjoint_local.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_mark_elements.argtypes = [vp, vp, vp, dbl, dbl, vp, vp, P(i32), vp, vp]
+    lib.hdg_mark_elements_noalloc.argtypes = [vp, vp, vp, dbl, dbl, vp, vp, P(i32), vp]
     lib.hdg_last_error.argtypes = []
     lib.hdg_last_error.restype = C.c_char_p
     lib.hdg_plan_destroy.argtypes = [vp]

@@ -16,6 +16,8 @@ void set_error(const std::string& msg) { g_err = msg; }
 hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int ne, const int8_t* degree,
                       const hdg_params& prm, int device);
 void free_plan(Plan& P);
+hdg_status mark_elements_noalloc(const Plan& p, const double* w, const double* eta, double theta, double eps_s,
+                                 int32_t* flag, double* sensor, int32_t* n_marked_host, hipStream_t s);
 }  // namespace hdg
 
 using namespace hdg;
@@ -591,6 +593,20 @@ hdg_status hdg_mark_elements(hdg_plan* plan, const double* w_dev, const double* 
         CHECK_HIP(hipStreamSynchronize(stream));
     }
     return HDG_OK;
+}
+
+hdg_status hdg_mark_elements_noalloc(hdg_plan* plan, const double* w_dev, const double* eta_dev, double theta,
+                                     double eps_s, int32_t* flag_dev, double* sensor_dev, int32_t* n_marked_host,
+                                     hipStream_t stream) {
+    if (!plan || !w_dev || !eta_dev || !flag_dev) {
+        set_error("hdg_mark_elements_noalloc: null argument");
+        return HDG_ERR_INVALID_ARG;
+    }
+    if (!(theta >= 0.0 && theta <= 1.0) || !(eps_s >= 0.0)) {
+        set_error("hdg_mark_elements_noalloc: need 0 <= theta <= 1 and eps_s >= 0");
+        return HDG_ERR_INVALID_ARG;
+    }
+    return mark_elements_noalloc(plan->p, w_dev, eta_dev, theta, eps_s, flag_dev, sensor_dev, n_marked_host, stream);
 }
 
 hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const double* w_dev, const double* q_dev,

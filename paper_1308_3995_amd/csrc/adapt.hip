@@ -13,6 +13,9 @@
 // refinement (2); unmarked elements get 0.
 #include <hipcub/hipcub.hpp>
 
+#include <mutex>
+#include <string>
+
 #include "hdg_internal.h"
 
 namespace hdg {
@@ -116,6 +119,79 @@ hipError_t launch_mark(const Plan& p, const double* w, const double* eta, double
     hipLaunchKernelGGL(k_dorfler, dim3(1), dim3(kScanThreads), 0, s, n, key_sorted, theta, m_dev);
     hipLaunchKernelGGL(k_mark, dim3((n + 255) / 256), dim3(256), 0, s, n, id_sorted, m_dev, sensor, eps_s, flag);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free marking: the same kernels on a scratch buffer that is a file-scope device
+// array (one copy per GPU, held until the process ends) instead of the caller's workspace.
+// Layout as in the workspace's marking region: the marked count (256 bytes), the sensor when
+// the caller passes none (ne doubles), then the sort buffers and the radix-sort scratch.
+// ---------------------------------------------------------------------------
+constexpr int64_t kMarkScratchMax = (int64_t)16 << 20;   // 16 MiB per GPU
+
+static __device__ __align__(256) char scratch[kMarkScratchMax];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` on each GPU
+}  // namespace
+
+int64_t mark_noalloc_need(const Plan& p, bool own_sensor) {
+    return 256 + (own_sensor ? (int64_t)p.ne * 8 : 0) + mark_scratch_bytes(p);
+}
+
+hdg_status mark_elements_noalloc(const Plan& p, const double* w, const double* eta, double theta, double eps_s,
+                                 int32_t* flag, double* sensor, int32_t* n_marked_host, hipStream_t s) {
+    const int64_t need = mark_noalloc_need(p, sensor == nullptr);
+    if (need > kMarkScratchMax) {
+        set_error("hdg_mark_elements_noalloc: the mesh needs " + std::to_string(need) +
+                  " bytes of marking scratch, more than the static " + std::to_string(kMarkScratchMax) +
+                  " (use hdg_mark_elements with a workspace)");
+        return HDG_ERR_INVALID_ARG;
+    }
+    hipError_t e = hipSetDevice(p.device);
+    if (e != hipSuccess || p.device < 0 || p.device >= kMaxDevices) {
+        set_error(std::string("hdg_mark_elements_noalloc: device ") + std::to_string(p.device) + ": " +
+                  hipGetErrorString(e));
+        return e == hipSuccess ? HDG_ERR_INVALID_ARG : HDG_ERR_HIP;
+    }
+    char* base = nullptr;
+    {
+        // once per device, with that device current: the array's address on this GPU
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (!g_scratch_ptr[p.device]) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr) {
+                set_error(std::string("hdg_mark_elements_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+                return HDG_ERR_HIP;
+            }
+            g_scratch_ptr[p.device] = (char*)ptr;
+        }
+        base = g_scratch_ptr[p.device];
+    }
+    int32_t* m_dev = (int32_t*)base;
+    double* sens = sensor ? sensor : (double*)(base + 256);
+    char* sort = base + 256 + (sensor ? 0 : (int64_t)p.ne * 8);
+    e = launch_mark(p, w, eta, theta, eps_s, sens, flag, sort, m_dev, s);
+    if (e != hipSuccess) {
+        set_error(std::string("hdg_mark_elements_noalloc: ") + hipGetErrorString(e));
+        return HDG_ERR_HIP;
+    }
+    if (n_marked_host) {
+        if (p.ne == 0) {
+            *n_marked_host = 0;
+            return HDG_OK;
+        }
+        e = hipMemcpyAsync(n_marked_host, m_dev, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error(std::string("hdg_mark_elements_noalloc: ") + hipGetErrorString(e));
+            return HDG_ERR_HIP;
+        }
+    }
+    return HDG_OK;
 }
 
 }  // namespace hdg
