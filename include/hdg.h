@@ -114,10 +114,13 @@ typedef struct hdg_plan hdg_plan;
  * basis and quadrature tables, and far-field projectors. Host inputs:
  *   xy_host[nv][2] vertex coordinates, tri_host[ne][3] vertex ids (counter-clockwise),
  *   degree_host[ne] element degrees in 1..5.
- * Allocates device memory on `device`. The mesh data of a plan never change; a plan does
- * cache the kernel variants its first assembly picks, captured launch graphs and the CFL
- * of hdg_set_cfl, so calls on one plan must not overlap one another; different plans may
- * be used at the same time from different host threads and streams. Errors:
+ * Allocates device memory on `device`. The mesh data of a plan never change. A plan may be
+ * shared by several streams and host threads: its caches (the kernel variants the first
+ * assembly picks by timing, the launch graphs captured per set of buffers) are guarded by a
+ * lock, and calls whose buffers (outputs and workspace) differ may run concurrently; calls
+ * that share a buffer race. Plan-level settings (hdg_set_cfl, hdg_set_poly_degree,
+ * hdg_set_kernel_timing) apply to every later call and are not meant to change while other
+ * calls on the plan are in flight. Errors:
  * HDG_ERR_INVALID_ARG (bad sizes, ids, degrees,
  * an edge shared by more than two triangles), HDG_ERR_SINGULAR_LOCAL (a triangle of
  * non-positive area), HDG_ERR_OOM, HDG_ERR_HIP. */

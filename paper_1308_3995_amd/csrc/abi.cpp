@@ -230,47 +230,29 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
     };
     hipError_t e = hipSuccess;
     bool launched = false;
-    if (p.tuned && p.use_graphs) {
-        // after the first call (which picks the kernel variants) the sequence is captured once
-        // per set of buffers and replayed
-        uint64_t key = 1469598103934665603ull;
-        auto mix = [&](const void* v) { key = (key ^ (uint64_t)(uintptr_t)v) * 1099511628211ull; };
-        for (const void* v : {(const void*)w_dev, (const void*)q_dev, (const void*)lam_dev, (const void*)bsr_values_dev,
-                              (const void*)rhs_dev, (const void*)local_store_dev, (const void*)ws, (const void*)status})
-            mix(v);
-        uint64_t cfl_bits;
-        std::memcpy(&cfl_bits, &p.prm.cfl, 8);   // the CFL is a kernel argument baked into the graph
-        key = (key ^ cfl_bits) * 1099511628211ull;
-        if (!p.cond_exec || p.cond_key != key) {
-            if (p.cond_exec) (void)hipGraphExecDestroy(p.cond_exec);
-            if (p.cond_graph) (void)hipGraphDestroy(p.cond_graph);
-            p.cond_exec = nullptr;
-            p.cond_graph = nullptr;
-            std::lock_guard<std::mutex> lock(device_mutex());
-            if (!p.capture_stream) CHECK_HIP(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
-            hipError_t ce = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeRelaxed);
-            if (ce == hipSuccess) {
-                hipError_t le = enqueue(p.capture_stream);
-                ce = hipStreamEndCapture(p.capture_stream, &p.cond_graph);
-                if (ce == hipSuccess) ce = le;
-            }
-            if (ce == hipSuccess) ce = hipGraphInstantiate(&p.cond_exec, p.cond_graph, nullptr, nullptr, 0);
-            if (ce != hipSuccess) {
-                (void)hipGetLastError();
-                if (p.cond_exec) (void)hipGraphExecDestroy(p.cond_exec);
-                if (p.cond_graph) (void)hipGraphDestroy(p.cond_graph);
-                p.cond_exec = nullptr;
-                p.cond_graph = nullptr;
-            } else {
-                p.cond_key = key;
+    {
+        std::lock_guard<std::mutex> plan_lock(p.cache_mu);
+        if (p.tuned && p.use_graphs) {
+            // after the first call (which picks the kernel variants) the sequence is captured once
+            // per set of buffers and replayed
+            uint64_t key = 0x636f6e64656e7365ull;   // distinct from the solver's cycle keys
+            auto mix = [&](const void* v) { key = (key ^ (uint64_t)(uintptr_t)v) * 1099511628211ull; };
+            for (const void* v : {(const void*)w_dev, (const void*)q_dev, (const void*)lam_dev,
+                                  (const void*)bsr_values_dev, (const void*)rhs_dev, (const void*)local_store_dev,
+                                  (const void*)ws, (const void*)status})
+                mix(v);
+            uint64_t cfl_bits;
+            std::memcpy(&cfl_bits, &p.prm.cfl, 8);   // the CFL is a kernel argument baked into the graph
+            key = (key ^ cfl_bits) * 1099511628211ull;
+            hipGraphExec_t x = graph_find(p, key);
+            if (!x) x = graph_capture(p, key, enqueue);
+            if (x) {
+                e = hipGraphLaunch(x, stream);
+                launched = true;
             }
         }
-        if (p.cond_exec) {
-            e = hipGraphLaunch(p.cond_exec, stream);
-            launched = true;
-        }
+        if (!launched) e = enqueue(stream);
     }
-    if (!launched) e = enqueue(stream);
     if (e == hipErrorInvalidValue) {
         set_error("hdg_assemble_condense: element degree or face degree outside the built kernels (1..5)");
         return HDG_ERR_INVALID_ARG;

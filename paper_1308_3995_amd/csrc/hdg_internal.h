@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hdg.h"
@@ -76,6 +78,10 @@ struct SlabDesc {
     int32_t bcol[5];      // first slab column of each block
 };
 static_assert(sizeof(SlabDesc) == 64, "one 64-byte record per face row");
+
+// Serialises graph captures against plan creation and destruction (device allocation,
+// uploads and frees), so that several host threads may drive different plans.
+std::mutex& device_mutex();
 
 struct Plan {
     int device = 0;
@@ -150,21 +156,48 @@ struct Plan {
     int poly_degree = 20;
     int poly_half = 1;
     std::vector<hipEvent_t> t_events;
-    // captured GMRES restart cycles (per matrix precision, plain or polynomial-preconditioned),
-    // replayed with hipGraphLaunch
+    // Captured launch sequences, replayed with hipGraphLaunch: GMRES restart cycles and the
+    // condensation, one per key (every pointer, size and kernel argument baked into the graph,
+    // so calls on different streams with their own buffers have their own graphs). `mu` guards
+    // these caches and the kernel-variant tuning (cache_mu), so one plan may serve several streams.
+    std::mutex cache_mu;
     hipStream_t capture_stream = nullptr;
-    hipGraphExec_t cycle_exec[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipGraph_t cycle_graph[4] = {nullptr, nullptr, nullptr, nullptr};
-    uint64_t cycle_key[4] = {0, 0, 0, 0};
+    std::map<uint64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     bool use_graphs = true;
     // condensation: register-budget variant per bucket (chosen by timing on the first call)
-    // and the captured launch sequence replayed on later calls
     std::vector<int> variant;             // per bucket, -1 until tuned
     bool tuned = false;
-    hipGraphExec_t cond_exec = nullptr;
-    hipGraph_t cond_graph = nullptr;
-    uint64_t cond_key = 0;
 };
+
+// The captured graph of `key` (nullptr if none). Call with p.cache_mu held.
+hipGraphExec_t graph_find(Plan& p, uint64_t key);
+// Capture `enqueue` (a function of the capture stream returning the first launch error) as the
+// graph of `key` and instantiate it; nullptr on failure (the caller launches directly). Call
+// with p.cache_mu held.
+template <typename F>
+hipGraphExec_t graph_capture(Plan& p, uint64_t key, F&& enqueue) {
+    std::lock_guard<std::mutex> lock(device_mutex());
+    if (!p.capture_stream && hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        hipError_t le = enqueue(p.capture_stream);
+        e = hipStreamEndCapture(p.capture_stream, &g);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (x) (void)hipGraphExecDestroy(x);
+        if (g) (void)hipGraphDestroy(g);
+        p.use_graphs = false;   // direct launches from now on
+        return nullptr;
+    }
+    p.graphs[key] = {g, x};
+    return x;
+}
 
 // Workspace carving for the skeleton solver (offsets in bytes from ws_solver).
 struct SolverLayout {
@@ -222,8 +255,5 @@ bool hessenberg_eigenvalues(int n, std::vector<double> H, double* wr, double* wi
 
 void set_error(const std::string& msg);
 
-// Serialises graph captures against plan creation and destruction (device allocation,
-// uploads and frees), so that several host threads may drive different plans.
-std::mutex& device_mutex();
 
 }  // namespace hdg

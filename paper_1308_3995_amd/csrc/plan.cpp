@@ -595,21 +595,21 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     return HDG_OK;
 }
 
+hipGraphExec_t graph_find(Plan& p, uint64_t key) {
+    auto it = p.graphs.find(key);
+    return it == p.graphs.end() ? nullptr : it->second.second;
+}
+
 void free_plan(Plan& P) {
     std::lock_guard<std::mutex> lock(device_mutex());
     for (hipEvent_t e : P.t_events)
         if (e) (void)hipEventDestroy(e);
     P.t_events.clear();
-    for (int i = 0; i < 4; ++i) {
-        if (P.cycle_exec[i]) (void)hipGraphExecDestroy(P.cycle_exec[i]);
-        if (P.cycle_graph[i]) (void)hipGraphDestroy(P.cycle_graph[i]);
-        P.cycle_exec[i] = nullptr;
-        P.cycle_graph[i] = nullptr;
+    for (auto& kv : P.graphs) {
+        if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+        if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
     }
-    if (P.cond_exec) (void)hipGraphExecDestroy(P.cond_exec);
-    if (P.cond_graph) (void)hipGraphDestroy(P.cond_graph);
-    P.cond_exec = nullptr;
-    P.cond_graph = nullptr;
+    P.graphs.clear();
     if (P.capture_stream) (void)hipStreamDestroy(P.capture_stream);
     P.capture_stream = nullptr;
     void* ptrs[] = {P.d_einfo, P.d_tab, P.d_bproj, P.d_face_off, P.d_face_deg, P.d_row_ptr, P.d_col,

@@ -1308,28 +1308,15 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
                 for (const PolyOp& o : poly->ops)
                     mix((uint64_t)(o.src_id | o.base_id << 4 | o.out_id << 8 | o.wout << 12 | o.first << 13));
             }
-            if (!p.cycle_exec[gi] || p.cycle_key[gi] != key) {
-                if (p.cycle_exec[gi]) (void)hipGraphExecDestroy(p.cycle_exec[gi]);
-                if (p.cycle_graph[gi]) (void)hipGraphDestroy(p.cycle_graph[gi]);
-                p.cycle_exec[gi] = nullptr;
-                p.cycle_graph[gi] = nullptr;
-                std::lock_guard<std::mutex> lock(device_mutex());
-                if (!p.capture_stream) HIPCHK(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
-                hipError_t e = hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeRelaxed);
-                if (e == hipSuccess) {
-                    enqueue_cycle(p.capture_stream, steps, nullptr);
-                    e = hipStreamEndCapture(p.capture_stream, &p.cycle_graph[gi]);
-                }
-                if (e == hipSuccess) e = hipGraphInstantiate(&p.cycle_exec[gi], p.cycle_graph[gi], nullptr, nullptr, 0);
-                if (e != hipSuccess) {
-                    (void)hipGetLastError();
-                    p.use_graphs = false;          // fall back to direct launches from now on
-                } else {
-                    p.cycle_key[gi] = key;
-                }
-            }
-            if (p.use_graphs && p.cycle_exec[gi]) {
-                HIPCHK(hipGraphLaunch(p.cycle_exec[gi], s));
+            mix((uint64_t)gi);
+            std::lock_guard<std::mutex> plan_lock(p.cache_mu);
+            hipGraphExec_t x = graph_find(p, key);
+            if (!x) x = graph_capture(p, key, [&](hipStream_t q) {
+                    enqueue_cycle(q, steps, nullptr);
+                    return hipGetLastError();
+                });
+            if (x) {
+                HIPCHK(hipGraphLaunch(x, s));
                 launched = true;
             }
         }
