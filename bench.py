@@ -287,6 +287,55 @@ def condensation_report(names, warmup: int = 5, reps: int = 30, sc_eps0: float =
     return out
 
 
+def full_step_report(name: str, mode: str, rtol: float, restart: int, cfl: float = 0.0, reps: int = 5,
+                     warmup: int = 1, max_iter: int = 200000):
+    """One full Newton step (assemble + condense, skeleton solve to rtol, back-substitution) of a
+    named workload, `warmup` untimed then the median of `reps` HIP-event-timed steps; cfl > 0
+    adds the pseudo-time term of Sec. 3.3 (a relaxed Newton step)."""
+    import torch
+    import hdg_inputs as hi
+    import paper_1308_3995_amd as hdg
+    case = hi.config_case(name)
+    case.cfl = cfl
+    plan = hdg.HDGPlan.from_case(case, precision=mode)
+    dev = plan.device
+    w = torch.tensor(case.W, dtype=torch.float64, device=dev)
+    q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
+    lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=dev)
+    dlam = torch.zeros(plan.n_skel, dtype=torch.float64, device=dev)
+    dw = torch.zeros_like(w)
+    dq = torch.zeros_like(q) if q is not None else None
+    ts, its, rrs, sts = [], [], [], []
+    for r in range(warmup + reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.hdg_assemble_condense(w, lam, q=q)
+        it, rr, st = plan.hdg_skeleton_solve(dlam, rtol=rtol, restart=restart, max_iter=max_iter,
+                                             raise_on_fail=False)
+        plan.hdg_back_substitute(dlam, dw, dq)
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= warmup:
+            ts.append(e0.elapsed_time(e1))
+            its.append(it)
+            rrs.append(rr)
+            sts.append(st)
+    ms = float(np.median(ts))
+    ok = all(st == 0 for st in sts)
+    out = {"workload": f"{case.physics} {case.ng}x{case.ng}, degrees {sorted(set(case.degree.tolist()))}"
+                       + (f", pseudo-time CFL {cfl:g}" if cfl > 0 else ", pure Newton"),
+           "precision": mode, "elements": case.n_elements, "skeleton_dofs": plan.n_skel, "ms": ms,
+           "reps": len(ts), "gmres_iters": its[-1], "relres": rrs[-1], "status": sts[-1], "converged": ok}
+    if ok:
+        out["elements_per_s"] = case.n_elements / (ms * 1e-3)
+        out["skeleton_dof_per_s"] = plan.n_skel / (ms * 1e-3)
+    log(f"[bench] full step {name} {mode}{' cfl %g' % cfl if cfl > 0 else ''}: {ms:.1f} ms, {its[-1]} GMRES "
+        f"iterations, relres {rrs[-1]:.2e}, status {sts[-1]}")
+    del plan
+    torch.cuda.synchronize()
+    return out
+
+
 def newton_loop_report(name: str, rtol: float, restart: int, max_steps: int = 12):
     """The relaxed Newton iteration (pseudo-time, CFL schedule with the paper's constants) from
     the workload's perturbed state to a residual reduction of 1e-10, mixed-precision skeleton
@@ -389,9 +438,15 @@ def main():
     ap.add_argument("--poly-fp32", action="store_true",
                     help="mixed mode: the polynomial's products read the float32 matrix, not a float16 copy")
     ap.add_argument("--modes", default="fp64,mixed")
-    ap.add_argument("--serving-requests", type=int, default=24,
+    ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the Poisson serving stream to run (0 = skip; 512 = the full stream)")
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-cfl", type=float, default=10.0,
+                    help="pseudo-time CFL of every serving request (0: pure Newton steps)")
+    ap.add_argument("--serving-newton-requests", type=int, default=128,
+                    help="requests of the same stream also served as pure Newton steps (0 = skip)")
+    ap.add_argument("--full-steps", default="c3:mixed:0,c3:fp64:0,c4:mixed:100,c4:fp64:100,c4:mixed:0",
+                    help="full Newton steps beside the headline: workload:precision:cfl, comma separated")
     ap.add_argument("--serving-max-iter", type=int, default=20000,
                     help="GMRES iterations per serving request before it counts as not converged")
     ap.add_argument("--condense-configs", default="c2,c3,c4",
@@ -508,7 +563,8 @@ def main():
         "dtype": "f64" if main_mode == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": "2-D Euler HDG, uniform p=3, 64x64 jittered unit square (8192 triangles), "
-                               "Mach 0.5, alpha 2 deg, perturbation 1e-2; one Newton step, GMRES(30) to 1e-10",
+                               "Mach 0.5, alpha 2 deg, perturbation 1e-2; one Newton step, block-Jacobi GMRES(30) "
+                               "with a degree-20 GMRES polynomial preconditioner to 1e-10",
                    "elements": ne, "skeleton_dofs": r["n_skel"], "precision": main_mode},
         "modes": {m: {"ms_per_step": v["ms_step"], "ms_per_step_median": v["ms_median"],
                       "ms_per_step_p99": v["ms_p99"], "elements_per_s": ne / (v["ms_step"] / 1e3),
@@ -520,16 +576,23 @@ def main():
     copy_peak = measured_copy_peak()
     log(f"[bench] device copy reaches {copy_peak:.0f} GB/s (published peak {HBM_PEAK_GBS:.0f})")
     achieved = kb / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-    out["roofline"] = {"kernel": "k_spmv_dots (preconditioned skeleton SpMV fused with the first Gram-Schmidt dots)",
-                       "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    kdom = r["k_dominant"]
+    kname = ({"mixed": "k_poly_op<__half>", "fp64": "k_poly_op<double>"}[main_mode] +
+             " (float16 / float64 preconditioned skeleton SpMV of one polynomial-preconditioner factor, its vector "
+             "work fused)") if kdom == 0 else "k_spmv_dots (preconditioned skeleton SpMV fused with the Gram-Schmidt dots)"
+    summary = ("profiles/k_poly_op_c2_euler_p3_mixed_hbm_traffic.txt" if kdom == 0
+               else "profiles/k_spmv_dots_c2_euler_p3_mixed_hbm_traffic.txt")
+    out["roofline"] = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": (measured_traffic("paper_1308_3995_amd/csrc/skeleton.hip",
-                                                    "profiles/k_spmv_dots_c2_euler_p3_mixed_hbm_traffic.txt")
+                       "traffic": (measured_traffic("paper_1308_3995_amd/csrc/skeleton.hip", summary)
                                    if main_mode == "mixed" else None),
                        "traffic_unit": "bytes/launch",
                        "peak_measured_copy": copy_peak, "frac_of_measured": achieved / copy_peak,
                        "launches": kl, "avg_launch_us": kms / max(1, kl) * 1e3,
-                       "bytes_per_launch": kb / max(1, kl)}
+                       "bytes_per_launch": kb / max(1, kl),
+                       "other_kernel": {"name": "k_spmv_dots" if kdom == 0 else "k_poly_op",
+                                        "launches": r["k_all"][1 - kdom][0], "ms": r["k_all"][1 - kdom][1],
+                                        "bytes": r["k_all"][1 - kdom][2]}}
     if args.condense_configs:
         fp64_meas = measured_fp64_peak()
         log(f"[bench] library DGEMM reaches {fp64_meas:.1f} TFLOP/s (published FP64 peak {FP64_PEAK_TFLOPS})")
@@ -539,28 +602,47 @@ def main():
     if args.shock_configs:
         out["condensation_shock_capturing"] = condensation_report(
             [c for c in args.shock_configs.split(",") if c], sc_eps0=0.2)
+    if args.full_steps:
+        out["full_steps"] = {}
+        for spec in [x for x in args.full_steps.split(",") if x]:
+            name, mode, cfl = spec.split(":")
+            cfl = float(cfl)
+            # a pure Newton step that stalls is reported with its status after a bounded solve
+            rep = full_step_report(name, mode, args.rtol, args.restart, cfl=cfl,
+                                   reps=1 if cfl == 0 and name == "c4" else 5,
+                                   warmup=0 if cfl == 0 and name == "c4" else 1,
+                                   max_iter=20000 if cfl == 0 and name == "c4" else 200000)
+            out["full_steps"][f"{name}_{mode}_" + (f"cfl{cfl:g}" if cfl > 0 else "newton")] = rep
     if args.newton_loop:
         out["pseudo_transient"] = newton_loop_report(args.newton_loop, args.rtol, args.restart)
     if args.adjoint:
         out["adjoint"] = adjoint_report(args.adjoint, args.rtol, args.restart)
     if args.serving_requests > 0:
         from paper_1308_3995_amd.serving import ServingEngine, stream_requests
-        log(f"[bench] serving: generating {args.serving_requests} requests")
-        reqs = stream_requests(512, 200.0, rtol=args.rtol)[: args.serving_requests]
-        eng = ServingEngine(max_slots=args.serving_slots, precision="mixed", restart=args.restart,
-                            max_iter=args.serving_max_iter)
-        st = eng.run(reqs, on_result=lambda r: log(f"[bench] serving: request {r.index} done, "
-                                                   f"latency {r.latency_s:.3f} s, {r.elements} elements, "
-                                                   f"{r.gmres_iters} GMRES iterations, status {r.status}"))
-        sm = st.summary()
-        sm["workload"] = (f"first {args.serving_requests} of 512 Poisson requests at 200/s (seed 1313): "
-                          f"2k-64k triangles log-uniform, p in 1..4, Euler or NS, Mach U(0.3,0.9), "
-                          f"alpha U(-3,3) deg; mixed precision, GMRES({args.restart}) to {args.rtol:g} "
-                          f"within {args.serving_max_iter} iterations; {args.serving_slots} slots; "
-                          f"latencies over the completed requests")
-        out["serving"] = sm
-        log(f"[bench] serving: p50 {sm['p50_latency_s']:.3f} s, p99 {sm['p99_latency_s']:.3f} s, "
-            f"{sm['elements_per_s']:.0f} elements/s")
+
+        def serve(n, cfl, key):
+            log(f"[bench] serving ({key}): generating {n} requests")
+            reqs = stream_requests(512, 200.0, rtol=args.rtol, cfl=cfl)[:n]
+            eng = ServingEngine(max_slots=args.serving_slots, precision="mixed", restart=args.restart,
+                                max_iter=args.serving_max_iter)
+            st = eng.run(reqs, on_result=lambda r: log(f"[bench] serving ({key}): request {r.index} done, "
+                                                       f"latency {r.latency_s:.3f} s, {r.elements} elements, "
+                                                       f"{r.gmres_iters} GMRES iterations, status {r.status}"))
+            sm = st.summary()
+            step = (f"relaxed Newton steps (pseudo-time CFL {cfl:g}, Sec. 3.3)" if cfl > 0
+                    else "pure Newton steps")
+            sm["workload"] = (f"first {n} of 512 Poisson requests at 200/s (seed 1313): 2k-64k triangles "
+                              f"log-uniform, p in 1..4, Euler or NS, Mach U(0.3,0.9), alpha U(-3,3) deg; {step}; "
+                              f"mixed precision, GMRES({args.restart}) to {args.rtol:g} within "
+                              f"{args.serving_max_iter} iterations; {args.serving_slots} slots; latencies over "
+                              f"every request (failed ones included), completed-only figures beside them")
+            log(f"[bench] serving ({key}): p50 {sm['p50_latency_s']:.3f} s, p99 {sm['p99_latency_s']:.3f} s, "
+                f"{sm['elements_per_s']:.0f} elements/s, failed {sm['failed_by_status']}")
+            return sm
+
+        out["serving"] = serve(args.serving_requests, args.serving_cfl, "relaxed")
+        if args.serving_newton_requests > 0:
+            out["serving_pure_newton"] = serve(args.serving_newton_requests, 0.0, "pure Newton")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

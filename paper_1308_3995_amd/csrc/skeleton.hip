@@ -50,8 +50,8 @@ SolverLayout solver_layout(const Plan& p, int restart) {
     L.hat16 = carve(p.hat_values * 2);
     L.V = carve(kmv * n * 8);
     L.Z = carve((int64_t)restart * n * 8);
-    L.pvec = carve(3 * n * 8);
-    L.ops = carve((int64_t)restart * 64);
+    L.pvec = carve(8 * n * 8);
+    L.ops = carve(2 * (int64_t)restart * 64);
     L.w = carve(n * 8);
     L.w2 = carve(n * 8);
     L.x = carve(n * 8);
@@ -583,7 +583,8 @@ constexpr int kPolyRowsPerBlock = 4;
 
 template <typename VT>
 __global__ __launch_bounds__(kThreads) void k_poly_op(GmArgs a, const VT* val, const PolyOp* ops, int op,
-                                                      const double* src, const double* base, double* out, double* y) {
+                                                      const double* src, const double* esrc, const double* base,
+                                                      double* out, double* y) {
     constexpr int CH = Vec16<VT>::CH;
     __shared__ double red[4][64 * CH];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -598,18 +599,20 @@ __global__ __launch_bounds__(kThreads) void k_poly_op(GmArgs a, const VT* val, c
     asm volatile("" ::: "memory");
     if (done != 0.0 || f[0] < 0) return;
     sr.issue(val, src);
-    // the entries of this lane's output row: own source value, previous iterate, y
-    double xs = 0.0, bs = 0.0, ys = 0.0;
+    // the entries of this lane's output row: own source value (the identity part of the
+    // product), the factor's own source when it differs (esrc), previous iterate, y
+    double xs = 0.0, es = 0.0, bs = 0.0, ys = 0.0;
     const bool mine = lane < sr.s[0];
     const int64_t e = sr.fo[0] + (mine ? lane : 0);
     xs = src[e];
+    es = esrc ? esrc[e] : xs;
     if (o.b0 != 0.0) bs = base[e];
     if (!o.first) ys = y[e];
     const double t = xs + sr.template finish<0>(val, src, lane, red[wave]);
     if (mine) {
-        const double ov = o.b0 * bs + o.b1 * xs + o.b2 * t;
+        const double ov = o.b0 * bs + o.b1 * es + o.b2 * t;
         if (o.wout) out[e] = ov;
-        y[e] = ys + o.a1 * xs + o.gam * ov;
+        y[e] = ys + o.a1 * es + o.gam * ov;
     }
 }
 
@@ -983,10 +986,12 @@ bool hessenberg_eigenvalues(int n, std::vector<double> H, double* wr, double* wi
 }
 
 struct Poly {
-    int degree = 0;
+    int degree = 0;              // products with Khat per application of Khat p (d; d1 d2 nested)
     std::vector<PolyOp> ops;
     const void* mat = nullptr;   // the matrix its SpMVs read: Khat in float64, float32 or float16
     int mat_bytes = 8;
+    int level = 1;               // 1: a polynomial p1(Khat); 2: p1(Khat) p2(B), B = Khat p1(Khat)
+    const Poly* inner = nullptr; // level 2: p1
 };
 
 // Ops of p(Khat) from the roots (wr, wi) of the residual polynomial. Buffer ids: 0 = v_j,
@@ -1138,9 +1143,58 @@ struct Solver {
     double *minv, *hat, *x, *u, *r;
     float* hat32;
     __half* hat16;
-    double* pbuf[4];  // polynomial vectors: [0] unused (v_j), [1], [2] ping-pong, [3] q
-    PolyOp* ops;
+    // polynomial vectors per level (index 0: the input, set per application): [1], [2] the
+    // running residual-polynomial vector (ping-pong), [3] q of a complex pair; level 2 adds
+    // the inner output z1 and its own output y2
+    double* pbuf[2][4];
+    double* z1;
+    double* y2;
+    PolyOp* ops[2];   // device op lists of the two levels
 };
+
+// out = p(Khat) in (level 1) or p1(Khat) p2(B) in with B = Khat p1(Khat) (level 2), every
+// product one k_poly_op launch with the factor's vector work fused. Level 2: each factor of p2
+// needs B src = Khat (p1(Khat) src): p1 is applied into z1, then one SpMV of z1 carries the
+// p2 factor's vector work on src (esrc); finally p1 is applied to p2's output y2.
+static void apply_poly(Plan& p, const GmArgs& a, const Solver& S, const Poly* poly, const double* in, double* out,
+                       hipStream_t s, std::vector<TimedLaunch>* tl) {
+    const dim3 gp((a.nf + kPolyRowsPerBlock - 1) / kPolyRowsPerBlock), blk(kThreads);
+    const double nval = (double)p.hat_values, n = (double)a.n;
+    const int lv = poly->level - 1;
+    auto buf = [&](int id) -> double* { return id == 0 ? const_cast<double*>(in) : S.pbuf[lv][id]; };
+    auto launch = [&](int k, const double* src, const double* esrc, const double* base, double* o, double* y) {
+        const PolyOp& op = poly->ops[k];
+        if (tl) (void)hipEventRecord(p.t_events[2 * tl->size()], s);
+        if (poly->mat_bytes == 2)
+            hipLaunchKernelGGL((k_poly_op<__half>), gp, blk, 0, s, a, (const __half*)poly->mat, S.ops[lv], k, src,
+                               esrc, base, o, y);
+        else if (poly->mat_bytes == 4)
+            hipLaunchKernelGGL((k_poly_op<float>), gp, blk, 0, s, a, (const float*)poly->mat, S.ops[lv], k, src,
+                               esrc, base, o, y);
+        else
+            hipLaunchKernelGGL((k_poly_op<double>), gp, blk, 0, s, a, (const double*)poly->mat, S.ops[lv], k, src,
+                               esrc, base, o, y);
+        if (tl) {
+            (void)hipEventRecord(p.t_events[2 * tl->size() + 1], s);
+            tl->push_back({0, nval * poly->mat_bytes +
+                                  n * 8.0 * (1.0 + (esrc ? 1.0 : 0.0) + (op.b0 != 0.0 ? 1.0 : 0.0) +
+                                             (op.first ? 1.0 : 2.0) + (op.wout ? 1.0 : 0.0))});
+        }
+    };
+    if (!poly->inner) {
+        for (size_t k = 0; k < poly->ops.size(); ++k) {
+            const PolyOp& o = poly->ops[k];
+            launch((int)k, buf(o.src_id), nullptr, buf(o.base_id), buf(o.out_id), out);
+        }
+        return;
+    }
+    for (size_t k = 0; k < poly->ops.size(); ++k) {
+        const PolyOp& o = poly->ops[k];
+        apply_poly(p, a, S, poly->inner, buf(o.src_id), S.z1, s, tl);
+        launch((int)k, S.z1, buf(o.src_id), buf(o.base_id), buf(o.out_id), S.y2);
+    }
+    apply_poly(p, a, S, poly->inner, S.y2, out, s, tl);
+}
 
 // The Arnoldi kernels are instantiated for every basis size so that their loops over the
 // Krylov vectors are branch-free and all loads issue back to back.
@@ -1169,23 +1223,7 @@ static void launch_step(Plan& p, const GmArgs& a, const Solver& S, const VT* hat
             hipLaunchKernelGGL((k_vnorm<C>), g2, blk, 0, s, a, src);
             double* z = a.Z + (int64_t)j * a.n;
             const double* vj = a.V + (int64_t)j * a.n;
-            for (size_t k = 0; k < poly->ops.size(); ++k) {
-                const PolyOp& o = poly->ops[k];
-                auto buf = [&](int id) -> double* { return id == 0 ? const_cast<double*>(vj) : S.pbuf[id]; };
-                const dim3 gp((a.nf + kPolyRowsPerBlock - 1) / kPolyRowsPerBlock);
-                mark_begin();
-                if (poly->mat_bytes == 2)
-                    hipLaunchKernelGGL((k_poly_op<__half>), gp, blk, 0, s, a, (const __half*)poly->mat, S.ops, (int)k,
-                                       buf(o.src_id), buf(o.base_id), buf(o.out_id), z);
-                else if (poly->mat_bytes == 4)
-                    hipLaunchKernelGGL((k_poly_op<float>), gp, blk, 0, s, a, (const float*)poly->mat, S.ops, (int)k,
-                                       buf(o.src_id), buf(o.base_id), buf(o.out_id), z);
-                else
-                    hipLaunchKernelGGL((k_poly_op<double>), gp, blk, 0, s, a, (const double*)poly->mat, S.ops, (int)k,
-                                       buf(o.src_id), buf(o.base_id), buf(o.out_id), z);
-                mark_end(0, nval * poly->mat_bytes +
-                                n * 8.0 * (1.0 + (o.b0 != 0.0 ? 1.0 : 0.0) + (o.first ? 1.0 : 2.0) + (o.wout ? 1.0 : 0.0)));
-            }
+            apply_poly(p, a, S, poly, vj, z, s, tl);
             mark_begin();
             hipLaunchKernelGGL((k_spmv_dots<VT, C, true>), g1, blk, 0, s, a, hat, z);
             mark_end(1, nval * sizeof(VT) + n * 8.0 * 2.0 + (double)(j + 1) * n * 8.0);
@@ -1211,9 +1249,18 @@ static Solver make_solver(Plan& p, char* ws) {
     S.x = (double*)(base + L.x);
     S.u = (double*)(base + L.y);
     S.r = (double*)(base + L.r);
-    S.pbuf[0] = nullptr;
-    for (int k = 1; k < 4; ++k) S.pbuf[k] = (double*)(base + L.pvec) + (int64_t)(k - 1) * p.face_off.back();
-    S.ops = (PolyOp*)(base + L.ops);
+    {
+        double* pv = (double*)(base + L.pvec);
+        const int64_t nn = p.face_off.back();
+        for (int lv = 0; lv < 2; ++lv) {
+            S.pbuf[lv][0] = nullptr;
+            for (int k = 1; k < 4; ++k) S.pbuf[lv][k] = pv + (int64_t)(lv * 3 + k - 1) * nn;
+        }
+        S.z1 = pv + 6 * nn;
+        S.y2 = pv + 7 * nn;
+        S.ops[0] = (PolyOp*)(base + L.ops);
+        S.ops[1] = S.ops[0] + kMaxPolyOps;
+    }
     GmArgs a{};
     a.nf = p.nf;
     a.n = p.face_off.back();
@@ -1262,11 +1309,23 @@ static hdg_status true_residual(const Plan& p, Solver& S, const double* bsr, con
 // flexible update), accumulating into u, until ||r0 - Khat u|| <= abs_tol (recursive estimate)
 // or max_iter operator applications (a polynomial step counts its degree). One host
 // synchronisation per cycle.
+// SpMV launches of one application of the polynomial (the Arnoldi step adds one more).
+static int poly_launches(const Poly* poly) {
+    if (!poly) return 0;
+    if (!poly->inner) return (int)poly->ops.size();
+    const int in = poly_launches(poly->inner);
+    return (int)poly->ops.size() * (in + 1) + in;
+}
+
+// With `stalled` non-null the solve also returns after a full cycle that reduced the residual
+// by less than a factor two (*stalled = true; the cycle's Hessenberg matrix is left in place).
 template <typename VT>
 static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0, int m, int max_iter,
-                             double abs_tol, const Poly* poly, hipStream_t s, int* iters, double* est) {
+                             double abs_tol, const Poly* poly, hipStream_t s, int* iters, double* est,
+                             bool* stalled = nullptr) {
     const int deg = poly ? poly->degree : 1;
-    const int per_cycle_events = 2 * m * (poly ? (int)poly->ops.size() + 1 : 1);
+    if (stalled) *stalled = false;
+    const int per_cycle_events = 2 * m * (poly_launches(poly) + 1);
     if (p.timing && (int)p.t_events.size() < per_cycle_events) {
         p.t_events.resize(per_cycle_events, nullptr);
         for (auto& e : p.t_events)
@@ -1302,10 +1361,10 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
             mix((uint64_t)(uintptr_t)a.V);
             mix((uint64_t)(uintptr_t)a.scal);
             mix((uint64_t)m);
-            if (poly) {
-                mix((uint64_t)(uintptr_t)poly->mat);
-                mix((uint64_t)poly->ops.size());
-                for (const PolyOp& o : poly->ops)
+            for (const Poly* q = poly; q; q = q->inner) {
+                mix((uint64_t)(uintptr_t)q->mat);
+                mix((uint64_t)(q->ops.size() | (size_t)q->level << 8));
+                for (const PolyOp& o : q->ops)
                     mix((uint64_t)(o.src_id | o.base_id << 4 | o.out_id << 8 | o.wout << 12 | o.first << 13));
             }
             mix((uint64_t)gi);
@@ -1331,7 +1390,7 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
         res = sc[SC_RES];
         if (p.timing) {
             // launches that did work: those of steps 0..jd-1 (later ones saw the converged flag)
-            const size_t per_step = poly ? poly->ops.size() + 1 : 1;
+            const size_t per_step = (size_t)poly_launches(poly) + 1;
             const size_t worked = std::min(tl.size(), (size_t)std::min(steps, jd) * per_step);
             for (size_t k = 0; k < worked; ++k) {
                 float ms = 0.f;
@@ -1343,9 +1402,33 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
             }
         }
         if (jd == 0 || res <= abs_tol || jd < steps) break;
+        if (stalled && steps == m && res > 0.5 * sc[SC_BETA]) {
+            *stalled = true;
+            break;
+        }
     }
     *iters = total;
     *est = res;
+    return HDG_OK;
+}
+
+// The second level of the polynomial preconditioner from the Hessenberg matrix of a stalled
+// cycle of GMRES on B = Khat p1(Khat) (m steps): its harmonic Ritz values are the roots of a
+// residual polynomial in B of degree m.
+static hdg_status build_level2(Plan& p, Solver& S, int m, const Poly& inner, Poly& outer, bool& ok, hipStream_t s) {
+    ok = false;
+    std::vector<double> Hc((size_t)m * kMaxV);
+    HIPCHK(hipMemcpyAsync(Hc.data(), S.ga.H, Hc.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!poly_from_hessenberg(Hc, m, outer)) return HDG_OK;
+    outer.level = 2;
+    outer.inner = &inner;
+    outer.mat = inner.mat;
+    outer.mat_bytes = inner.mat_bytes;
+    outer.degree = m * inner.degree;
+    HIPCHK(hipMemcpyAsync(S.ops[1], outer.ops.data(), outer.ops.size() * sizeof(PolyOp), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ok = true;
     return HDG_OK;
 }
 
@@ -1366,9 +1449,60 @@ static hdg_status build_poly(Plan& p, Solver& S, const VT* hat, const double* r0
     HIPCHK(hipMemcpyAsync(Hc.data(), S.ga.H, Hc.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (!poly_from_hessenberg(Hc, d, poly)) return HDG_OK;
-    HIPCHK(hipMemcpyAsync(S.ops, poly.ops.data(), poly.ops.size() * sizeof(PolyOp), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(S.ops[0], poly.ops.data(), poly.ops.size() * sizeof(PolyOp), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     ok = true;
+    return HDG_OK;
+}
+
+// The polynomial preconditioner of one skeleton solve: the first level from the solve's first
+// cycle, the second built once if a later cycle stalls.
+struct PolyState {
+    Poly p1, p2;
+    bool tried1 = false, have1 = false, tried2 = false, have2 = false;
+    const void* mat = nullptr;   // matrix of the polynomial's products
+    int mat_bytes = 8;
+};
+
+// GMRES on Khat u = r0 (u accumulating) until the recursive residual estimate meets tol or
+// `budget` operator applications: the first call builds the first polynomial level from a plain
+// cycle of pdeg steps; a cycle that reduces the residual by less than half brings in the second
+// level (restart cycles of at most 10 steps, each step about pdeg * restart products).
+template <typename VT>
+static hdg_status inner_solve(Plan& p, Solver& S, const VT* hat, const double* r0, int restart, int budget,
+                              double tol, int pdeg, PolyState& ps, hipStream_t s, int* it_out, double* est_out) {
+    int it = 0;
+    double est = HUGE_VAL;
+    if (!ps.tried1 && pdeg >= 2) {
+        ps.tried1 = true;
+        int it1 = 0;
+        hdg_status st = build_poly<VT>(p, S, hat, r0, pdeg, budget, tol, s, ps.p1, ps.have1, &it1, &est);
+        if (st != HDG_OK) return st;
+        ps.p1.mat = ps.mat;
+        ps.p1.mat_bytes = ps.mat_bytes;
+        it += it1;
+        if (it1 > 0 && est <= tol) {
+            *it_out = it;
+            *est_out = est;
+            return HDG_OK;
+        }
+    }
+    while (it < budget) {
+        const Poly* active = ps.have2 ? &ps.p2 : ps.have1 ? &ps.p1 : nullptr;
+        const int m = ps.have2 ? std::min(restart, 10) : restart;
+        bool stalled = false;
+        int it2 = 0;
+        hdg_status st = gmres_khat<VT>(p, S, hat, r0, m, budget - it, tol, active, s, &it2, &est,
+                                       ps.have1 && !ps.tried2 ? &stalled : nullptr);
+        if (st != HDG_OK) return st;
+        it += it2;
+        if (!stalled) break;
+        ps.tried2 = true;
+        st = build_level2(p, S, m, ps.p1, ps.p2, ps.have2, s);
+        if (st != HDG_OK) return st;
+    }
+    *it_out = it;
+    *est_out = est;
     return HDG_OK;
 }
 
@@ -1420,88 +1554,50 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
     const double tol = rtol * enorm;
     int total = 0;
     double relres = 1.0;
-    Poly poly;
-    bool have_poly = false, tried_poly = pdeg < 2;
-    if (!mixed) {
-        // GMRES on Khat u = E, dLambda = M^-1 u; continue until the true residual meets tol
+    PolyState ps;
+    // Iterative refinement on the float64 K: r = E - K dLambda, GMRES on Khat u = r, dLambda += M^-1 u.
+    // HDG_FP64 solves the correction on the float64 Khat to the final tolerance (one outer step
+    // unless the recursive estimate drifted from the true residual); HDG_MIXED on the float32 Khat
+    // to 1e-6 of r, and when an outer step fails to halve the float64 residual (kappa(Khat) u_32
+    // too close to 1 for refinement to contract) the rest of the solve runs on the float64 Khat.
+    // The polynomial is a preconditioner: in the mixed mode its products may read a float16 copy.
+    // A correction that came out non-finite is dropped and the solve goes on without the polynomial.
+    ps.mat = mixed ? (p.poly_half ? (const void*)S.hat16 : (const void*)S.hat32) : (const void*)S.hat;
+    ps.mat_bytes = mixed ? (p.poly_half ? 2 : 4) : 8;
+    double prev = HUGE_VAL;
+    bool fp64_inner = !mixed;
+    for (int outer = 0; outer < 200 && total < max_iter; ++outer) {
+        double tr = 0.0;
+        st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
+        if (st != HDG_OK) return st;
+        relres = tr / enorm;
+        if (tr <= tol) break;
+        if (tr > 0.5 * prev) fp64_inner = true;
+        prev = tr;
+        HIPCHK(hipMemcpyAsync(S.x, S.r, n * 8, hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, S.u, 0.0);
-        for (int outer = 0; outer < 50 && total < max_iter; ++outer) {
-            int it = 0;
-            double est = 0.0;
-            if (!tried_poly) {
-                tried_poly = true;
-                st = build_poly<double>(p, S, S.hat, rhs, pdeg, max_iter - total, tol, s, poly, have_poly, &it, &est);
-                if (st != HDG_OK) return st;
-                total += it;
-                poly.mat = S.hat;
-                poly.mat_bytes = 8;
-            }
-            if (total < max_iter && !(est <= tol && it > 0)) {
-                int it2 = 0;
-                st = gmres_khat<double>(p, S, S.hat, rhs, restart, max_iter - total, tol, have_poly ? &poly : nullptr,
-                                        s, &it2, &est);
-                if (st != HDG_OK) return st;
-                total += it2;
-                it += it2;
-            }
-            hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv,
-                               S.u, dlam, 0);
-            double tr = 0.0;
-            st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
-            if (st != HDG_OK) return st;
-            relres = tr / enorm;
-            if (tr <= tol || it == 0) break;
+        int it = 0;
+        double est = 0.0;
+        // the float32 matrix bounds what one refinement step can gain; ask for 1e-6
+        const double inner_tol = fp64_inner ? tol : std::max(tol, 1e-6 * tr);
+        if (fp64_inner)
+            st = inner_solve<double>(p, S, S.hat, S.x, restart, max_iter - total, inner_tol, pdeg, ps, s, &it, &est);
+        else
+            st = inner_solve<float>(p, S, S.hat32, S.x, restart, max_iter - total, inner_tol, pdeg, ps, s, &it,
+                                    &est);
+        if (st != HDG_OK) return st;
+        total += it;
+        if (!std::isfinite(est)) {
+            if (!ps.have1 && !ps.have2) break;     // no polynomial to drop: reported below
+            ps.have1 = ps.have2 = false;
+            ps.tried1 = ps.tried2 = true;
+            continue;
         }
-    } else {
-        // iterative refinement: r = E - K x in float64, inner GMRES on the float32 Khat. When an
-        // outer step fails to halve the float64 residual (kappa(Khat) u_32 too close to 1 for
-        // refinement to contract), the rest of the solve runs on the float64 Khat.
-        double prev = HUGE_VAL;
-        bool fp64_inner = false;
-        for (int outer = 0; outer < 200 && total < max_iter; ++outer) {
-            double tr = 0.0;
-            st = true_residual(p, S, bsr, rhs, dlam, s, &tr);
-            if (st != HDG_OK) return st;
-            relres = tr / enorm;
-            if (tr <= tol) break;
-            if (tr > 0.5 * prev) fp64_inner = true;
-            prev = tr;
-            HIPCHK(hipMemcpyAsync(S.x, S.r, n * 8, hipMemcpyDeviceToDevice, s));
-            hipLaunchKernelGGL(k_fill, dim3(vblocks), dim3(256), 0, s, n, S.u, 0.0);
-            int it = 0;
-            double est = 0.0;
-            // the float32 matrix bounds what one refinement step can gain; ask for 1e-6
-            const double inner_tol = fp64_inner ? tol : std::max(tol, 1e-6 * tr);
-            if (!tried_poly) {
-                tried_poly = true;
-                if (fp64_inner)
-                    st = build_poly<double>(p, S, S.hat, S.x, pdeg, max_iter - total, inner_tol, s, poly, have_poly,
-                                            &it, &est);
-                else
-                    st = build_poly<float>(p, S, S.hat32, S.x, pdeg, max_iter - total, inner_tol, s, poly, have_poly,
-                                           &it, &est);
-                if (st != HDG_OK) return st;
-                total += it;
-                // the polynomial is a preconditioner: its products may read a float16 copy of Khat
-                poly.mat = p.poly_half ? (const void*)S.hat16 : (const void*)S.hat32;
-                poly.mat_bytes = p.poly_half ? 2 : 4;
-            }
-            if (total < max_iter && !(est <= inner_tol && it > 0)) {
-                int it2 = 0;
-                if (fp64_inner)
-                    st = gmres_khat<double>(p, S, S.hat, S.x, restart, max_iter - total, inner_tol,
-                                            have_poly ? &poly : nullptr, s, &it2, &est);
-                else
-                    st = gmres_khat<float>(p, S, S.hat32, S.x, restart, max_iter - total, inner_tol,
-                                           have_poly ? &poly : nullptr, s, &it2, &est);
-                if (st != HDG_OK) return st;
-                total += it2;
-                it += it2;
-            }
-            hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv,
-                               S.u, dlam, 1);
-            if (it == 0) break;
-        }
+        hipLaunchKernelGGL(k_bj_apply, dim3(p.nf), dim3(64), 0, s, p.nf, p.d_face_off, p.d_diag_off, S.minv, S.u,
+                           dlam, 1);
+        if (it == 0) break;
+    }
+    {
         if (!(relres <= rtol)) {
             double tr = 0.0;
             st = true_residual(p, S, bsr, rhs, dlam, s, &tr);

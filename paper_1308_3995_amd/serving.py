@@ -1,9 +1,10 @@
 """Continuous-batching request loop for Newton-step solves of independent HDG cases.
 
-Requests arrive on their own clock (seconds after the start of `run`). A request is
-admitted as soon as it has arrived, a slot is free and its device footprint (skeleton
-matrix, local store, workspace and state, from hdg_plan_sizes) fits in the HBM budget
-next to the cases already on the device. Each admitted case keeps its plan, state and
+Requests arrive on their own clock (seconds after the start of `run`). Preparation threads
+build each arrived request's plan (host tables and device constants) off the admission path.
+A request is admitted, in arrival order, as soon as its plan is ready, a slot is free and its
+device footprint (skeleton matrix, local store, workspace and state, from hdg_plan_sizes)
+fits in the HBM budget next to the cases already on the device. Each admitted case keeps its plan, state and
 matrices resident and runs one full Newton step (hdg_assemble_condense,
 hdg_skeleton_solve, hdg_back_substitute) on its own HIP stream from its own host thread,
 so the kernels of concurrent cases overlap on the GPU. When a case finishes, its slot and
@@ -91,7 +92,8 @@ class ServeStats:
 
 class ServingEngine:
     def __init__(self, max_slots: int = 8, hbm_budget_bytes: Optional[int] = None, precision: str = "mixed",
-                 restart: int = 30, max_iter: int = 20000, keep_results: bool = False, device: int = 0):
+                 restart: int = 30, max_iter: int = 20000, keep_results: bool = False, device: int = 0,
+                 prep_threads: int = 2, poly_degree: Optional[int] = None):
         import torch
         self.max_slots = max_slots
         if hbm_budget_bytes is None:
@@ -103,6 +105,8 @@ class ServingEngine:
         self.max_iter = max_iter   # GMRES iterations per request before it is reported NOT_CONVERGED
         self.keep = keep_results
         self.device = device
+        self.prep_threads = prep_threads   # host threads building plans ahead of admission
+        self.poly_degree = poly_degree     # None: the library's default polynomial preconditioner
         self._lock = threading.Lock()
         self._cv = threading.Condition(self._lock)
         self._in_use = 0
@@ -176,16 +180,38 @@ class ServingEngine:
             if on_result:
                 on_result(res)
 
-        with ThreadPoolExecutor(max_workers=self.max_slots) as pool:
+        def prepare(req):
+            # host-side plan (mesh tables, buckets, device constants) and its footprint, built on
+            # a preparation thread once the request has arrived
+            now = time.perf_counter() - t0
+            if req.arrival_s > now:
+                time.sleep(req.arrival_s - now)
+            plan = HDGPlan.from_case(req.case, precision=self.precision, device=self.device, allocate=False)
+            if self.poly_degree is not None:
+                plan.hdg_set_poly_degree(self.poly_degree)
+            return plan, self.footprint(plan.sizes, plan.npmax, plan.ne, plan.physics == "ns")
+
+        with ThreadPoolExecutor(max_workers=self.max_slots) as pool, \
+                ThreadPoolExecutor(max_workers=self.prep_threads) as prep:
+            prepared = [prep.submit(prepare, r) for r in pending]
             i = 0
             while i < len(pending):
                 req = pending[i]
-                now = time.perf_counter() - t0
-                if req.arrival_s > now:
-                    time.sleep(min(req.arrival_s - now, 0.01))
+                try:
+                    plan, fp = prepared[i].result()
+                except Exception as exc:     # the plan could not be built: the request fails alone
+                    from . import _lib
+                    status = exc.status if isinstance(exc, _lib.HdgError) else STATUS_HOST_FAILURE
+                    now = time.perf_counter() - t0
+                    res = ServeResult(req.index, req.arrival_s, now, now, 0, 0, 0, float("nan"), status, 0)
+                    with self._cv:
+                        stats.results.append(res)
+                    if on_result:
+                        on_result(res)
+                    prepared[i] = None
+                    i += 1
                     continue
-                plan = HDGPlan.from_case(req.case, precision=self.precision, device=self.device, allocate=False)
-                fp = self.footprint(plan.sizes, plan.npmax, plan.ne, plan.physics == "ns")
+                prepared[i] = None
                 with self._cv:
                     while self._active >= self.max_slots or (self._active > 0 and self._in_use + fp > self.budget):
                         self._cv.wait(timeout=0.05)
@@ -217,11 +243,14 @@ class ServingEngine:
 
 
 def stream_requests(n_requests: int, rate_per_s: float, seed: int = 1313, ne_range=(2000, 64000),
-                    degrees=(1, 2, 3, 4), rtol: float = 1e-10) -> List[ServeRequest]:
+                    degrees=(1, 2, 3, 4), rtol: float = 1e-10, cfl: float = 0.0) -> List[ServeRequest]:
     """The serving workload: Poisson arrivals, log-uniform mesh sizes, Euler or NS with
-    probability 1/2, p uniform in `degrees`, Mach ~ U(0.3, 0.9), alpha ~ U(-3, 3) deg."""
+    probability 1/2, p uniform in `degrees`, Mach ~ U(0.3, 0.9), alpha ~ U(-3, 3) deg. cfl > 0
+    makes every request a relaxed Newton step (the pseudo-time term of Sec. 3.3 at that CFL)."""
     import hdg_inputs as hi
     out = []
     for r in hi.serving_stream(n_requests, rate_per_s, seed, ne_range, degrees):
-        out.append(ServeRequest(r.index, r.arrival_s, r.case(), rtol))
+        c = r.case()
+        c.cfl = cfl
+        out.append(ServeRequest(r.index, r.arrival_s, c, rtol))
     return out
