@@ -860,6 +860,18 @@ __global__ void k_fill(int64_t n, double* x, double v) {
     if (k < n) x[k] = v;
 }
 
+// x_k uniform in [-1, 1) from a counter-based hash of (seed, k) (the splitmix64 finaliser):
+// the start vector of the Arnoldi process that builds the polynomial preconditioner.
+__global__ void k_rand_vec(int64_t n, double* x, uint64_t seed) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint64_t z = seed + 0x9e3779b97f4a7c15ull * (uint64_t)(k + 1);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    x[k] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
 // Clears the solver's scalars except the tolerance (set by k_set_tol before each cycle, so a
 // captured cycle serves every tolerance).
 __global__ void k_set_scalars(double* scal) {
@@ -1149,6 +1161,7 @@ struct Solver {
     double* pbuf[2][4];
     double* z1;
     double* y2;
+    double* w0;
     PolyOp* ops[2];   // device op lists of the two levels
 };
 
@@ -1258,6 +1271,7 @@ static Solver make_solver(Plan& p, char* ws) {
         }
         S.z1 = pv + 6 * nn;
         S.y2 = pv + 7 * nn;
+        S.w0 = S.y2;   // the polynomial's start vector (before any level-2 application)
         S.ops[0] = (PolyOp*)(base + L.ops);
         S.ops[1] = S.ops[0] + kMaxPolyOps;
     }
@@ -1322,7 +1336,7 @@ static int poly_launches(const Poly* poly) {
 template <typename VT>
 static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0, int m, int max_iter,
                              double abs_tol, const Poly* poly, hipStream_t s, int* iters, double* est,
-                             bool* stalled = nullptr) {
+                             bool* stalled = nullptr, double* stall_ratio = nullptr) {
     const int deg = poly ? poly->degree : 1;
     if (stalled) *stalled = false;
     const int per_cycle_events = 2 * m * (poly_launches(poly) + 1);
@@ -1404,6 +1418,7 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
         if (jd == 0 || res <= abs_tol || jd < steps) break;
         if (stalled && steps == m && res > 0.5 * sc[SC_BETA]) {
             *stalled = true;
+            if (stall_ratio) *stall_ratio = res / sc[SC_BETA];
             break;
         }
     }
@@ -1473,30 +1488,41 @@ static hdg_status inner_solve(Plan& p, Solver& S, const VT* hat, const double* r
                               double tol, int pdeg, PolyState& ps, hipStream_t s, int* it_out, double* est_out) {
     int it = 0;
     double est = HUGE_VAL;
-    if (!ps.tried1 && pdeg >= 2) {
+    if (!ps.tried1 && pdeg >= 2 && budget > pdeg) {
+        // the first level comes from d Arnoldi steps on a fixed pseudo-random vector (its roots then
+        // reflect the spectrum, not one right-hand side); that cycle's correction is discarded
         ps.tried1 = true;
+        const int64_t n = S.ga.n;
+        const unsigned vb = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_rand_vec, dim3(vb), dim3(256), 0, s, n, S.w0, 0x48444731ull);
         int it1 = 0;
-        hdg_status st = build_poly<VT>(p, S, hat, r0, pdeg, budget, tol, s, ps.p1, ps.have1, &it1, &est);
+        double e1 = 0.0;
+        hdg_status st = build_poly<VT>(p, S, hat, S.w0, pdeg, pdeg, 0.0, s, ps.p1, ps.have1, &it1, &e1);
         if (st != HDG_OK) return st;
+        hipLaunchKernelGGL(k_fill, dim3(vb), dim3(256), 0, s, n, S.u, 0.0);
         ps.p1.mat = ps.mat;
         ps.p1.mat_bytes = ps.mat_bytes;
         it += it1;
-        if (it1 > 0 && est <= tol) {
-            *it_out = it;
-            *est_out = est;
-            return HDG_OK;
-        }
     }
+    bool first_poly_cycle = true;
     while (it < budget) {
         const Poly* active = ps.have2 ? &ps.p2 : ps.have1 ? &ps.p1 : nullptr;
         const int m = ps.have2 ? std::min(restart, 10) : restart;
         bool stalled = false;
         int it2 = 0;
+        double ratio = 0.0;
         hdg_status st = gmres_khat<VT>(p, S, hat, r0, m, budget - it, tol, active, s, &it2, &est,
-                                       ps.have1 && !ps.tried2 ? &stalled : nullptr);
+                                       ps.have1 && !ps.tried2 ? &stalled : nullptr, &ratio);
         if (st != HDG_OK) return st;
         it += it2;
         if (!stalled) break;
+        if (first_poly_cycle && !ps.have2 && ratio > 0.95) {
+            // no progress at all in the first polynomial cycle: the polynomial is unusable here
+            ps.have1 = false;
+            ps.tried2 = true;
+            continue;
+        }
+        first_poly_cycle = false;
         ps.tried2 = true;
         st = build_level2(p, S, m, ps.p1, ps.p2, ps.have2, s);
         if (st != HDG_OK) return st;
