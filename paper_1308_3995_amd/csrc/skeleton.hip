@@ -1146,7 +1146,8 @@ static bool poly_from_hessenberg(const std::vector<double>& Hc, int d, Poly& P) 
 // Kernel-time accounting of the benchmarks: launch pairs of events per cycle, per kernel class.
 struct TimedLaunch {
     int cls;          // 0: k_poly_op, 1: k_spmv_dots
-    double bytes;
+    double bytes;     // algorithmic bytes of the launches between the event pair
+    int count;        // launches between the event pair
 };
 
 struct Solver {
@@ -1170,14 +1171,13 @@ struct Solver {
 // needs B src = Khat (p1(Khat) src): p1 is applied into z1, then one SpMV of z1 carries the
 // p2 factor's vector work on src (esrc); finally p1 is applied to p2's output y2.
 static void apply_poly(Plan& p, const GmArgs& a, const Solver& S, const Poly* poly, const double* in, double* out,
-                       hipStream_t s, std::vector<TimedLaunch>* tl) {
+                       hipStream_t s, TimedLaunch* tl) {
     const dim3 gp((a.nf + kPolyRowsPerBlock - 1) / kPolyRowsPerBlock), blk(kThreads);
     const double nval = (double)p.hat_values, n = (double)a.n;
     const int lv = poly->level - 1;
     auto buf = [&](int id) -> double* { return id == 0 ? const_cast<double*>(in) : S.pbuf[lv][id]; };
     auto launch = [&](int k, const double* src, const double* esrc, const double* base, double* o, double* y) {
         const PolyOp& op = poly->ops[k];
-        if (tl) (void)hipEventRecord(p.t_events[2 * tl->size()], s);
         if (poly->mat_bytes == 2)
             hipLaunchKernelGGL((k_poly_op<__half>), gp, blk, 0, s, a, (const __half*)poly->mat, S.ops[lv], k, src,
                                esrc, base, o, y);
@@ -1188,10 +1188,10 @@ static void apply_poly(Plan& p, const GmArgs& a, const Solver& S, const Poly* po
             hipLaunchKernelGGL((k_poly_op<double>), gp, blk, 0, s, a, (const double*)poly->mat, S.ops[lv], k, src,
                                esrc, base, o, y);
         if (tl) {
-            (void)hipEventRecord(p.t_events[2 * tl->size() + 1], s);
-            tl->push_back({0, nval * poly->mat_bytes +
-                                  n * 8.0 * (1.0 + (esrc ? 1.0 : 0.0) + (op.b0 != 0.0 ? 1.0 : 0.0) +
-                                             (op.first ? 1.0 : 2.0) + (op.wout ? 1.0 : 0.0))});
+            tl->bytes += nval * poly->mat_bytes +
+                         n * 8.0 * (1.0 + (esrc ? 1.0 : 0.0) + (op.b0 != 0.0 ? 1.0 : 0.0) + (op.first ? 1.0 : 2.0) +
+                                    (op.wout ? 1.0 : 0.0));
+            tl->count += 1;
         }
     };
     if (!poly->inner) {
@@ -1229,14 +1229,23 @@ static void launch_step(Plan& p, const GmArgs& a, const Solver& S, const VT* hat
         auto mark_end = [&](int cls, double bytes) {
             if (tl) {
                 (void)hipEventRecord(ev(2 * (int)tl->size() + 1), s);
-                tl->push_back({cls, bytes});
+                tl->push_back({cls, bytes, 1});
             }
         };
         if (poly) {
             hipLaunchKernelGGL((k_vnorm<C>), g2, blk, 0, s, a, src);
             double* z = a.Z + (int64_t)j * a.n;
             const double* vj = a.V + (int64_t)j * a.n;
-            apply_poly(p, a, S, poly, vj, z, s, tl);
+            // the polynomial's launches run back to back: one event pair around all of them
+            if (tl) {
+                TimedLaunch run{0, 0.0, 0};
+                (void)hipEventRecord(ev(2 * (int)tl->size()), s);
+                apply_poly(p, a, S, poly, vj, z, s, &run);
+                (void)hipEventRecord(ev(2 * (int)tl->size() + 1), s);
+                tl->push_back(run);
+            } else {
+                apply_poly(p, a, S, poly, vj, z, s, nullptr);
+            }
             mark_begin();
             hipLaunchKernelGGL((k_spmv_dots<VT, C, true>), g1, blk, 0, s, a, hat, z);
             mark_end(1, nval * sizeof(VT) + n * 8.0 * 2.0 + (double)(j + 1) * n * 8.0);
@@ -1339,7 +1348,7 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
                              bool* stalled = nullptr, double* stall_ratio = nullptr) {
     const int deg = poly ? poly->degree : 1;
     if (stalled) *stalled = false;
-    const int per_cycle_events = 2 * m * (poly_launches(poly) + 1);
+    const int per_cycle_events = 2 * m * 2;
     if (p.timing && (int)p.t_events.size() < per_cycle_events) {
         p.t_events.resize(per_cycle_events, nullptr);
         for (auto& e : p.t_events)
@@ -1404,14 +1413,14 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
         res = sc[SC_RES];
         if (p.timing) {
             // launches that did work: those of steps 0..jd-1 (later ones saw the converged flag)
-            const size_t per_step = (size_t)poly_launches(poly) + 1;
+            const size_t per_step = poly ? 2 : 1;
             const size_t worked = std::min(tl.size(), (size_t)std::min(steps, jd) * per_step);
             for (size_t k = 0; k < worked; ++k) {
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, p.t_events[2 * k], p.t_events[2 * k + 1]));
                 const int c = tl[k].cls;
                 p.t_ms[c] += ms;
-                p.t_launches[c] += 1;
+                p.t_launches[c] += tl[k].count;
                 p.t_bytes[c] += tl[k].bytes;
             }
         }
