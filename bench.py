@@ -234,8 +234,9 @@ def measured_fp64_peak(n: int = 8192, reps: int = 3) -> float:
 
 
 def condensation_report(names, warmup: int = 5, reps: int = 30, sc_eps0: float = 0.0,
-                        fp64_measured: float = 0.0, hbm_measured: float = 0.0):
-    """Assemble + condense time of each named workload (float64 path), with its roofline:
+                        fp64_measured: float = 0.0, hbm_measured: float = 0.0, precision: str = "fp64"):
+    """Assemble + condense time of each named workload (float64 path, or the mixed-precision
+    condensation with precision="mixed_condense"), with its roofline:
     `warmup` untimed calls, then the median and p99 of `reps` individually timed calls.
     sc_eps0 > 0 switches shock capturing on (Euler workloads; its extra work is not counted
     in the roofline's algorithmic figures)."""
@@ -246,7 +247,13 @@ def condensation_report(names, warmup: int = 5, reps: int = 30, sc_eps0: float =
     for name in names:
         case = hi.config_case(name)
         case.sc_eps0 = sc_eps0
-        plan = hdg.HDGPlan.from_case(case, precision="fp64")
+        try:
+            plan = hdg.HDGPlan.from_case(case, precision=precision)
+        except hdg.HdgError as exc:
+            out[name] = {"workload": f"{case.physics} {case.ng}x{case.ng}", "precision": precision,
+                         "not_built": str(exc)}
+            log(f"[bench] condensation {name} ({precision}): {exc}")
+            continue
         dev = plan.device
         w = torch.tensor(case.W, dtype=torch.float64, device=dev)
         q = torch.tensor(case.Q, dtype=torch.float64, device=dev) if case.Q is not None else None
@@ -268,7 +275,7 @@ def condensation_report(names, warmup: int = 5, reps: int = 30, sc_eps0: float =
         t_f = fl / (FP64_PEAK_TFLOPS * 1e12)
         t_b = by / (HBM_PEAK_GBS * 1e9)
         out[name] = {"workload": f"{case.physics} {case.ng}x{case.ng}, degrees {sorted(set(case.degree.tolist()))}",
-                     "elements": case.n_elements, "ms": ms, "ms_p99": p99, "reps": reps,
+                     "precision": precision, "elements": case.n_elements, "ms": ms, "ms_p99": p99, "reps": reps,
                      "elements_per_s": case.n_elements / (ms * 1e-3),
                      "algorithmic_gflop": fl / 1e9, "algorithmic_gb": by / 1e9,
                      "achieved_tflops": fl / (ms * 1e-3) / 1e12, "achieved_gbs": by / (ms * 1e-3) / 1e9,
@@ -280,7 +287,7 @@ def condensation_report(names, warmup: int = 5, reps: int = 30, sc_eps0: float =
         tag = f" with shock capturing (eps_0 {sc_eps0:g})" if sc_eps0 > 0 else ""
         if sc_eps0 > 0:
             out[name]["shock_capturing_eps0"] = sc_eps0
-        log(f"[bench] condensation {name}{tag}: {ms:.3f} ms, {case.n_elements / ms / 1e3:.2f} M elements/s, "
+        log(f"[bench] condensation {name}{tag} ({precision}): {ms:.3f} ms, {case.n_elements / ms / 1e3:.2f} M elements/s, "
             f"roofline {out[name]['roofline_frac']:.3f} ({out[name]['bound']})")
         del plan
         torch.cuda.synchronize()
@@ -445,7 +452,8 @@ def main():
                     help="pseudo-time CFL of every serving request (0: pure Newton steps)")
     ap.add_argument("--serving-newton-requests", type=int, default=128,
                     help="requests of the same stream also served as pure Newton steps (0 = skip)")
-    ap.add_argument("--full-steps", default="c3:mixed:0,c3:fp64:0,c4:mixed:100,c4:fp64:100,c4:mixed:0",
+    ap.add_argument("--full-steps", default="c2:mixed_condense:0,c3:mixed:0,c3:fp64:0,c3:mixed_condense:0,"
+                                            "c4:mixed:100,c4:fp64:100,c4:mixed:0",
                     help="full Newton steps beside the headline: workload:precision:cfl, comma separated")
     ap.add_argument("--serving-max-iter", type=int, default=20000,
                     help="GMRES iterations per serving request before it counts as not converged")
@@ -599,6 +607,12 @@ def main():
         out["measured_peaks"] = {"hbm_copy_gbs": copy_peak, "fp64_dgemm_tflops": fp64_meas}
         out["condensation"] = condensation_report([c for c in args.condense_configs.split(",") if c],
                                                   fp64_measured=fp64_meas, hbm_measured=copy_peak)
+        out["condensation_mixed"] = condensation_report([c for c in args.condense_configs.split(",") if c],
+                                                        fp64_measured=fp64_meas, hbm_measured=copy_peak,
+                                                        precision="mixed_condense")
+        for k, v in out["condensation_mixed"].items():
+            if "ms" in v and k in out["condensation"]:
+                v["speedup_over_fp64"] = out["condensation"][k]["ms"] / v["ms"]
     if args.shock_configs:
         out["condensation_shock_capturing"] = condensation_report(
             [c for c in args.shock_configs.split(",") if c], sc_eps0=0.2)

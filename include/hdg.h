@@ -67,8 +67,15 @@ typedef enum { HDG_EULER = 0, HDG_NS = 1 } hdg_physics;
  * HDG_MIXED: the skeleton solve runs its inner GMRES on a float32 copy of the
  *            preconditioned skeleton matrix, wrapped in float64 iterative
  *            refinement on the float64 skeleton matrix (residuals, Krylov
- *            vectors and orthogonalisation stay float64). */
-typedef enum { HDG_FP64 = 0, HDG_MIXED = 1 } hdg_precision;
+ *            vectors and orthogonalisation stay float64); the condensation is float64.
+ * HDG_MIXED_CONDENSE: as HDG_MIXED, and the condensation of Euler elements of degree <= 4
+ *            eliminates [A_K | B_K | r_K] in float32 (the blocks are assembled in float64),
+ *            refines y_K in float64 (the float64 residual r_K - A_K y_K through the recorded
+ *            float32 elimination, two sweeps) and forms g_K from it; X_K and S_K keep
+ *            float32 accuracy, so the skeleton matrix is that of the float32 local solves.
+ *            Navier-Stokes plans refuse it (HDG_ERR_INVALID_ARG); degree-5 elements are
+ *            condensed in float64. */
+typedef enum { HDG_FP64 = 0, HDG_MIXED = 1, HDG_MIXED_CONDENSE = 2 } hdg_precision;
 
 typedef struct {
     int32_t physics;      /* hdg_physics */

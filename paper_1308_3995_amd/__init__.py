@@ -13,8 +13,8 @@ from typing import Optional
 
 import numpy as np
 
-from ._lib import (HDG_EULER, HDG_FP64, HDG_MIXED, HDG_NS, HdgError, HdgParams, HdgSizes, check,  # noqa: F401
-                   load)
+from ._lib import (HDG_EULER, HDG_FP64, HDG_MIXED, HDG_MIXED_CONDENSE, HDG_NS, HdgError, HdgParams,  # noqa: F401
+                   HdgSizes, check, load)
 
 __all__ = ["load", "HDGPlan", "HdgError", "HDG_FP64", "HDG_MIXED"]
 
@@ -47,7 +47,8 @@ class HDGPlan:
         deg = np.ascontiguousarray(degree, dtype=np.int8)
         self.physics = physics
         self.precision = precision
-        prm = HdgParams(HDG_NS if physics == "ns" else HDG_EULER, HDG_MIXED if precision == "mixed" else HDG_FP64,
+        prec = {"fp64": HDG_FP64, "mixed": HDG_MIXED, "mixed_condense": HDG_MIXED_CONDENSE}[precision]
+        prm = HdgParams(HDG_NS if physics == "ns" else HDG_EULER, prec,
                         gamma, mach, math.radians(aoa_deg), reynolds, prandtl, alpha, cfl, sc_eps0, sc_beta)
         h = C.c_void_p()
         check(self.lib.hdg_plan_create(C.byref(h), xy.ctypes.data, xy.shape[0], tri.ctypes.data, tri.shape[0],

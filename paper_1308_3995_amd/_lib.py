@@ -15,7 +15,7 @@ HDG_OK = 0
 STATUS_NAMES = {0: "HDG_OK", 1: "HDG_ERR_INVALID_ARG", 2: "HDG_ERR_OOM", 3: "HDG_ERR_SINGULAR_LOCAL",
                 4: "HDG_ERR_NONFINITE", 5: "HDG_ERR_NOT_CONVERGED", 6: "HDG_ERR_HIP"}
 HDG_EULER, HDG_NS = 0, 1
-HDG_FP64, HDG_MIXED = 0, 1
+HDG_FP64, HDG_MIXED, HDG_MIXED_CONDENSE = 0, 1, 2
 
 EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_pattern", "hdg_assemble_condense",
            "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",

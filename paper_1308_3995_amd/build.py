@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhdg.so")
-SOURCES = ["plan.cpp", "abi.cpp", "condense.hip", "skeleton.hip", "ns.hip", "newton.hip", "adapt.hip"]
+SOURCES = ["plan.cpp", "abi.cpp", "condense.hip", "condense_mixed.hip", "skeleton.hip", "ns.hip", "newton.hip",
+           "adapt.hip"]
 
 ARCH = os.environ.get("HDG_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are disabled for every device function.

@@ -24,12 +24,17 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
-// Broadcast of lane src's value (src uniform across the wave) through two readlanes.
+// Broadcast of lane src's value (src uniform across the wave) through two readlanes (one for a
+// float).
 __device__ __forceinline__ double lane_bcast(double v, int src) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)b, src);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
     return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
 // Wave-wide maximum of a 32-bit key: DPP prefix maxima within rows of 16 lanes, then the
@@ -49,8 +54,8 @@ __device__ __forceinline__ unsigned wave_max_key(unsigned x) {
 // keeps the pivot within a factor 1 - 2^-24 of the largest candidate, which is as stable as
 // exact partial pivoting. Keys: 0 for used rows, bits(|v|) + 1 otherwise (the bit pattern
 // of a non-negative float orders like its value).
-template <int RH>
-__device__ __forceinline__ int pivot_row(const double (&v)[RH], const bool (&used)[RH]) {
+template <int RH, typename T>
+__device__ __forceinline__ int pivot_row(const T (&v)[RH], const bool (&used)[RH]) {
     unsigned key[RH], best = 0u;
 #pragma unroll
     for (int h = 0; h < RH; ++h) {
@@ -70,11 +75,14 @@ __device__ __forceinline__ int pivot_row(const double (&v)[RH], const bool (&use
 // lane and 64 + lane), N = 4 Np <= 64 RH rows. Wave w holds the A columns
 // (w / WPF) Np + (w % WPF) NPW + jj, jj < NPW (NPW = ceil(Np / WPF); columns past Np are
 // padding), in mA, and NBW right-hand-side columns in mB. mykk[h] receives the step at
-// which row h * 64 + lane was the pivot row.
-template <int NP, int NBW, int RH, int WPF>
-__device__ __forceinline__ void gj_eliminate(double (&mA)[RH][(NP + WPF - 1) / WPF], double (&mB)[RH][NBW],
-                                             int wave, int lane, double (*sFm)[64 * RH], int* sPiv, double* sPVk,
-                                             int (&mykk)[RH]) {
+// which row h * 64 + lane was the pivot row. T is double, or float for the mixed-precision
+// condensation. With rec_f non-null the multipliers of step k go to rec_f[k * 64 RH + row] and
+// its pivot row to rec_piv[k], so that the elimination can be replayed on further right-hand
+// sides (gj_replay).
+template <int NP, int NBW, int RH, int WPF, typename T = double>
+__device__ __forceinline__ void gj_eliminate(T (&mA)[RH][(NP + WPF - 1) / WPF], T (&mB)[RH][NBW],
+                                             int wave, int lane, T (*sFm)[64 * RH], int* sPiv, T* sPVk,
+                                             int (&mykk)[RH], T* rec_f = nullptr, int* rec_piv = nullptr) {
     constexpr int N = 4 * NP;
     constexpr int NPW = (NP + WPF - 1) / WPF;
     static_assert(N <= 64 * RH, "rows per lane");
@@ -87,28 +95,31 @@ __device__ __forceinline__ void gj_eliminate(double (&mA)[RH][(NP + WPF - 1) / W
         mykk[h] = 0;
     }
     // entry of the pivot row held by this wave in a column (p uniform)
-    auto prow = [&](const double (&col)[RH], int p) {
-        double v = col[0];
+    auto prow = [&](const T (&col)[RH], int p) {
+        T v = col[0];
 #pragma unroll
         for (int h = 1; h < RH; ++h)
             if ((p >> 6) == h) v = col[h];
         return lane_bcast(v, p & 63);
     };
-    auto publish = [&](int k, const double (&col)[RH]) {
+    auto publish = [&](int k, const T (&col)[RH]) {
         const int pn = pivot_row<RH>(col, used);
-        const double pv = prow(col, pn);
+        const T pv = prow(col, pn);
 #pragma unroll
         for (int h = 0; h < RH; ++h) {
             const int row = h * 64 + lane;
-            sFm[k & 1][h * 64 + lane] = (row == pn || row >= N) ? 0.0 : col[h] / pv;
+            const T fm = (row == pn || row >= N) ? T(0) : col[h] / pv;
+            sFm[k & 1][h * 64 + lane] = fm;
+            if (rec_f) rec_f[k * 64 * RH + h * 64 + lane] = fm;
         }
         if (lane == 0) {
             sPiv[k & 1] = pn;
             sPVk[k] = pv;
+            if (rec_piv) rec_piv[k] = pn;
         }
     };
     if (wave == 0) {
-        double c0[RH];
+        T c0[RH];
 #pragma unroll
         for (int h = 0; h < RH; ++h) c0[h] = mA[h][0];
         publish(0, c0);
@@ -118,7 +129,7 @@ __device__ __forceinline__ void gj_eliminate(double (&mA)[RH][(NP + WPF - 1) / W
     for (int k = 1; k <= N; ++k) {
         // apply step k - 1; the owner of column k (if any) then publishes step k
         const int piv = __builtin_amdgcn_readfirstlane(sPiv[(k - 1) & 1]);
-        double f[RH];
+        T f[RH];
 #pragma unroll
         for (int h = 0; h < RH; ++h) {
             f[h] = sFm[(k - 1) & 1][h * 64 + lane];
@@ -128,10 +139,10 @@ __device__ __forceinline__ void gj_eliminate(double (&mA)[RH][(NP + WPF - 1) / W
             }
         }
         auto update = [&](auto& m, int j) {
-            double col[RH];
+            T col[RH];
 #pragma unroll
             for (int h = 0; h < RH; ++h) col[h] = m[h][j];
-            const double pr = prow(col, piv);
+            const T pr = prow(col, piv);
 #pragma unroll
             for (int h = 0; h < RH; ++h) m[h][j] -= f[h] * pr;
         };
@@ -139,7 +150,7 @@ __device__ __forceinline__ void gj_eliminate(double (&mA)[RH][(NP + WPF - 1) / W
         const int jk = k % NP, ow = (k / NP) * WPF + jk / NPW, jl = jk % NPW;
         if (k < N && wave == ow) {
             update(mA, jl);
-            double ck[RH];
+            T ck[RH];
 #pragma unroll
             for (int h = 0; h < RH; ++h) ck[h] = mA[h][jl];
             publish(k, ck);
@@ -155,6 +166,20 @@ __device__ __forceinline__ void gj_eliminate(double (&mA)[RH][(NP + WPF - 1) / W
         for (int i = 0; i < NBW; ++i) update(mB, i);
         __syncthreads();
     }
+}
+
+// Replay of a recorded elimination on one more right-hand side, by one wave (RH = 1, one row per
+// lane, lanes past N idle): v holds the row-`lane` entry of the new column in float64 and is
+// updated step by step with the recorded (float) multipliers; afterwards the solution entry of
+// step kk is (the entry of the row pivoted at kk) / sPVk[kk], as after gj_eliminate.
+template <int N, typename T>
+__device__ __forceinline__ double gj_replay(double v, int lane, const T* rec_f, const int* rec_piv) {
+    for (int k = 0; k < N; ++k) {
+        const int piv = __builtin_amdgcn_readfirstlane(rec_piv[k]);
+        const double pr = lane_bcast(v, piv);
+        v -= (double)rec_f[k * 64 + lane] * pr;
+    }
+    return v;
 }
 
 }  // namespace hdg

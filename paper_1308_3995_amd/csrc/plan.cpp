@@ -253,7 +253,14 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
     P.nv = nv;
     if (ne <= 0 || nv < 3) { set_error("empty mesh"); return HDG_ERR_INVALID_ARG; }
     if (prm.physics != HDG_EULER && prm.physics != HDG_NS) { set_error("unknown physics"); return HDG_ERR_INVALID_ARG; }
-    if (prm.precision != HDG_FP64 && prm.precision != HDG_MIXED) { set_error("unknown precision"); return HDG_ERR_INVALID_ARG; }
+    if (prm.precision != HDG_FP64 && prm.precision != HDG_MIXED && prm.precision != HDG_MIXED_CONDENSE) {
+        set_error("unknown precision");
+        return HDG_ERR_INVALID_ARG;
+    }
+    if (prm.precision == HDG_MIXED_CONDENSE && prm.physics == HDG_NS) {
+        set_error("HDG_MIXED_CONDENSE: the mixed-precision condensation is built for the Euler equations only");
+        return HDG_ERR_INVALID_ARG;
+    }
     if (!(prm.gamma > 1.0) || !(prm.mach >= 0.0) || (P.ns && !(prm.reynolds > 0.0)) || !(prm.cfl >= 0.0) ||
         !(prm.sc_eps0 >= 0.0) || !std::isfinite(prm.sc_beta)) {
         set_error("invalid flow parameters");

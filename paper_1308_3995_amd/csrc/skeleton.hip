@@ -1554,7 +1554,7 @@ hdg_status skeleton_solve(Plan& p, const double* bsr, const double* rhs, double*
         return HDG_OK;
     }
     Solver S = make_solver(p, ws);
-    const bool mixed = p.prm.precision == HDG_MIXED;
+    const bool mixed = p.prm.precision != HDG_FP64;
     const unsigned vblocks = (unsigned)((n + 255) / 256);
     const int pdeg = p.poly_degree;
 
