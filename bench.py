@@ -213,12 +213,14 @@ def measured_copy_peak(reps: int = 5) -> float:
     return 2.0 * n * 8 / (best * 1e-3) / 1e9
 
 
-def measured_fp64_peak(n: int = 8192, reps: int = 3) -> float:
-    """FP64 rate (TFLOP/s) a plain library DGEMM of n x n reaches, best of `reps`: the measured
-    peak beside the published 78.6 TFLOP/s."""
+def measured_fp64_peak(n: int = 8192, reps: int = 3, dtype: str = "float64") -> float:
+    """Rate (TFLOP/s) a plain library GEMM of n x n reaches, best of `reps`: the measured FP64 peak
+    beside the published 78.6 TFLOP/s (dtype "float32": the FP32 rate, TF32 off, beside 157.3)."""
     import torch
-    a = torch.rand(n, n, dtype=torch.float64, device="cuda")
-    b = torch.rand(n, n, dtype=torch.float64, device="cuda")
+    dt = getattr(torch, dtype)
+    torch.backends.cuda.matmul.allow_tf32 = False
+    a = torch.rand(n, n, dtype=dt, device="cuda")
+    b = torch.rand(n, n, dtype=dt, device="cuda")
     c = a @ b
     torch.cuda.synchronize()
     best = float("inf")
@@ -604,7 +606,10 @@ def main():
     if args.condense_configs:
         fp64_meas = measured_fp64_peak()
         log(f"[bench] library DGEMM reaches {fp64_meas:.1f} TFLOP/s (published FP64 peak {FP64_PEAK_TFLOPS})")
-        out["measured_peaks"] = {"hbm_copy_gbs": copy_peak, "fp64_dgemm_tflops": fp64_meas}
+        fp32_meas = measured_fp64_peak(dtype="float32")
+        log(f"[bench] library SGEMM reaches {fp32_meas:.1f} TFLOP/s (published FP32 peak 157.3)")
+        out["measured_peaks"] = {"hbm_copy_gbs": copy_peak, "fp64_dgemm_tflops": fp64_meas,
+                                 "fp32_sgemm_tflops": fp32_meas}
         out["condensation"] = condensation_report([c for c in args.condense_configs.split(",") if c],
                                                   fp64_measured=fp64_meas, hbm_measured=copy_peak)
         out["condensation_mixed"] = condensation_report([c for c in args.condense_configs.split(",") if c],

@@ -165,11 +165,15 @@ hdg_status hdg_plan_pattern(const hdg_plan* plan, int64_t* row_ptr_host, int32_t
  * (optional): if non-NULL the call synchronises and returns ||E||_2. The call itself
  * returns HDG_ERR_SINGULAR_LOCAL or HDG_ERR_NONFINITE only when res_norm_host or
  * elem_status_dev asks it to look (that needs a synchronisation).
- * Batching: one launch per (element degree, face degree) bucket. The first call on a plan
- * times the two register-budget variants of every bucket's kernel, keeps the faster one and
- * synchronises the stream once (the variants compute identical values). Later calls
- * capture the whole launch sequence in a hipGraph once per set of buffer pointers and
- * replay it; they are asynchronous unless res_norm_host or elem_status_dev is given.
+ * Batching: one launch per (element degree, face degree) bucket. Euler buckets have four
+ * kernel variants (blocked Gauss-Jordan on the matrix cores or the register-resident one, each
+ * at a 128- and a 256-VGPR budget). The first call on a plan times the variants of every
+ * bucket shape the process has not met yet, keeps the fastest, runs it and synchronises the
+ * stream once; the choice is kept per (physics, degree, face degree, precision, shock
+ * capturing, element-count class) for every later plan of the process, so plans agree bit for
+ * bit (the variants agree only up to rounding). Later calls capture the whole launch sequence
+ * in a hipGraph once per set of buffer pointers and replay it; they are asynchronous unless
+ * res_norm_host or elem_status_dev is given.
  * Call once outside any stream capture of the caller's own before capturing it. */
 hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const double* q_dev,
                                  const double* lam_dev, double* bsr_values_dev, double* rhs_dev,

@@ -20,9 +20,11 @@ SOURCES = ["plan.cpp", "abi.cpp", "condense.hip", "condense_mixed.hip", "skeleto
            "adapt.hip"]
 
 ARCH = os.environ.get("HDG_OFFLOAD_ARCH", "gfx950")
-# Packed FP32 instructions are disabled for every device function.
+# Packed FP32 instructions are disabled for every device function; matrix-core instructions keep
+# their accumulators in ordinary VGPRs (no copies through the accumulation registers).
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-Wno-unused-command-line-argument", f"-I{os.path.join(ROOT, 'include')}"]
+          "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form", "-Wno-unused-command-line-argument",
+          f"-I{os.path.join(ROOT, 'include')}"]
 
 
 def hipcc() -> str:

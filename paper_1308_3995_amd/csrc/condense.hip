@@ -14,17 +14,26 @@
 // matrix; the diagonal blocks and g_K go to per-face slots summed by k_diag_sum in a
 // fixed order, so the assembly is deterministic and atomic-free.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "euler_elem.h"
 #include "gj.h"
+#include "gj_blocked.h"
 #include "hdg_internal.h"
 
 namespace hdg {
 
-// MINW is the register budget's target in waves per SIMD (4: 128 VGPRs, 2: 256); both are
-// built and the faster one per bucket is picked by timing on the plan's first call.
-template <int P, int PF, bool DBG, int MINW, bool SC>
+// MINW is the register budget's target in waves per SIMD (4: 128 VGPRs, 2: 256); GJB selects the
+// elimination: the blocked matrix-core Gauss-Jordan (gj_blocked.h) or the register-resident
+// one with one pivot column per step (gj.h). All four are built and the fastest per bucket is
+// picked by timing on the plan's first call.
+//
+// LDS: one region serves the phases in turn: the point data (ElemShared) and the staged
+// reference tables during assembly, then (blocked elimination) the augmented system
+// [A_K | B_K | r_K] staged column-major, then [X_K | y_K] for the skeleton rows.
+template <int P, int PF, bool DBG, int MINW, bool SC, bool GJB>
 __global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_condense_euler(CondArgs a) {
     constexpr int NP = n_modes(P);
@@ -32,6 +41,7 @@ void k_condense_euler(CondArgs a) {
     constexpr int NPF = PF + 1;
     constexpr int F = 12 * NPF;
     constexpr int FB = 4 * NPF;                // B_K columns of one local face
+    constexpr int NCOL = N + F + 1;            // columns of [A_K | B_K | r_K]
     constexpr int RH = EulerShape<P>::RH;
     constexpr int WPF = EulerShape<P>::WPF;
     constexpr int NW = EulerShape<P>::NW;
@@ -39,13 +49,16 @@ void k_condense_euler(CondArgs a) {
     constexpr int NPW = (NP + WPF - 1) / WPF;  // A_K columns per wave
     constexpr int NBW = (F + 1 + NW - 1) / NW; // B_K / r_K columns per wave (zero padded)
     constexpr int Q = n_vol_q(P);
+    constexpr int QF = PF + 2;
+    using GB = GjBlocked<N, NCOL, NW, double>;
+    constexpr int ESD = (int)(sizeof(ElemShared<P, PF>) / sizeof(double));
+    constexpr int TAB = 2 * Q * NP + 3 * QF * NP + sc_scratch_doubles<P>();
+    constexpr int SYS = GJB ? N * NCOL : (F + 1) * N;   // staged system or [X_K | y_K]
+    constexpr int UD = ESD + TAB > SYS ? ESD + TAB : SYS;
 
-    __shared__ ElemShared<P, PF> sh;
+    __shared__ double sU[UD];
     __shared__ FaceTables<P, PF> ft;
-    __shared__ double sX[(F + 1) * N];
-    __shared__ double sFm[2][64 * RH];
-    __shared__ double sPVk[N];
-    __shared__ int sPiv[2];
+    __shared__ double sJB[3][QF][16];
     __shared__ int sBad;
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -54,12 +67,11 @@ void k_condense_euler(CondArgs a) {
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
     if (tid == 0) sBad = 0;
-    // reference tables staged in the (not yet used) sX area: basis gradients [r][q][i] and the
-    // element's basis at its face points [lf][g][i]; then the shock-capturing scratch
-    constexpr int QF = PF + 2;
-    static_assert(2 * Q * NP + 3 * QF * NP + sc_scratch_doubles<P>() <= (F + 1) * N, "table staging fits in sX");
-    double* sVg = sX;
-    double* sFp = sX + 2 * Q * NP;
+    // assembly phase: point data, then the reference tables (basis gradients [r][q][i] and the
+    // element's basis at its face points [lf][g][i]) and the shock-capturing scratch
+    ElemShared<P, PF>& sh = *reinterpret_cast<ElemShared<P, PF>*>(sU);
+    double* sVg = sU + ESD;
+    double* sFp = sVg + 2 * Q * NP;
     double* sScb = sFp + 3 * QF * NP;
     point_data<P, PF, SC>(a, E, sh, sScb, tid, NTH);
     for (int t = tid; t < 2 * Q * NP; t += NTH) sVg[t] = a.vgrad[t];
@@ -70,7 +82,7 @@ void k_condense_euler(CondArgs a) {
     }
     face_tables<P, PF>(a, E, sh, sFp, ft, tid, NTH);
     __syncthreads();
-    const auto& sJB = sh.sJB;
+    for (int t = tid; t < 3 * QF * 16; t += NTH) (&sJB[0][0][0])[t] = (&sh.sJB[0][0][0])[t];
     const int fld = wave / WPF, part = wave % WPF;
     double sig;
     {
@@ -98,7 +110,7 @@ void k_condense_euler(CondArgs a) {
                 const int pe = E->pe[lf];
                 if (E->face[lf] >= 0 && k <= pe) {
                     const double* fp = sFp + lf * QF * NP;
-                    for (int g = 0; g < pe + 2; ++g) v += fp[g * NP + ii] * sJB[lf][g][fa * 4 + b] * ft.ps[lf][g][k];
+                    for (int g = 0; g < pe + 2; ++g) v += fp[g * NP + ii] * sh.sJB[lf][g][fa * 4 + b] * ft.ps[lf][g][k];
                 }
             } else if (cb == F) {
                 v = r_entry<P, PF, SC>(a, E, sh, sVg, sFp, sScb, fa, ii);
@@ -128,44 +140,109 @@ void k_condense_euler(CondArgs a) {
     }
     if (DBG) {
         __syncthreads();
-        schur_rows<P, PF, DBG>(a, E, sh, ft, sX, tid, NTH);
+        schur_rows<P, PF, DBG>(a, E, sJB, ft, sU, tid, NTH);
         return;
     }
 
-    // ---- Gauss-Jordan elimination with partial pivoting
-    int mykk[RH];
-    gj_eliminate<NP, NBW, RH, WPF>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
-
-    // ---- X_K = A_K^-1 B_K and y_K = A_K^-1 r_K: row kk of the solution sits in the row
-    // whose pivot was taken at step kk
+    double* sX = sU;
     const int bslot = slot - a.start;
     double* st = a.store + (int64_t)bslot * ((F + 1) * N);
+    if constexpr (!GJB) {
+        // ---- register-resident Gauss-Jordan elimination with partial pivoting (its first
+        // barrier follows every wave's assembly, so sX may overwrite the assembly tables)
+        __shared__ double sFm[2][64 * RH];
+        __shared__ double sPVk[N];
+        __shared__ int sPiv[2];
+        int mykk[RH];
+        gj_eliminate<NP, NBW, RH, WPF>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk);
+        // X_K = A_K^-1 B_K and y_K = A_K^-1 r_K: row kk of the solution sits in the row whose
+        // pivot was taken at step kk
 #pragma unroll
-    for (int h = 0; h < RH; ++h) {
-        if (h * 64 + lane >= N) continue;
-        const int kk = mykk[h];
-        const double pv = sPVk[kk];
-        const double inv = 1.0 / pv;
-        bool bad = false;
+        for (int h = 0; h < RH; ++h) {
+            if (h * 64 + lane >= N) continue;
+            const int kk = mykk[h];
+            const double pv = sPVk[kk];
+            const double inv = 1.0 / pv;
+            bool bad = false;
 #pragma unroll
-        for (int i = 0; i < NBW; ++i) {
-            const int cb = wave * NBW + i;
-            if (cb <= F) {
-                const double x = mB[h][i] * inv;
-                bad |= !isfinite(x);
-                sX[cb * N + kk] = x;
-                st[(int64_t)cb * N + kk] = x;
+            for (int i = 0; i < NBW; ++i) {
+                const int cb = wave * NBW + i;
+                if (cb <= F) {
+                    const double x = mB[h][i] * inv;
+                    bad |= !isfinite(x);
+                    sX[cb * N + kk] = x;
+                    st[(int64_t)cb * N + kk] = x;
+                }
+            }
+            if (!(fabs(pv) > 0.0) || !isfinite(inv)) sBad = 1;
+            else if (bad && sBad == 0) sBad = 2;
+        }
+        __syncthreads();
+        if (tid == 0 && sBad != 0) {
+            a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+            a.flag[0] = 1;
+        }
+        schur_rows<P, PF, DBG>(a, E, sJB, ft, sX, tid, NTH);
+    } else {
+        // ---- stage [A_K | B_K | r_K] column-major (the assembly tables are no longer read)
+        __shared__ typename GB::Shared gs;
+        GB::init(gs, tid, NTH);
+        __syncthreads();
+        double* sW = sU;
+#pragma unroll
+        for (int h = 0; h < RH; ++h) {
+            const int row = h * 64 + lane;
+            if (row >= N) continue;
+#pragma unroll
+            for (int j = 0; j < NPW; ++j)
+                if (part * NPW + j < NP) sW[(fld * NP + part * NPW + j) * N + row] = mA[h][j];
+#pragma unroll
+            for (int i = 0; i < NBW; ++i) {
+                const int cb = wave * NBW + i;
+                if (cb <= F) sW[(N + cb) * N + row] = mB[h][i];
             }
         }
-        if (!(fabs(pv) > 0.0) || !isfinite(inv)) sBad = 1;
-        else if (bad && sBad == 0) sBad = 2;
+        __syncthreads();
+
+        // ---- blocked Gauss-Jordan elimination with partial pivoting on the matrix cores
+        typename GB::tile acc[GB::TPW];
+        GB::load(acc, sW, wave, lane);
+        GB::eliminate(acc, gs, wave, lane);
+
+        // ---- X_K = A_K^-1 B_K and y_K = A_K^-1 r_K: row kk of the solution sits in the row
+        // pivoted at step kk (sX overwrites the staged system, which every wave has loaded)
+        {
+            const int lc = lane & 15, g = lane >> 4;
+            bool bad = false, sing = false;
+#pragma unroll
+            for (int s = 0; s < GB::TPW; ++s) {
+                const int c = 16 * (wave + NW * s) + lc;
+                if (c < N || c >= NCOL) continue;
+#pragma unroll
+                for (int rt = 0; rt < GB::RT; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * rt + GB::row_in_tile(g, v);
+                        if (r >= N) continue;
+                        const int kk = gs.rowstep[r];
+                        const double pv = gs.pvk[kk];
+                        const double x = GB::get(acc[s], rt, v) / pv;
+                        sing |= !(fabs(pv) > 0.0) || !isfinite(pv);
+                        bad |= !isfinite(x);
+                        sX[(c - N) * N + kk] = x;
+                    }
+            }
+            if (sing) sBad = 1;
+            else if (bad && sBad == 0) sBad = 2;
+        }
+        __syncthreads();
+        for (int t = tid; t < (F + 1) * N; t += NTH) st[t] = sX[t];
+        if (tid == 0 && sBad != 0) {
+            a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
+            a.flag[0] = 1;
+        }
+        schur_rows<P, PF, DBG>(a, E, sJB, ft, sX, tid, NTH);
     }
-    __syncthreads();
-    if (tid == 0 && sBad != 0) {
-        a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
-        a.flag[0] = 1;
-    }
-    schur_rows<P, PF, DBG>(a, E, sh, ft, sX, tid, NTH);
 }
 
 // Sum the two diagonal contributions of every face in a fixed order and the two halves
@@ -222,6 +299,8 @@ __global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start
 }
 
 // One launch per (degree, face-degree) bucket; 4, 8 or 16 waves per element (degree <= 3, 4, 5).
+// Variants: 0 / 1 register-resident elimination at 128 / 256 VGPRs, 2 / 3 blocked matrix-core
+// elimination at 128 / 256 VGPRs.
 template <int P, int PF>
 static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, bool dbg, int variant, hipStream_t s) {
     a.vphi = p.d_tab + p.tix.vol_phi[P];
@@ -231,17 +310,21 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.start = bk.start;
     constexpr int nth = 64 * EulerShape<P>::NW;
     if (a.sc_eps0 > 0.0) {
-        // shock capturing on: one register budget (both tuning variants launch it)
+        // shock capturing on: one kernel shape (every tuning variant launches it)
         if (dbg)
-            hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, true>), dim3(bk.count), dim3(nth), 0, s, a);
+            hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, true, false>), dim3(bk.count), dim3(nth), 0, s, a);
         else
-            hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, true>), dim3(bk.count), dim3(nth), 0, s, a);
+            hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, true, false>), dim3(bk.count), dim3(nth), 0, s, a);
     } else if (dbg) {
-        hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, false>), dim3(bk.count), dim3(nth), 0, s, a);
+        hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, false, false>), dim3(bk.count), dim3(nth), 0, s, a);
     } else if (variant == 1) {
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, false>), dim3(bk.count), dim3(nth), 0, s, a);
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, false, false>), dim3(bk.count), dim3(nth), 0, s, a);
+    } else if (variant == 2) {
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, false, true>), dim3(bk.count), dim3(nth), 0, s, a);
+    } else if (variant == 3) {
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, false, true>), dim3(bk.count), dim3(nth), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, false>), dim3(bk.count), dim3(nth), 0, s, a);
+        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, false, false>), dim3(bk.count), dim3(nth), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -278,40 +361,59 @@ hipError_t launch_clear_status(const Plan& p, int32_t* status, int32_t* flag, hi
     return hipGetLastError();
 }
 
-// Times both register-budget variants of every bucket (two interleaved rounds, the faster of
-// each variant's two launches counts) and keeps the faster. Both variants compute the same
-// values, so the outputs of the last launch are the condensed system. Synchronises once.
+// Times the kernel variants of every bucket (two interleaved rounds, the faster of each
+// variant's two launches counts) and keeps the fastest. The variants compute the same values up
+// to rounding, so the outputs of the last launch are the condensed system. Synchronises once.
+constexpr int kCondenseVariants = 4;
+
 template <typename LaunchFn>
-static hipError_t tune_buckets(Plan& p, hipStream_t s, LaunchFn launch_variant) {
-    const int nb = (int)p.buckets.size();
-    std::vector<hipEvent_t> ev((size_t)nb * 8, nullptr);
+static hipError_t tune_buckets(Plan& p, hipStream_t s, const std::vector<int>& todo, LaunchFn launch_variant) {
+    constexpr int NV = kCondenseVariants;
+    const int nt = (int)todo.size();
+    std::vector<hipEvent_t> ev((size_t)nt * 4 * NV, nullptr);
     hipError_t err = hipSuccess;
     for (auto& e : ev)
         if (err == hipSuccess) err = hipEventCreate(&e);
-    for (int b = 0; b < nb && err == hipSuccess; ++b)
+    for (int i = 0; i < nt && err == hipSuccess; ++i)
         for (int round = 0; round < 2 && err == hipSuccess; ++round)
-            for (int v = 0; v < 2 && err == hipSuccess; ++v) {
-                hipEvent_t* e = &ev[(size_t)b * 8 + round * 4 + v * 2];
+            for (int v = 0; v < NV && err == hipSuccess; ++v) {
+                hipEvent_t* e = &ev[(size_t)i * 4 * NV + round * 2 * NV + v * 2];
                 err = hipEventRecord(e[0], s);
-                if (err == hipSuccess) err = launch_variant(b, v);
+                if (err == hipSuccess) err = launch_variant(todo[i], v);
                 if (err == hipSuccess) err = hipEventRecord(e[1], s);
             }
-    if (err == hipSuccess && nb > 0) err = hipEventSynchronize(ev.back());
-    p.variant.assign(nb, 0);
-    for (int b = 0; b < nb && err == hipSuccess; ++b) {
-        float t[2] = {1e30f, 1e30f};
+    if (err == hipSuccess && nt > 0) err = hipEventSynchronize(ev.back());
+    for (int i = 0; i < nt && err == hipSuccess; ++i) {
+        float t[NV];
+        for (int v = 0; v < NV; ++v) t[v] = 1e30f;
         for (int round = 0; round < 2; ++round)
-            for (int v = 0; v < 2; ++v) {
+            for (int v = 0; v < NV; ++v) {
                 float ms = 0.f;
-                const hipEvent_t* e = &ev[(size_t)b * 8 + round * 4 + v * 2];
+                const hipEvent_t* e = &ev[(size_t)i * 4 * NV + round * 2 * NV + v * 2];
                 if (hipEventElapsedTime(&ms, e[0], e[1]) == hipSuccess) t[v] = std::min(t[v], ms);
             }
-        p.variant[b] = t[1] < t[0] ? 1 : 0;
+        int best = 0;
+        for (int v = 1; v < NV; ++v)
+            if (t[v] < t[best]) best = v;
+        p.variant[todo[i]] = best;
     }
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
-    if (err == hipSuccess) p.tuned = true;
     return err;
+}
+
+// The tuned variant per bucket shape is shared by every plan of the process: the first plan that
+// meets a (physics, degree, face degree, precision, shock capturing, element-count class) times
+// the variants and later plans reuse its choice, so that the plans of one process run the same
+// kernels and give the same bits.
+static std::mutex g_variant_mu;
+static std::map<uint64_t, int> g_variant;
+
+static uint64_t variant_key(const Plan& p, const Bucket& bk) {
+    uint64_t size_class = 0;
+    for (int64_t c = bk.count; c > 0; c >>= 1) ++size_class;   // bit length of the element count
+    return (uint64_t)bk.p | (uint64_t)bk.pf << 4 | (uint64_t)p.prm.precision << 8 |
+           (uint64_t)(p.prm.sc_eps0 > 0.0) << 12 | (uint64_t)p.ns << 13 | size_class << 16;
 }
 
 hipError_t launch_condense(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
@@ -349,12 +451,31 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
     // HDG_MIXED_CONDENSE: float32 elimination with float64 refinement of y_K for degree <= 4
     const bool mixed = p.prm.precision == HDG_MIXED_CONDENSE;
     if (!debug && !p.tuned) {
-        return tune_buckets(p, s, [&](int b, int v) {
-            CondArgs ab = a;
-            ab.store = store + p.buckets[b].store_off;
-            if (mixed && mixed_bucket_supported(p.buckets[b])) return dispatch_condense_mixed(p, p.buckets[b], ab, s);
-            return dispatch_condense(p, p.buckets[b], ab, false, v, s);
-        });
+        const int nb = (int)p.buckets.size();
+        p.variant.assign(nb, 0);
+        std::vector<int> todo;
+        {
+            std::lock_guard<std::mutex> g(g_variant_mu);
+            for (int b = 0; b < nb; ++b) {
+                const auto it = g_variant.find(variant_key(p, p.buckets[b]));
+                if (it != g_variant.end()) p.variant[b] = it->second;
+                else todo.push_back(b);
+            }
+        }
+        if (!todo.empty()) {
+            const hipError_t err = tune_buckets(p, s, todo, [&](int b, int v) {
+                CondArgs ab = a;
+                ab.store = store + p.buckets[b].store_off;
+                if (mixed && mixed_bucket_supported(p.buckets[b]))
+                    return dispatch_condense_mixed(p, p.buckets[b], ab, s);
+                return dispatch_condense(p, p.buckets[b], ab, false, v, s);
+            });
+            if (err != hipSuccess) return err;
+            std::lock_guard<std::mutex> g(g_variant_mu);
+            for (int b : todo) p.variant[b] = g_variant.emplace(variant_key(p, p.buckets[b]), p.variant[b]).first->second;
+        }
+        p.tuned = true;
+        // the chosen variants run once more below, so the outputs come from them
     }
     for (size_t b = 0; b < p.buckets.size(); ++b) {
         const Bucket& bk = p.buckets[b];

@@ -1,16 +1,18 @@
 // Mixed-precision static condensation for the Euler equations (element degree <= 4), gfx950.
 //
 // The element's blocks are assembled in float64 exactly as in the float64 kernel (Sec. 3.2,
-// eq. linearsystem). The augmented system [A_K | B_K | r_K] is then eliminated in float32
-// (Gauss-Jordan with partial pivoting, the multipliers and pivot rows of every step recorded in
-// LDS), giving X_K = A_K^-1 B_K and a first y_K to float32 accuracy. y_K is refined in float64:
-// the residual r_K - A_K y_K is formed with the float64 A_K kept in registers, the recorded
-// elimination is replayed on it in float64 arithmetic, and the correction is added (two
-// sweeps, each contracting the error by about kappa(A_K) times the float32 unit roundoff).
-// The skeleton rows follow as in the float64 kernel (Sec. 3.4 eq. hybridsystem):
-// g_K = r_lam,K - C_K y_K from the refined y_K, S_K = D_K - C_K X_K from the float32 X_K.
+// eq. linearsystem). The augmented system [A_K | B_K | r_K] is then eliminated in float32 on the
+// matrix cores (blocked Gauss-Jordan with partial pivoting, the rank-4 operator and pivot rows
+// of every panel recorded in LDS), giving X_K = A_K^-1 B_K and a first y_K to float32 accuracy.
+// y_K is refined in float64: the residual r_K - A_K y_K is formed with the float64 A_K kept in
+// registers, the recorded elimination is replayed on it in float64 arithmetic, and the
+// correction is added (two sweeps, each contracting the error by about kappa(A_K) times the
+// float32 unit roundoff). The skeleton rows follow as in the float64 kernel (Sec. 3.4
+// eq. hybridsystem): g_K = r_lam,K - C_K y_K from the refined y_K, S_K = D_K - C_K X_K from the
+// float32 X_K.
 #include "euler_elem.h"
 #include "gj.h"
+#include "gj_blocked.h"
 
 namespace hdg {
 
@@ -22,6 +24,7 @@ void k_condense_euler_mixed(CondArgs a) {
     constexpr int NPF = PF + 1;
     constexpr int F = 12 * NPF;
     constexpr int FB = 4 * NPF;                // B_K columns of one local face
+    constexpr int NCOL = N + F + 1;
     constexpr int RH = EulerShape<P>::RH;
     static_assert(RH == 1, "one row per lane (degree <= 4)");
     constexpr int WPF = EulerShape<P>::WPF;
@@ -33,14 +36,20 @@ void k_condense_euler_mixed(CondArgs a) {
     constexpr int QF = PF + 2;
     constexpr int kSweeps = 2;                 // float64 refinement sweeps of y_K
     constexpr int RW = F / NBW, IR = F % NBW;  // the wave and column slot holding r_K
+    using GB = GjBlocked<N, NCOL, NW, float>;
+    static_assert(GB::ROWS <= 64, "the float64 replay runs one row per lane");
+    constexpr int ESD = (int)(sizeof(ElemShared<P, PF>) / sizeof(double));
+    constexpr int TAB = 2 * Q * NP + 3 * QF * NP + sc_scratch_doubles<P>();
+    constexpr int WD = (N * NCOL + 1) / 2;     // the float32 staged system, in doubles
+    constexpr int UD0 = ESD + TAB > WD ? ESD + TAB : WD;
+    constexpr int UD = UD0 > (F + 1) * N ? UD0 : (F + 1) * N;
 
-    __shared__ ElemShared<P, PF> sh;
+    // one region in turn: assembly point data and tables, the staged float32 system, [X_K | y_K]
+    __shared__ double sU[UD];
     __shared__ FaceTables<P, PF> ft;
-    __shared__ double sX[(F + 1) * N];
-    __shared__ float sFm[2][64];
-    __shared__ float sPVk[N];
-    __shared__ int sPiv[2];
-    __shared__ float recF[N * 64];
+    __shared__ double sJB[3][QF][16];
+    __shared__ typename GB::Shared gs;
+    __shared__ float recY[N * GB::ROWS];
     __shared__ int recPiv[N];
     __shared__ double sPart[NW][64];
     __shared__ int sBad;
@@ -50,10 +59,9 @@ void k_condense_euler_mixed(CondArgs a) {
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
     if (tid == 0) sBad = 0;
-    // reference tables staged in the (not yet used) sX area
-    static_assert(2 * Q * NP + 3 * QF * NP + sc_scratch_doubles<P>() <= (F + 1) * N, "table staging fits in sX");
-    double* sVg = sX;
-    double* sFp = sX + 2 * Q * NP;
+    ElemShared<P, PF>& sh = *reinterpret_cast<ElemShared<P, PF>*>(sU);
+    double* sVg = sU + ESD;
+    double* sFp = sVg + 2 * Q * NP;
     double* sScb = sFp + 3 * QF * NP;
     point_data<P, PF, false>(a, E, sh, sScb, tid, NTH);
     for (int t = tid; t < 2 * Q * NP; t += NTH) sVg[t] = a.vgrad[t];
@@ -64,7 +72,7 @@ void k_condense_euler_mixed(CondArgs a) {
     }
     face_tables<P, PF>(a, E, sh, sFp, ft, tid, NTH);
     __syncthreads();
-    const auto& sJB = sh.sJB;
+    for (int t = tid; t < 3 * QF * 16; t += NTH) (&sJB[0][0][0])[t] = (&sh.sJB[0][0][0])[t];
     const int fld = wave / WPF, part = wave % WPF;
     double sig;
     {
@@ -89,7 +97,7 @@ void k_condense_euler_mixed(CondArgs a) {
             const int pe = E->pe[lf];
             if (E->face[lf] >= 0 && k <= pe) {
                 const double* fp = sFp + lf * QF * NP;
-                for (int g = 0; g < pe + 2; ++g) v += fp[g * NP + ii] * sJB[lf][g][fa * 4 + b] * ft.ps[lf][g][k];
+                for (int g = 0; g < pe + 2; ++g) v += fp[g * NP + ii] * sh.sJB[lf][g][fa * 4 + b] * ft.ps[lf][g][k];
             }
         } else if (cb == F) {
             v = r_entry<P, PF, false>(a, E, sh, sVg, sFp, sScb, fa, ii);
@@ -102,68 +110,86 @@ void k_condense_euler_mixed(CondArgs a) {
         if (lane == 0) a.res_elem[slot] = s2;
     }
 
-    // ---- float32 Gauss-Jordan elimination, every step recorded
-    float mA[RH][NPW], mB[RH][NBW];
-#pragma unroll
-    for (int j = 0; j < NPW; ++j) mA[0][j] = (float)A64[j];
-#pragma unroll
-    for (int i = 0; i < NBW; ++i) mB[0][i] = (float)B64[i];
-    int mykk[RH];
-    gj_eliminate<NP, NBW, RH, WPF, float>(mA, mB, wave, lane, sFm, sPiv, sPVk, mykk, recF, recPiv);
-
-    // ---- X_K and the first y_K: row kk of the solution sits in the row pivoted at step kk
-    const int bslot = slot - a.start;
-    double* st = a.store + (int64_t)bslot * ((F + 1) * N);
+    // ---- stage the float32 system column-major (the assembly tables are no longer read)
+    GB::init(gs, tid, NTH);
+    __syncthreads();
+    float* sWf = reinterpret_cast<float*>(sU);
     if (row < N) {
-        const int kk = mykk[0];
-        const double pv = (double)sPVk[kk];
-        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < NPW; ++j)
+            if (part * NPW + j < NP) sWf[(fld * NP + part * NPW + j) * N + row] = (float)A64[j];
 #pragma unroll
         for (int i = 0; i < NBW; ++i) {
             const int cb = wave * NBW + i;
-            if (cb <= F) {
-                const double x = (double)mB[0][i] / pv;
-                bad |= !isfinite(x);
-                sX[cb * N + kk] = x;
-                if (cb < F) st[(int64_t)cb * N + kk] = x;
-            }
+            if (cb <= F) sWf[(N + cb) * N + row] = (float)B64[i];
         }
-        if (!(fabs(pv) > 0.0) || !isfinite(pv)) sBad = 1;
+    }
+    __syncthreads();
+
+    // ---- float32 blocked Gauss-Jordan elimination on the matrix cores, every panel recorded
+    typename GB::tile acc[GB::TPW];
+    GB::load(acc, sWf, wave, lane);
+    GB::eliminate(acc, gs, wave, lane, recY, recPiv);
+
+    // ---- X_K and the first y_K: row kk of the solution sits in the row pivoted at step kk
+    double* sX = sU;
+    {
+        const int lc = lane & 15, g = lane >> 4;
+        bool bad = false, sing = false;
+#pragma unroll
+        for (int s = 0; s < GB::TPW; ++s) {
+            const int c = 16 * (wave + NW * s) + lc;
+            if (c < N || c >= NCOL) continue;
+#pragma unroll
+            for (int rt = 0; rt < GB::RT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * rt + GB::row_in_tile(g, v);
+                    if (r >= N) continue;
+                    const int kk = gs.rowstep[r];
+                    const double pv = (double)gs.pvk[kk];
+                    const double x = (double)GB::get(acc[s], rt, v) / pv;
+                    sing |= !(fabs(pv) > 0.0) || !isfinite(pv);
+                    bad |= !isfinite(x);
+                    sX[(c - N) * N + kk] = x;
+                }
+        }
+        if (sing) sBad = 1;
         else if (bad && sBad == 0) sBad = 2;
     }
     __syncthreads();
 
     // ---- float64 refinement of y_K: y += (recorded elimination)(r - A y), kSweeps times
     for (int sweep = 0; sweep < kSweeps; ++sweep) {
-        double acc = wave == RW ? r64 : 0.0;
+        double acc64 = wave == RW ? r64 : 0.0;
 #pragma unroll
         for (int j = 0; j < NPW; ++j)
-            if (part * NPW + j < NP) acc -= A64[j] * sX[F * N + fld * NP + part * NPW + j];
-        sPart[wave][lane] = row < N ? acc : 0.0;
+            if (part * NPW + j < NP) acc64 -= A64[j] * sX[F * N + fld * NP + part * NPW + j];
+        sPart[wave][lane] = row < N ? acc64 : 0.0;
         __syncthreads();
         if (wave == 0) {
             double v = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) v += sPart[w][lane];
-            v = gj_replay<N>(v, lane, recF, recPiv);
+            v = gj_blocked_replay<N, GB::ROWS>(v, lane, recY, recPiv);
             if (row < N) {
-                const int kk = mykk[0];
-                sX[F * N + kk] += v / (double)sPVk[kk];
+                const int kk = gs.rowstep[row];
+                sX[F * N + kk] += v / (double)gs.pvk[kk];
             }
         }
         __syncthreads();
     }
-    for (int t = tid; t < N; t += NTH) {
-        const double yv = sX[F * N + t];
-        st[(int64_t)F * N + t] = yv;
-        if (!isfinite(yv)) sBad = sBad ? sBad : 2;
-    }
+    const int bslot = slot - a.start;
+    double* st = a.store + (int64_t)bslot * ((F + 1) * N);
+    for (int t = tid; t < (F + 1) * N; t += NTH) st[t] = sX[t];
+    for (int t = tid; t < N; t += NTH)
+        if (!isfinite(sX[F * N + t])) sBad = sBad ? sBad : 2;
     __syncthreads();
     if (tid == 0 && sBad != 0) {
         a.status[e] = sBad == 1 ? HDG_ERR_SINGULAR_LOCAL : HDG_ERR_NONFINITE;
         a.flag[0] = 1;
     }
-    schur_rows<P, PF, false>(a, E, sh, ft, sX, tid, NTH);
+    schur_rows<P, PF, false>(a, E, sJB, ft, sX, tid, NTH);
 }
 
 bool mixed_bucket_supported(const Bucket& bk) { return bk.p >= 1 && bk.p <= 4 && bk.pf >= bk.p && bk.pf <= 5; }

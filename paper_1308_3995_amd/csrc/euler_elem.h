@@ -312,12 +312,13 @@ __device__ __forceinline__ void face_tables(const CondArgs& a, const ElemInfo* E
 
 // Skeleton rows (local face, field, mode) of
 //   S_K = D_K - C_K X_K,   g_K = r_lam,K - C_K y_K.
-// sX holds [X_K | y_K] column-major with N rows. The nth threads split the F x F entries:
+// sX holds [X_K | y_K] column-major with N rows, sJB the weighted trace-flux Jacobians in lambda
+// at the face points (the D_K blocks). The nth threads split the F x F entries:
 // thread t takes row t % F and every CH-th column from t / F, so consecutive threads store
 // consecutive rows of a skeleton block. With DBG the rows of C_K, D_K and r_lam,K are
 // written to the debug buffer instead.
 template <int P, int PF, bool DBG>
-__device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E, const ElemShared<P, PF>& sh,
+__device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E, const double (&sJB)[3][PF + 2][16],
                                            const FaceTables<P, PF>& ft, const double* sX, int tid, int nth) {
     constexpr int NP = n_modes(P);
     constexpr int N = 4 * NP;
@@ -326,7 +327,6 @@ __device__ __forceinline__ void schur_rows(const CondArgs& a, const ElemInfo* E,
     constexpr int NC = N + F + 1;
     const int CH = nth >= F ? nth / F : 1;
     const double alpha = a.alpha;
-    const auto& sJB = sh.sJB;
     for (int t = tid; t < F * CH; t += nth) {
         const int r = t % F, ch = t / F;
         const int lf = r / (4 * NPF), b = (r / NPF) % 4, k = r % NPF;

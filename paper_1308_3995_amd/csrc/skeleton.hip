@@ -16,6 +16,17 @@
 // host round trip per iteration; the host reads the flag once per cycle. Reductions
 // are two-stage and fixed-order (per-block partials, then a redundant reduction by the
 // consumer blocks), so results are deterministic.
+//
+// Polynomial preconditioning (on by default, degree 20): d Arnoldi steps on Khat from a fixed
+// pseudo-random start vector give the harmonic Ritz values, the roots of the degree-d GMRES
+// residual polynomial 1 - Khat p(Khat); flexible GMRES then runs on Khat p(Khat), one
+// application of p being d fused SpMV-plus-vector-update launches over a copy of Khat (float16
+// by default: the polynomial only needs to be a good preconditioner, the outer iteration keeps
+// its float64 operator). A first cycle that leaves the residual above 0.95 of its start drops the
+// polynomial; a later cycle that does not halve the residual builds a second level p2(B) on
+// B = Khat p1(Khat). Mixed precision wraps the inner solve (float32 Khat) in float64 iterative
+// refinement on the float64 K; a non-finite correction is dropped and the solve goes on
+// without the polynomial.
 #include <hip/hip_fp16.h>
 
 #include <cmath>

@@ -379,7 +379,7 @@ def test_c2_full_size_sampled(hdg):
 def test_graph_replays_match_direct_launches(hdg, c1_oracle):
     """The captured condensation sequence and GMRES cycles, replayed across several steps with
     eager work in between, give the same bits as direct launches (deterministic kernels; the
-    register-budget variants picked by the first call compute identical values)."""
+    kernel variants tuned by the first plan are reused by every later plan of the process)."""
     import os
     import torch
     case, step = c1_oracle
