@@ -469,6 +469,9 @@ def main():
                     help="workload of the adjoint + marking report, solved at one degree more ('' = none)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--condense-only", action="store_true",
+                    help="only run the condensation reports of --condense-configs, float64 and the mixed-precision "
+                         "tier (a short run for kernel counters; prints them as one JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -483,6 +486,12 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": n * 8, "bytes_written": n * 8, "launches": 3}))
+        return
+    if args.condense_only:
+        names = [c for c in args.condense_configs.split(",") if c]
+        print(json.dumps({"condensation": condensation_report(names, warmup=1, reps=2),
+                          "condensation_mixed": condensation_report(names, warmup=1, reps=2,
+                                                                    precision="mixed_condense")}))
         return
     import hdg_inputs as hi
     import paper_1308_3995_amd as hdg

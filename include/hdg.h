@@ -367,9 +367,8 @@ hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev,
 hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree, int32_t fp16_matrix);
 
 /* Profiling hook for benchmarks: when enabled, hdg_skeleton_solve launches its restart cycles
- * directly (not from captured graphs) and brackets its SpMV launches with HIP events on the
- * caller's stream (each launch of kernel 1; each run of kernel 0's launches that one application
- * of the polynomial issues back to back), accumulating per kernel the launch count, the summed
+ * directly (not from captured graphs) and brackets each of its SpMV launches with a pair of
+ * HIP events on the caller's stream, accumulating per kernel the launch count, the summed
  * event time and the algorithmic bytes of those launches. kernel 0: the polynomial
  * preconditioner's SpMV (matrix values, the source, the previous iterate for the second
  * factor of a complex pair, the output vector and the running p(Khat) v_j); kernel 1: the

@@ -27,6 +27,7 @@
 // B = Khat p1(Khat). Mixed precision wraps the inner solve (float32 Khat) in float64 iterative
 // refinement on the float64 K; a non-finite correction is dropped and the solve goes on
 // without the polynomial.
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 
 #include <cmath>
@@ -1154,7 +1155,9 @@ static bool poly_from_hessenberg(const std::vector<double>& Hc, int d, Poly& P) 
     return poly_from_roots(d, wr.data(), wi.data(), P);
 }
 
-// Kernel-time accounting of the benchmarks: launch pairs of events per cycle, per kernel class.
+// Kernel-time accounting of the benchmarks: every timed launch carries a start and a stop event
+// that the dispatch itself records around the kernel's execution (hipExtLaunchKernelGGL), so the
+// host's submission time between launches is not counted; per kernel class.
 struct TimedLaunch {
     int cls;          // 0: k_poly_op, 1: k_spmv_dots
     double bytes;     // algorithmic bytes of the launches between the event pair
@@ -1182,27 +1185,30 @@ struct Solver {
 // needs B src = Khat (p1(Khat) src): p1 is applied into z1, then one SpMV of z1 carries the
 // p2 factor's vector work on src (esrc); finally p1 is applied to p2's output y2.
 static void apply_poly(Plan& p, const GmArgs& a, const Solver& S, const Poly* poly, const double* in, double* out,
-                       hipStream_t s, TimedLaunch* tl) {
+                       hipStream_t s, std::vector<TimedLaunch>* tl) {
     const dim3 gp((a.nf + kPolyRowsPerBlock - 1) / kPolyRowsPerBlock), blk(kThreads);
     const double nval = (double)p.hat_values, n = (double)a.n;
     const int lv = poly->level - 1;
     auto buf = [&](int id) -> double* { return id == 0 ? const_cast<double*>(in) : S.pbuf[lv][id]; };
     auto launch = [&](int k, const double* src, const double* esrc, const double* base, double* o, double* y) {
         const PolyOp& op = poly->ops[k];
+        hipEvent_t e0 = tl ? p.t_events[2 * tl->size()] : nullptr, e1 = tl ? p.t_events[2 * tl->size() + 1] : nullptr;
+        const PolyOp* ops = S.ops[lv];
         if (poly->mat_bytes == 2)
-            hipLaunchKernelGGL((k_poly_op<__half>), gp, blk, 0, s, a, (const __half*)poly->mat, S.ops[lv], k, src,
-                               esrc, base, o, y);
+            hipExtLaunchKernelGGL((k_poly_op<__half>), gp, blk, 0, s, e0, e1, 0, a, (const __half*)poly->mat, ops, k,
+                                  src, esrc, base, o, y);
         else if (poly->mat_bytes == 4)
-            hipLaunchKernelGGL((k_poly_op<float>), gp, blk, 0, s, a, (const float*)poly->mat, S.ops[lv], k, src,
-                               esrc, base, o, y);
+            hipExtLaunchKernelGGL((k_poly_op<float>), gp, blk, 0, s, e0, e1, 0, a, (const float*)poly->mat, ops, k,
+                                  src, esrc, base, o, y);
         else
-            hipLaunchKernelGGL((k_poly_op<double>), gp, blk, 0, s, a, (const double*)poly->mat, S.ops[lv], k, src,
-                               esrc, base, o, y);
+            hipExtLaunchKernelGGL((k_poly_op<double>), gp, blk, 0, s, e0, e1, 0, a, (const double*)poly->mat, ops, k,
+                                  src, esrc, base, o, y);
         if (tl) {
-            tl->bytes += nval * poly->mat_bytes +
-                         n * 8.0 * (1.0 + (esrc ? 1.0 : 0.0) + (op.b0 != 0.0 ? 1.0 : 0.0) + (op.first ? 1.0 : 2.0) +
-                                    (op.wout ? 1.0 : 0.0));
-            tl->count += 1;
+            tl->push_back({0,
+                           nval * poly->mat_bytes +
+                               n * 8.0 * (1.0 + (esrc ? 1.0 : 0.0) + (op.b0 != 0.0 ? 1.0 : 0.0) +
+                                          (op.first ? 1.0 : 2.0) + (op.wout ? 1.0 : 0.0)),
+                           1});
         }
     };
     if (!poly->inner) {
@@ -1233,37 +1239,21 @@ static void launch_step(Plan& p, const GmArgs& a, const Solver& S, const VT* hat
         const dim3 g1(a.B1), g2(a.B2), blk(kThreads);
         const int j = C - 1;
         const double nval = (double)p.hat_values, n = (double)a.n;
-        auto ev = [&](int k) { return p.t_events[k]; };
-        auto mark_begin = [&]() {
-            if (tl) (void)hipEventRecord(ev(2 * (int)tl->size()), s);
-        };
-        auto mark_end = [&](int cls, double bytes) {
-            if (tl) {
-                (void)hipEventRecord(ev(2 * (int)tl->size() + 1), s);
-                tl->push_back({cls, bytes, 1});
-            }
+        // timed launches: start and stop events recorded by the dispatch itself
+        auto ev = [&](int k) { return tl ? p.t_events[2 * tl->size() + k] : nullptr; };
+        auto timed = [&](int cls, double bytes) {
+            if (tl) tl->push_back({cls, bytes, 1});
         };
         if (poly) {
             hipLaunchKernelGGL((k_vnorm<C>), g2, blk, 0, s, a, src);
             double* z = a.Z + (int64_t)j * a.n;
             const double* vj = a.V + (int64_t)j * a.n;
-            // the polynomial's launches run back to back: one event pair around all of them
-            if (tl) {
-                TimedLaunch run{0, 0.0, 0};
-                (void)hipEventRecord(ev(2 * (int)tl->size()), s);
-                apply_poly(p, a, S, poly, vj, z, s, &run);
-                (void)hipEventRecord(ev(2 * (int)tl->size() + 1), s);
-                tl->push_back(run);
-            } else {
-                apply_poly(p, a, S, poly, vj, z, s, nullptr);
-            }
-            mark_begin();
-            hipLaunchKernelGGL((k_spmv_dots<VT, C, true>), g1, blk, 0, s, a, hat, z);
-            mark_end(1, nval * sizeof(VT) + n * 8.0 * 2.0 + (double)(j + 1) * n * 8.0);
+            apply_poly(p, a, S, poly, vj, z, s, tl);
+            hipExtLaunchKernelGGL((k_spmv_dots<VT, C, true>), g1, blk, 0, s, ev(0), ev(1), 0, a, hat, (const double*)z);
+            timed(1, nval * sizeof(VT) + n * 8.0 * 2.0 + (double)(j + 1) * n * 8.0);
         } else {
-            mark_begin();
-            hipLaunchKernelGGL((k_spmv_dots<VT, C, false>), g1, blk, 0, s, a, hat, src);
-            mark_end(1, nval * sizeof(VT) + n * 8.0 * 3.0 + (double)j * n * 8.0);
+            hipExtLaunchKernelGGL((k_spmv_dots<VT, C, false>), g1, blk, 0, s, ev(0), ev(1), 0, a, hat, src);
+            timed(1, nval * sizeof(VT) + n * 8.0 * 3.0 + (double)j * n * 8.0);
         }
         hipLaunchKernelGGL(k_reduce_h, dim3(C < kMaxRestart ? C + 1 : C), blk, 0, s, a, a.P1, a.B1, C, j);
         hipLaunchKernelGGL((k_update_dots<C>), g2, blk, 0, s, a);
@@ -1359,7 +1349,8 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
                              bool* stalled = nullptr, double* stall_ratio = nullptr) {
     const int deg = poly ? poly->degree : 1;
     if (stalled) *stalled = false;
-    const int per_cycle_events = 2 * m * 2;
+    const int per_step = poly ? poly_launches(poly) + 1 : 1;   // timed launches per Arnoldi step
+    const int per_cycle_events = 2 * m * per_step;
     if (p.timing && (int)p.t_events.size() < per_cycle_events) {
         p.t_events.resize(per_cycle_events, nullptr);
         for (auto& e : p.t_events)
@@ -1424,8 +1415,7 @@ static hdg_status gmres_khat(Plan& p, Solver& S, const VT* hat, const double* r0
         res = sc[SC_RES];
         if (p.timing) {
             // launches that did work: those of steps 0..jd-1 (later ones saw the converged flag)
-            const size_t per_step = poly ? 2 : 1;
-            const size_t worked = std::min(tl.size(), (size_t)std::min(steps, jd) * per_step);
+            const size_t worked = std::min(tl.size(), (size_t)std::min(steps, jd) * (size_t)per_step);
             for (size_t k = 0; k < worked; ++k) {
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, p.t_events[2 * k], p.t_events[2 * k + 1]));
