@@ -181,6 +181,26 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
                                  int32_t* elem_status_dev, double* res_norm_host,
                                  hipStream_t stream);
 
+/* Condensation of several independent cases at once (Sec. 3.4: the static condensation is
+ * element by element, so the elements of different cases can share launches; for serving).
+ * Equivalent to hdg_assemble_condense(plans[i], w_dev[i], q_dev ? q_dev[i] : NULL, lam_dev[i],
+ * bsr_values_dev[i], rhs_dev[i], local_store_dev[i], workspace_dev[i], NULL, NULL, stream) for
+ * every i < n, with bit-identical outputs. Plans whose kernel variants are already picked (any
+ * earlier condensation in the process with the same bucket shapes) that are Euler, without shock
+ * capturing and with float64 condensation are condensed together: one launch per (element
+ * degree, face degree, kernel variant) over the elements of up to 8 plans, then each plan's face
+ * sums. The other plans (Navier-Stokes, HDG_MIXED_CONDENSE, shock capturing, a first call) are
+ * condensed one by one within the call. All work is enqueued on `stream`; nothing is captured in
+ * a graph. The plans must be distinct and live on one device; their buffers must not overlap.
+ * Arrays have n entries (q_dev may be NULL for Euler plans). batched_out (optional): the number of
+ * plans condensed together. Errors: HDG_ERR_INVALID_ARG for n < 0, null arrays or entries, a
+ * repeated plan or plans on different devices; otherwise as hdg_assemble_condense. */
+hdg_status hdg_assemble_condense_batch(int32_t n, hdg_plan* const* plans, const double* const* w_dev,
+                                       const double* const* q_dev, const double* const* lam_dev,
+                                       double* const* bsr_values_dev, double* const* rhs_dev,
+                                       void* const* local_store_dev, void* const* workspace_dev,
+                                       int32_t* batched_out, hipStream_t stream);
+
 /* Skeleton solve K dLambda = E (Sec. 3.4 eq. hybridsystem): restarted GMRES(restart)
  * with right block-Jacobi preconditioning on the face-diagonal blocks and classical
  * Gram-Schmidt (a second pass when the first one cancels), all in float64 (HDG_MIXED: inner

@@ -16,7 +16,7 @@ import numpy as np
 from ._lib import (HDG_EULER, HDG_FP64, HDG_MIXED, HDG_MIXED_CONDENSE, HDG_NS, HdgError, HdgParams,  # noqa: F401
                    HdgSizes, check, load)
 
-__all__ = ["load", "HDGPlan", "HdgError", "HDG_FP64", "HDG_MIXED"]
+__all__ = ["load", "HDGPlan", "HdgError", "HDG_FP64", "HDG_MIXED", "hdg_assemble_condense_batch"]
 
 
 def _vp(t) -> Optional[C.c_void_p]:
@@ -304,3 +304,23 @@ def hessenberg_eigenvalues(h):
     wr, wi = np.zeros(n), np.zeros(n)
     check(lib.hdg_debug_hessenberg_eigenvalues(n, h.ctypes.data, wr.ctypes.data, wi.ctypes.data))
     return wr + 1j * wi
+
+
+def hdg_assemble_condense_batch(plans, ws, lams, qs=None, stream=None) -> int:
+    """hdg_assemble_condense_batch over several plans (each with its own state w, lam and, for
+    Navier-Stokes, q; outputs in each plan's buffers). Returns the number of plans condensed
+    together."""
+    n = len(plans)
+    if not (len(ws) == len(lams) == n) or (qs is not None and len(qs) != n):
+        raise ValueError("hdg_assemble_condense_batch: one state per plan")
+    arr = C.c_void_p * max(1, n)
+    def ptrs(ts):
+        return arr(*[None if t is None else t.data_ptr() for t in ts])
+    out = C.c_int32(0)
+    lib = load()
+    check(lib.hdg_assemble_condense_batch(
+        n, arr(*[p.handle.value for p in plans]), ptrs(ws),
+        ptrs(qs) if qs is not None else None, ptrs(lams), ptrs([p.bsr for p in plans]),
+        ptrs([p.rhs for p in plans]), ptrs([p.store for p in plans]), ptrs([p.ws for p in plans]),
+        C.byref(out), _stream(stream)))
+    return out.value

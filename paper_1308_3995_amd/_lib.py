@@ -18,7 +18,7 @@ HDG_EULER, HDG_NS = 0, 1
 HDG_FP64, HDG_MIXED, HDG_MIXED_CONDENSE = 0, 1, 2
 
 EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_pattern", "hdg_assemble_condense",
-           "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
+           "hdg_assemble_condense_batch", "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
            "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_set_cfl", "hdg_residual_norm", "hdg_apply_update",
            "hdg_cfl_schedule", "hdg_pseudo_transient_solve", "hdg_skeleton_transpose", "hdg_adjoint_rhs",
            "hdg_adjoint_local", "hdg_mark_elements", "hdg_mark_elements_noalloc", "hdg_set_poly_degree", "hdg_debug_hessenberg_eigenvalues",
@@ -72,6 +72,7 @@ def load(path: str = LIB_PATH):
     lib.hdg_plan_faces.argtypes = [vp, vp, vp, vp]
     lib.hdg_plan_pattern.argtypes = [vp, vp, vp, vp]
     lib.hdg_assemble_condense.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, P(dbl), vp]
+    lib.hdg_assemble_condense_batch.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, P(C.c_int32), vp]
     lib.hdg_skeleton_solve.argtypes = [vp, vp, vp, vp, dbl, i32, i32, vp, vp, P(i32), P(dbl)]
     lib.hdg_back_substitute.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_debug_element_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32)]

@@ -278,6 +278,76 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
     return HDG_OK;
 }
 
+hdg_status hdg_assemble_condense_batch(int32_t n, hdg_plan* const* plans, const double* const* w_dev,
+                                       const double* const* q_dev, const double* const* lam_dev,
+                                       double* const* bsr_values_dev, double* const* rhs_dev,
+                                       void* const* local_store_dev, void* const* workspace_dev, int32_t* batched_out,
+                                       hipStream_t stream) {
+    if (batched_out) *batched_out = 0;
+    if (n < 0 || (n > 0 && (!plans || !w_dev || !lam_dev || !bsr_values_dev || !rhs_dev || !local_store_dev ||
+                            !workspace_dev))) {
+        set_error("hdg_assemble_condense_batch: null argument or n < 0");
+        return HDG_ERR_INVALID_ARG;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i] || !w_dev[i] || !lam_dev[i] || !bsr_values_dev[i] || !rhs_dev[i] || !local_store_dev[i] ||
+            !workspace_dev[i]) {
+            set_error("hdg_assemble_condense_batch: null entry");
+            return HDG_ERR_INVALID_ARG;
+        }
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) {
+                set_error("hdg_assemble_condense_batch: a plan appears twice");
+                return HDG_ERR_INVALID_ARG;
+            }
+        if (plans[i]->p.device != plans[0]->p.device) {
+            set_error("hdg_assemble_condense_batch: the plans live on different devices");
+            return HDG_ERR_INVALID_ARG;
+        }
+    }
+    if (n == 0) return HDG_OK;
+    CHECK_HIP(hipSetDevice(plans[0]->p.device));
+    // plans that cannot join the batch (first call, Navier-Stokes, shock capturing, the mixed-precision
+    // condensation) are condensed one by one
+    std::vector<int> joined;
+    for (int i = 0; i < n; ++i) {
+        Plan& p = plans[i]->p;
+        bool ok;
+        {
+            std::lock_guard<std::mutex> lock(p.cache_mu);
+            ok = condense_batchable(p);
+        }
+        if (ok) {
+            joined.push_back(i);
+            continue;
+        }
+        const hdg_status st = hdg_assemble_condense(plans[i], w_dev[i], q_dev ? q_dev[i] : nullptr, lam_dev[i],
+                                                    bsr_values_dev[i], rhs_dev[i], local_store_dev[i],
+                                                    workspace_dev[i], nullptr, nullptr, stream);
+        if (st != HDG_OK) return st;
+    }
+    if (joined.empty()) return HDG_OK;
+    std::vector<CondenseBatchItem> items;
+    for (int i : joined)
+        items.push_back({&plans[i]->p, w_dev[i], lam_dev[i], bsr_values_dev[i], rhs_dev[i],
+                         (double*)local_store_dev[i], (char*)workspace_dev[i]});
+    // the plans' caches (kernel variants) stay fixed while the batch is enqueued; locks in address order
+    std::vector<std::mutex*> locks;
+    for (const CondenseBatchItem& it : items) locks.push_back(&const_cast<Plan*>(it.p)->cache_mu);
+    std::sort(locks.begin(), locks.end());
+    for (std::mutex* m : locks) m->lock();
+    int launches = 0;
+    const hipError_t e = launch_condense_batch(items, &launches, stream);
+    for (auto m = locks.rbegin(); m != locks.rend(); ++m) (*m)->unlock();
+    if (e == hipErrorInvalidValue) {
+        set_error("hdg_assemble_condense_batch: element degree or face degree outside the built kernels (1..5)");
+        return HDG_ERR_INVALID_ARG;
+    }
+    CHECK_HIP(e);
+    if (batched_out) *batched_out = (int32_t)items.size();
+    return HDG_OK;
+}
+
 hdg_status hdg_skeleton_solve(hdg_plan* plan, const double* bsr_values_dev, const double* rhs_dev, double* dlambda_dev,
                               double rtol, int32_t restart, int32_t max_iter, void* workspace_dev, hipStream_t stream,
                               int32_t* iters_out, double* relres_out) {

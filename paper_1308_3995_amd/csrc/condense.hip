@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "euler_elem.h"
@@ -27,15 +28,15 @@ namespace hdg {
 
 // MINW is the register budget's target in waves per SIMD (4: 128 VGPRs, 2: 256); GJB selects the
 // elimination: the blocked matrix-core Gauss-Jordan (gj_blocked.h) or the register-resident
-// one with one pivot column per step (gj.h). All four are built and the fastest per bucket is
-// picked by timing on the plan's first call.
+// one with one pivot column per step (gj.h). All four run as k_condense_euler_batch (for one plan
+// or several) and the fastest per bucket shape is picked by timing; k_condense_euler serves the
+// inspection (DBG) and shock-capturing (SC) instantiations.
 //
 // LDS: one region serves the phases in turn: the point data (ElemShared) and the staged
 // reference tables during assembly, then (blocked elimination) the augmented system
 // [A_K | B_K | r_K] staged column-major, then [X_K | y_K] for the skeleton rows.
 template <int P, int PF, bool DBG, int MINW, bool SC, bool GJB>
-__global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
-void k_condense_euler(CondArgs a) {
+__device__ __forceinline__ void condense_euler_element(const CondArgs& a, int block) {
     constexpr int NP = n_modes(P);
     constexpr int N = 4 * NP;
     constexpr int NPF = PF + 1;
@@ -62,7 +63,7 @@ void k_condense_euler(CondArgs a) {
     __shared__ int sBad;
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int slot = a.start + blockIdx.x;
+    const int slot = a.start + block;
     if (DBG && slot != a.debug_slot) return;
     const ElemInfo* E = a.einfo + slot;
     const int e = E->elem;
@@ -245,6 +246,25 @@ void k_condense_euler(CondArgs a) {
     }
 }
 
+template <int P, int PF, bool DBG, int MINW, bool SC, bool GJB>
+__global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
+void k_condense_euler(CondArgs a) {
+    condense_euler_element<P, PF, DBG, MINW, SC, GJB>(a, blockIdx.x);
+}
+
+// The elements of one bucket shape from several plans in one launch (serving): block b condenses
+// element b - first[i] of item i, first[i] <= b < first[i + 1], with item i's arguments (a plan's
+// bucket and buffers). The same element code as k_condense_euler, so the results are identical.
+// The items travel by value in the kernel arguments (copied at launch).
+template <int P, int PF, int MINW, bool GJB>
+__global__ __launch_bounds__(64 * EulerShape<P>::NW) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
+void k_condense_euler_batch(CondBatch ba) {
+    const int b = (int)blockIdx.x;
+    int i = 0;   // the last item whose first block is <= b
+    while (i + 1 < ba.n && ba.first[i + 1] <= b) ++i;
+    condense_euler_element<P, PF, false, MINW, false, GJB>(ba.a[i], b - ba.first[i]);
+}
+
 // Sum the two diagonal contributions of every face in a fixed order and the two halves
 // of the condensed right-hand side.
 __global__ void k_diag_sum(int nf, const int64_t* face_off, const int64_t* diag_off, const int64_t* row_ptr,
@@ -298,6 +318,16 @@ __global__ __launch_bounds__(64) void k_backsub(const ElemInfo* einfo, int start
         }
 }
 
+template <int P, int PF>
+static hipError_t launch_batch_group(int variant, int blocks, const CondBatch& ba, hipStream_t s) {
+    const dim3 g(blocks), t(64 * EulerShape<P>::NW);
+    if (variant == 1) hipLaunchKernelGGL((k_condense_euler_batch<P, PF, 2, false>), g, t, 0, s, ba);
+    else if (variant == 2) hipLaunchKernelGGL((k_condense_euler_batch<P, PF, 4, true>), g, t, 0, s, ba);
+    else if (variant == 3) hipLaunchKernelGGL((k_condense_euler_batch<P, PF, 2, true>), g, t, 0, s, ba);
+    else hipLaunchKernelGGL((k_condense_euler_batch<P, PF, 4, false>), g, t, 0, s, ba);
+    return hipGetLastError();
+}
+
 // One launch per (degree, face-degree) bucket; 4, 8 or 16 waves per element (degree <= 3, 4, 5).
 // Variants: 0 / 1 register-resident elimination at 128 / 256 VGPRs, 2 / 3 blocked matrix-core
 // elimination at 128 / 256 VGPRs.
@@ -317,14 +347,15 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
             hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, true, false>), dim3(bk.count), dim3(nth), 0, s, a);
     } else if (dbg) {
         hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, false, false>), dim3(bk.count), dim3(nth), 0, s, a);
-    } else if (variant == 1) {
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, false, false>), dim3(bk.count), dim3(nth), 0, s, a);
-    } else if (variant == 2) {
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, false, true>), dim3(bk.count), dim3(nth), 0, s, a);
-    } else if (variant == 3) {
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, false, true>), dim3(bk.count), dim3(nth), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, false, false>), dim3(bk.count), dim3(nth), 0, s, a);
+        // the kernel of the batched condensation with one item: one plan alone and several plans
+        // together run the same machine code, so they give the same bits
+        CondBatch ba{};
+        ba.a[0] = a;
+        ba.first[0] = 0;
+        ba.first[1] = bk.count;
+        ba.n = 1;
+        return launch_batch_group<P, PF>(variant, bk.count, ba, s);
     }
     return hipGetLastError();
 }
@@ -416,10 +447,10 @@ static uint64_t variant_key(const Plan& p, const Bucket& bk) {
            (uint64_t)(p.prm.sc_eps0 > 0.0) << 12 | (uint64_t)p.ns << 13 | size_class << 16;
 }
 
-hipError_t launch_condense(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
-                           double* diag_part, double* g_part, double* res_elem, double* rl_part, double* store,
-                           int32_t* status, int32_t* flag, double* debug, int debug_slot, hipStream_t s) {
-    (void)q;
+// The kernel arguments of one plan and set of buffers (bucket fields set per launch).
+static CondArgs condense_args(const Plan& p, const double* w, const double* lam, double* bsr, double* diag_part,
+                              double* g_part, double* res_elem, double* rl_part, int32_t* status, int32_t* flag,
+                              double* debug, int debug_slot) {
     CondArgs a{};
     a.einfo = p.d_einfo;
     a.leg = p.d_tab + p.tix.leg;
@@ -446,6 +477,25 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
     a.cfl = p.prm.cfl;
     a.sc_eps0 = p.prm.sc_eps0;
     a.sc_beta = p.prm.sc_beta;
+    return a;
+}
+
+// Bucket fields of the arguments: the degree's reference tables, the bucket's first element
+// slot and its part of the local store.
+static void set_bucket_args(const Plan& p, const Bucket& bk, double* store, CondArgs& a) {
+    a.vphi = p.d_tab + p.tix.vol_phi[bk.p];
+    a.vgrad = p.d_tab + p.tix.vol_grad[bk.p];
+    a.vw = p.d_tab + p.tix.vol_w[bk.p];
+    a.fphi = p.d_tab + p.tix.face_phi[bk.p];
+    a.start = bk.start;
+    a.store = store + bk.store_off;
+}
+
+hipError_t launch_condense(Plan& p, const double* w, const double* q, const double* lam, double* bsr,
+                           double* diag_part, double* g_part, double* res_elem, double* rl_part, double* store,
+                           int32_t* status, int32_t* flag, double* debug, int debug_slot, hipStream_t s) {
+    (void)q;
+    CondArgs a = condense_args(p, w, lam, bsr, diag_part, g_part, res_elem, rl_part, status, flag, debug, debug_slot);
     for (const Bucket& bk : p.buckets)
         if (!bucket_supported(bk)) return hipErrorInvalidValue;
     // HDG_MIXED_CONDENSE: float32 elimination with float64 refinement of y_K for degree <= 4
@@ -487,6 +537,83 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// ---- condensation of several plans' elements in one launch per bucket shape (serving)
+
+static hipError_t dispatch_batch_group(int p, int pf, int variant, int blocks, const CondBatch& ba, hipStream_t s) {
+#define HDG_CASE(PP, FF) \
+    if (p == PP && pf == FF) return launch_batch_group<PP, FF>(variant, blocks, ba, s);
+    HDG_BUCKETS(HDG_CASE)
+#undef HDG_CASE
+    return hipErrorInvalidValue;
+}
+
+bool condense_batchable(Plan& p) {
+    if (p.ns || p.prm.sc_eps0 > 0.0 || p.prm.precision == HDG_MIXED_CONDENSE) return false;
+    for (const Bucket& bk : p.buckets)
+        if (!bucket_supported(bk)) return false;
+    if (!p.tuned) {
+        // a plan's first call: its variants come from the process-wide choice if every bucket
+        // shape has one (no timing needed); otherwise it is condensed alone, which times them
+        std::vector<int> v(p.buckets.size());
+        std::lock_guard<std::mutex> g(g_variant_mu);
+        for (size_t b = 0; b < p.buckets.size(); ++b) {
+            const auto it = g_variant.find(variant_key(p, p.buckets[b]));
+            if (it == g_variant.end()) return false;
+            v[b] = it->second;
+        }
+        p.variant = v;
+        p.tuned = true;
+    }
+    return p.variant.size() == p.buckets.size();
+}
+
+hipError_t launch_condense_batch(const std::vector<CondenseBatchItem>& items, int* launches, hipStream_t s) {
+    // group the buckets of every item by (degree, face degree, kernel variant), in item order
+    std::map<std::tuple<int, int, int>, std::vector<std::pair<int, int>>> groups;
+    for (int i = 0; i < (int)items.size(); ++i) {
+        const Plan& p = *items[i].p;
+        for (int b = 0; b < (int)p.buckets.size(); ++b)
+            groups[{p.buckets[b].p, p.buckets[b].pf, p.variant[b]}].push_back({i, b});
+    }
+    hipError_t e = hipSuccess;
+    for (const CondenseBatchItem& it : items) {
+        const Plan& p = *it.p;
+        int32_t* status = (int32_t*)(it.ws + p.ws_status);
+        if (e == hipSuccess) e = launch_clear_status(p, status, status + p.ne, s);
+    }
+    int nl = 0;
+    for (const auto& g : groups) {
+        const auto& ents = g.second;
+        for (size_t k0 = 0; k0 < ents.size() && e == hipSuccess; k0 += kCondBatch) {
+            CondBatch ba{};
+            int blocks = 0;
+            ba.n = (int)std::min<size_t>(kCondBatch, ents.size() - k0);
+            for (int k = 0; k < ba.n; ++k) {
+                const CondenseBatchItem& it = items[ents[k0 + k].first];
+                const Plan& p = *it.p;
+                const Bucket& bk = p.buckets[ents[k0 + k].second];
+                int32_t* status = (int32_t*)(it.ws + p.ws_status);
+                ba.a[k] = condense_args(p, it.w, it.lam, it.bsr, (double*)(it.ws + p.ws_diag_part),
+                                        (double*)(it.ws + p.ws_g_part), (double*)(it.ws + p.ws_res_elem),
+                                        (double*)(it.ws + p.ws_rl_part), status, status + p.ne, nullptr, -1);
+                set_bucket_args(p, bk, it.store, ba.a[k]);
+                ba.first[k] = blocks;
+                blocks += bk.count;
+            }
+            ba.first[ba.n] = blocks;
+            e = dispatch_batch_group(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), blocks, ba, s);
+            ++nl;
+        }
+    }
+    for (const CondenseBatchItem& it : items) {
+        const Plan& p = *it.p;
+        if (e == hipSuccess)
+            e = launch_diag_sum(p, (double*)(it.ws + p.ws_diag_part), (double*)(it.ws + p.ws_g_part), it.bsr, it.rhs, s);
+    }
+    if (launches) *launches = nl;
+    return e;
 }
 
 hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double* g_part, double* bsr, double* rhs,

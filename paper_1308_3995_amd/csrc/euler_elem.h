@@ -477,6 +477,16 @@ struct EulerShape {
 };
 
 
+// Up to kCondBatch (plan, bucket) items of one bucket shape condensed in one launch; the table
+// travels by value in the kernel arguments.
+constexpr int kCondBatch = 8;
+struct CondBatch {
+    CondArgs a[kCondBatch];
+    int first[kCondBatch + 1];   // first block of every item, then the total
+    int n;
+};
+static_assert(sizeof(CondBatch) <= 4000, "the batch table fits the kernel arguments");
+
 // Mixed-precision condensation of the Euler buckets of degree <= 4 (condense_mixed.hip): float32
 // elimination, float64 refinement of y_K; returns hipErrorInvalidValue for other buckets.
 hipError_t dispatch_condense_mixed(const Plan& p, const Bucket& bk, const CondArgs& a, hipStream_t s);

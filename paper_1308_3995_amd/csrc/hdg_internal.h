@@ -213,6 +213,24 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
                            double* store, int32_t* status, int32_t* flag, double* debug, int debug_slot,
                            hipStream_t s);
 hipError_t launch_clear_status(const Plan& p, int32_t* status, int32_t* flag, hipStream_t s);
+// One plan of a batched condensation and its buffers (ws: the plan's workspace).
+struct CondenseBatchItem {
+    const Plan* p;
+    const double* w;
+    const double* lam;
+    double* bsr;
+    double* rhs;
+    double* store;
+    char* ws;
+};
+// A plan whose condensation can join a batch: Euler, float64 condensation, no shock capturing,
+// its kernel variants picked (a plan's first call takes them from the process-wide choice when
+// every bucket shape has one). Call with the plan's lock held.
+bool condense_batchable(Plan& p);
+// Condenses every item (all batchable) with one launch per (degree, face degree, kernel variant)
+// and up to kCondBatch items, then sums each plan's face diagonals; `launches` gets the number of
+// condensation launches.
+hipError_t launch_condense_batch(const std::vector<CondenseBatchItem>& items, int* launches, hipStream_t s);
 hipError_t launch_diag_sum(const Plan& p, const double* diag_part, const double* g_part, double* bsr,
                            double* rhs, hipStream_t s);
 hipError_t launch_back_substitute(const Plan& p, const double* store, const double* dlam, double* dw,

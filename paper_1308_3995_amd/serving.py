@@ -7,8 +7,9 @@ device footprint (skeleton matrix, local store, workspace and state, from hdg_pl
 fits in the HBM budget next to the cases already on the device. Each admitted case keeps its plan, state and
 matrices resident and runs one full Newton step (hdg_assemble_condense,
 hdg_skeleton_solve, hdg_back_substitute) on its own HIP stream from its own host thread,
-so the kernels of concurrent cases overlap on the GPU. When a case finishes, its slot and
-memory are released and waiting requests are admitted. Latency is completion minus
+so the kernels of concurrent cases overlap on the GPU; the condensations of concurrent Euler
+cases are gathered into batched calls (one launch per bucket shape over all of their elements).
+When a case finishes, its slot and memory are released and waiting requests are admitted. Latency is completion minus
 arrival. All device work is deterministic (fixed-order reductions), so a case's result
 does not depend on what else is running.
 """
@@ -61,6 +62,7 @@ class ServeStats:
     wall_s: float = 0.0
     max_concurrent: int = 0
     max_bytes_in_use: int = 0
+    condense_batches: dict = field(default_factory=dict)   # batched condensation calls and their cases
 
     def summary(self) -> dict:
         # latency percentiles over every request, failed ones included (a failure is a
@@ -87,13 +89,85 @@ class ServeStats:
                 "elements_per_s": ne / self.wall_s if self.wall_s > 0 else 0.0,
                 "skeleton_dof_per_s": nd / self.wall_s if self.wall_s > 0 else 0.0,
                 "wall_s": self.wall_s, "max_concurrent": self.max_concurrent,
-                "max_bytes_in_use": self.max_bytes_in_use}
+                "max_bytes_in_use": self.max_bytes_in_use, "condense_batches": self.condense_batches}
+
+
+class _CondenseBatcher:
+    """Issues the condensation of admitted Euler cases as batched library calls
+    (hdg_assemble_condense_batch) on a stream of its own: a case hands over its plan and state
+    and waits; the batcher takes every pending case (up to max_items), makes its stream wait for
+    their inputs, condenses them with one call (one launch per bucket shape for all of them) and
+    records an event that each case's stream then waits for. The outputs are bit-identical to the
+    case's own hdg_assemble_condense. If a batched call fails, its cases are condensed one by one so
+    that a failure stays with its own case."""
+
+    def __init__(self, device: int, max_items: int = 8):
+        import torch
+        self.stream = torch.cuda.Stream(device=device)
+        self.max_items = max_items
+        self.calls = 0          # batched library calls
+        self.cases = 0          # cases that went through the batcher
+        self.joined = 0         # cases condensed together (the rest one by one within a call)
+        self._cv = threading.Condition()
+        self._pending = []
+        self._stop = False
+        self._thread = threading.Thread(target=self._loop, daemon=True)
+        self._thread.start()
+
+    def condense(self, plan, w, lam, case_stream):
+        import torch
+        ready = torch.cuda.Event()
+        ready.record(case_stream)
+        item = {"plan": plan, "w": w, "lam": lam, "ready": ready, "done": threading.Event(), "event": None,
+                "error": None}
+        with self._cv:
+            self._pending.append(item)
+            self._cv.notify()
+        item["done"].wait()
+        if item["error"] is not None:
+            raise item["error"]
+        case_stream.wait_event(item["event"])
+
+    def _loop(self):
+        import torch
+        from . import hdg_assemble_condense_batch
+        while True:
+            with self._cv:
+                while not self._pending and not self._stop:
+                    self._cv.wait()
+                if not self._pending:
+                    return
+                batch, self._pending = self._pending[: self.max_items], self._pending[self.max_items:]
+            for it in batch:
+                self.stream.wait_event(it["ready"])
+            try:
+                self.joined += hdg_assemble_condense_batch([it["plan"] for it in batch], [it["w"] for it in batch],
+                                                           [it["lam"] for it in batch], stream=self.stream)
+            except Exception:
+                for it in batch:     # isolate the failing case
+                    try:
+                        it["plan"].hdg_assemble_condense(it["w"], it["lam"], stream=self.stream)
+                    except Exception as exc:
+                        it["error"] = exc
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+            self.calls += 1
+            self.cases += len(batch)
+            for it in batch:
+                it["event"] = ev
+                it["done"].set()
+
+    def close(self):
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        self._thread.join()
 
 
 class ServingEngine:
     def __init__(self, max_slots: int = 8, hbm_budget_bytes: Optional[int] = None, precision: str = "mixed",
                  restart: int = 30, max_iter: int = 20000, keep_results: bool = False, device: int = 0,
-                 prep_threads: int = 2, poly_degree: Optional[int] = None):
+                 prep_threads: int = 2, poly_degree: Optional[int] = None, batch_condense: bool = True):
         import torch
         self.max_slots = max_slots
         if hbm_budget_bytes is None:
@@ -107,6 +181,8 @@ class ServingEngine:
         self.device = device
         self.prep_threads = prep_threads   # host threads building plans ahead of admission
         self.poly_degree = poly_degree     # None: the library's default polynomial preconditioner
+        self.batch_condense = batch_condense   # Euler condensations of concurrent cases share launches
+        self._batcher = None
         self._lock = threading.Lock()
         self._cv = threading.Condition(self._lock)
         self._in_use = 0
@@ -139,7 +215,10 @@ class ServingEngine:
                 dq = torch.zeros_like(q) if q is not None else None
                 ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
                 ev[0].record(stream)
-                plan.hdg_assemble_condense(w, lam, q=q, stream=stream)
+                if self._batcher is not None and q is None:
+                    self._batcher.condense(plan, w, lam, stream)
+                else:
+                    plan.hdg_assemble_condense(w, lam, q=q, stream=stream)
                 ev[1].record(stream)
                 it, rr, status = plan.hdg_skeleton_solve(dlam, rtol=req.rtol, restart=self.restart,
                                                          max_iter=self.max_iter, stream=stream, raise_on_fail=False)
@@ -191,6 +270,7 @@ class ServingEngine:
                 plan.hdg_set_poly_degree(self.poly_degree)
             return plan, self.footprint(plan.sizes, plan.npmax, plan.ne, plan.physics == "ns")
 
+        self._batcher = _CondenseBatcher(self.device, self.max_slots) if self.batch_condense else None
         with ThreadPoolExecutor(max_workers=self.max_slots) as pool, \
                 ThreadPoolExecutor(max_workers=self.prep_threads) as prep:
             prepared = [prep.submit(prepare, r) for r in pending]
@@ -238,6 +318,11 @@ class ServingEngine:
             for f in futures:
                 f.result()
         stats.wall_s = time.perf_counter() - t0
+        if self._batcher is not None:
+            self._batcher.close()
+            stats.condense_batches = {"calls": self._batcher.calls, "cases": self._batcher.cases,
+                                      "condensed_together": self._batcher.joined}
+            self._batcher = None
         stats.results.sort(key=lambda r: r.index)
         return stats
 
