@@ -449,7 +449,7 @@ def main():
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--serving-requests", type=int, default=512,
                     help="requests of the Poisson serving stream to run (0 = skip; 512 = the full stream)")
-    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-slots", type=int, default=16)
     ap.add_argument("--serving-cfl", type=float, default=10.0,
                     help="pseudo-time CFL of every serving request (0: pure Newton steps)")
     ap.add_argument("--serving-newton-requests", type=int, default=128,
