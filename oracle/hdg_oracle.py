@@ -371,17 +371,22 @@ class Mesh:
 # Element-local residual (eq. hdg_ls1 .. hdg_cont), batched and complex-safe
 # ---------------------------------------------------------------------------
 
-def shock_viscosity(mesh: Mesh, e: int, W: np.ndarray) -> float:
+def shock_viscosity(mesh: Mesh, e: int, W: np.ndarray, Q: Optional[np.ndarray] = None) -> float:
     """Artificial viscosity of Sec. 3.2 (shock capturing): eps_K = eps_0 h~^(2 - beta) / |K|
     int_K d(w), with d(w) = sum over the components of |div f_c(w)| (the strong convective
     residual, by the chain rule from the flux Jacobians and the gradient of w_h) and
-    h~ = h_K / p_K, h_K the element's longest edge. W: (4, Np) real coefficients."""
+    h~ = h_K / p_K, h_K the element's longest edge. W: (4, Np) real coefficients. With Q
+    ((8, Np) real coefficients of q_h, row 4 d + a = d w_a / d x_d; Navier-Stokes) the gradient
+    in the strong residual is q_h, the viscous form of Sec. 3.2."""
     phys = mesh.phys
     if phys.sc_eps0 <= 0.0:
         return 0.0
     g = mesh.geom(e)
     wq = W @ g.phi                                   # (4, Q)
-    gw = np.einsum("an,dnq->dqa", W, g.dphi)         # (2, Q, 4) physical gradient
+    if Q is None:
+        gw = np.einsum("an,dnq->dqa", W, g.dphi)     # (2, Q, 4) physical gradient
+    else:
+        gw = (Q @ g.phi).T.reshape(-1, 2, 4).transpose(1, 0, 2)   # (2, Q, 4): q_h at the points
     d = np.zeros(wq.shape[1])
     for q in range(wq.shape[1]):
         div = (normal_flux_jacobian(wq[:, q], (1.0, 0.0), phys.gamma) @ gw[0, q]
@@ -412,12 +417,17 @@ def element_residual(mesh: Mesh, e: int, W, Q, lam_faces):
     # volume term: -(grad phi_i, F)
     Rw = -np.einsum("q,dnq,dbqa->ban", g.wq, g.dphi, F)
     if phys.sc_eps0 > 0.0:
-        # shock capturing, volume term only: (grad phi_i, eps grad w_h). eps is evaluated at the
+        # shock capturing, volume term only: (grad phi_i, eps grad w_h); Navier-Stokes takes the
+        # viscous form (grad phi_i, eps q_h) with eps from q_h as well. eps is evaluated at the
         # real part of the state: the Newton matrix holds it fixed (the paper leaves the
         # linearisation of the non-smooth |.| open)
-        eps = shock_viscosity(mesh, e, np.asarray(W[0]).real)
-        gw = np.einsum("ban,dnq->bdqa", W, g.dphi)
-        Rw = Rw + eps * np.einsum("q,dnq,bdqa->ban", g.wq, g.dphi, gw)
+        if ns:
+            eps = shock_viscosity(mesh, e, np.asarray(W[0]).real, np.asarray(Q[0]).real)
+            Rw = Rw + eps * np.einsum("q,dnq,bqda->ban", g.wq, g.dphi, qq)
+        else:
+            eps = shock_viscosity(mesh, e, np.asarray(W[0]).real)
+            gw = np.einsum("ban,dnq->bdqa", W, g.dphi)
+            Rw = Rw + eps * np.einsum("q,dnq,bdqa->ban", g.wq, g.dphi, gw)
     Rq = None
     if ns:
         # (tau, q) + (div tau, w)

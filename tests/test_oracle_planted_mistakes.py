@@ -13,6 +13,7 @@ import pytest
 from oracle import hdg_oracle as O
 import test_oracle_discretization as PD
 import test_oracle_physics as PP
+import test_oracle_shock as PS
 
 
 def _planted(func, edits):
@@ -51,6 +52,10 @@ CASES = [
     ("inward face normals", "element_residual",
      [("n = side.normal", "n = -side.normal")],
      lambda: PD.test_free_stream_preservation("euler")),
+    # Sec. 3.2, viscous form: the Navier-Stokes sensor reading grad w_h instead of q_h
+    ("sensor ignores q_h", "shock_viscosity",
+     [("if Q is None:", "if True:")],
+     PS.test_ns_viscosity_with_the_exact_gradient_equals_the_euler_form),
 ]
 
 
