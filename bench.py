@@ -10,7 +10,7 @@ GMRES on the skeleton (hdg_skeleton_solve) to a relative residual of 1e-10, and
 back-substitution (hdg_back_substitute). Both precision modes are timed; the reported
 `value` is condensed elements per second of full Newton steps of the mixed mode.
 Beside the step: assemble + condense alone on three workloads (`condensation`), and with shock
-capturing on the transonic hp workload (`condensation_shock_capturing`), the
+capturing on the transonic hp and the Navier-Stokes workloads (`condensation_shock_capturing`), the
 relaxed Newton iteration with the pseudo-time CFL schedule run to convergence
 (`pseudo_transient`), the hybridized adjoint at one degree more with the marking decisions
 (`adjoint`), a sample of the serving stream (`serving`) and the CPU oracle (`cpu_baseline`).
@@ -461,7 +461,7 @@ def main():
                     help="GMRES iterations per serving request before it counts as not converged")
     ap.add_argument("--condense-configs", default="c2,c3,c4",
                     help="workloads whose assemble + condense time is reported beside the step ('' = none)")
-    ap.add_argument("--shock-configs", default="c3",
+    ap.add_argument("--shock-configs", default="c3,c4",
                     help="workloads whose assemble + condense is also timed with shock capturing on ('' = none)")
     ap.add_argument("--newton-loop", default="c2",
                     help="workload of the pseudo-transient Newton iteration report ('' = none)")

@@ -91,11 +91,12 @@ typedef struct {
                              block, lambda_c = sum_e (|v.n| + c)|e| and lambda_v = (mu gamma /
                              (rho Pr)) sum_e |e|^2 / |K| at the element-mean state; the right-hand
                              side is unchanged. 0 = pure Newton; must be >= 0. */
-    double sc_eps0;       /* shock capturing (Sec. 3.2, Euler only): the volume term
+    double sc_eps0;       /* shock capturing (Sec. 3.2): the volume term
                              (grad phi, eps_K grad w_h) with eps_K = sc_eps0 (h_K / p_K)^(2 - sc_beta)
                              / |K| int_K sum_i |(div f_c(w_h))_i|, h_K the longest edge; eps_K is
                              held fixed in the Newton matrix. 0 = off (the paper: 0.2); >= 0.
-                             hdg_plan_create refuses sc_eps0 > 0 for Navier-Stokes. */
+                             Navier-Stokes takes the viscous form: q_h in place of grad w_h, in the
+                             term and in the strong residual. */
     double sc_beta;       /* shock-capturing exponent beta (the paper: 0) */
 } hdg_params;
 

@@ -178,7 +178,73 @@ struct NsArgs {
     double winf[4];
     double alpha, gamma, mu, prandtl;
     double cfl;         // pseudo-time CFL number (0: pure Newton)
+    double sc_eps0;     // shock-capturing factor (0: off) and exponent beta
+    double sc_beta;
 };
+
+// Shock capturing in the viscous form (Sec. 3.2): the element's artificial viscosity
+//   eps_K = eps_0 h~^(2 - beta) / |K| int_K d,   d = sum_a |(A_x(w) q_x + A_y(w) q_y)_a|,
+// the strong convective residual with q_h in place of grad w_h (A_d the convective flux
+// Jacobians at w_h), h~ = h_K / p_K with h_K the longest edge. The volume term
+// (grad phi_i, eps_K q_h) enters the flux as F_d -= eps_K q_d, with eps_K held fixed in the
+// Newton matrix (dF_d/dq_d gains -eps_K). All nth threads of the block call this; each sums its
+// volume points and the partial sums are added in a fixed order through red[nth] (LDS).
+// Returns 0 when the term is off.
+template <int P>
+__device__ double ns_sc_viscosity(const NsArgs& a, const ElemInfo* E, const double* sW, const double* sQ, double* red,
+                                  int tid, int nth) {
+    if (!(a.sc_eps0 > 0.0)) return 0.0;
+    constexpr int NP = n_modes(P), Q = n_vol_q(P);
+    double s = 0.0;
+    for (int qp = tid; qp < Q; qp += nth) {
+        double w[4], q[8];
+        for (int c = 0; c < 4; ++c) {
+            double t = 0.0;
+            for (int i = 0; i < NP; ++i) t += a.vphi[qp * NP + i] * sW[c * NP + i];
+            w[c] = t;
+        }
+        for (int c = 0; c < 8; ++c) {
+            double t = 0.0;
+            for (int i = 0; i < NP; ++i) t += a.vphi[qp * NP + i] * sQ[c * NP + i];
+            q[c] = t;
+        }
+        double Fc[2][4], Jw[2][4][4], Jq[2][4][8];
+        ns_flux_jac(w, q, a.gamma, 0.0, a.prandtl, Fc, Jw, Jq);   // mu = 0: the convective flux
+        double d = 0.0;
+        for (int r = 0; r < 4; ++r) {
+            double v = 0.0;
+            for (int c = 0; c < 4; ++c) v += Jw[0][r][c] * q[c] + Jw[1][r][c] * q[4 + c];
+            d += fabs(v);
+        }
+        s += a.vw[qp] * E->detj * d;
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0, area = 0.0;
+        for (int k = 0; k < nth; ++k) t += red[k];
+        for (int qp = 0; qp < Q; ++qp) area += a.vw[qp];
+        area *= E->detj;
+        const double h = fmax(E->len[0], fmax(E->len[1], E->len[2]));
+        red[0] = a.sc_eps0 * pow(h / (double)P, 2.0 - a.sc_beta) / area * t;
+    }
+    __syncthreads();
+    const double eps = red[0];
+    __syncthreads();
+    return eps;
+}
+
+// The volume term of the viscous shock capturing at one point (eps_K held fixed).
+__device__ __forceinline__ void ns_sc_apply(double eps, const double* q, double (*F)[4], double (*Jq)[4][8]) {
+    if (eps == 0.0) return;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            F[d][r] -= eps * q[4 * d + r];
+            Jq[d][r][4 * d + r] -= eps;
+        }
+}
 
 template <int P, int PF>
 struct NsDims {
@@ -243,6 +309,8 @@ __global__ __launch_bounds__(256) void k_ns_assemble(NsArgs a) {
         sLam[lf][fa][k] = (f >= 0 && k <= E->pe[lf]) ? a.lam[a.face_off[f] + fa * (E->pe[lf] + 1) + k] : 0.0;
     }
     __syncthreads();
+    __shared__ double sRed[NTH];
+    const double eps_sc = ns_sc_viscosity<P>(a, E, sW, sQ, sRed, tid, NTH);
     // volume point data
     for (int qp = tid; qp < Q; qp += NTH) {
         double w[4], q[8];
@@ -258,6 +326,7 @@ __global__ __launch_bounds__(256) void k_ns_assemble(NsArgs a) {
         }
         double Fv[2][4], Jw[2][4][4], Jq[2][4][8];
         ns_flux_jac(w, q, gm, mu, pr, Fv, Jw, Jq);
+        ns_sc_apply(eps_sc, q, Fv, Jq);
         const double sc = a.vw[qp] * detj;
         vw_[qp] = sc;
         for (int c = 0; c < 4; ++c) vwv[qp][c] = w[c];
@@ -509,6 +578,8 @@ __global__ __launch_bounds__(64) void k_ns_points(NsArgs a) {
         sLam[lf][fa][k] = (f >= 0 && k <= E->pe[lf]) ? a.lam[a.face_off[f] + fa * (E->pe[lf] + 1) + k] : 0.0;
     }
     __syncthreads();
+    __shared__ double sRed[64];
+    const double eps_sc = ns_sc_viscosity<P>(a, E, sW, sQ, sRed, tid, 64);
     for (int t = tid; t < Q + 24; t += 64) {
         if (t < Q) {
             const int qp = t;
@@ -525,6 +596,7 @@ __global__ __launch_bounds__(64) void k_ns_points(NsArgs a) {
             }
             double Fv[2][4], Jw[2][4][4], Jq[2][4][8];
             ns_flux_jac(w, q, gm, mu, pr, Fv, Jw, Jq);
+            ns_sc_apply(eps_sc, q, Fv, Jq);
             const double sc = a.vw[qp] * detj;
             pt.vw_[qp] = sc;
             for (int c = 0; c < 4; ++c) pt.vwv[qp][c] = w[c];
@@ -1190,6 +1262,8 @@ hipError_t launch_ns(Plan& p, const double* w, const double* q, const double* la
     a.mu = p.mu;
     a.prandtl = p.prm.prandtl;
     a.cfl = p.prm.cfl;
+    a.sc_eps0 = p.prm.sc_eps0;
+    a.sc_beta = p.prm.sc_beta;
     const bool tuning = only_slot < 0 && !p.tuned;
     const int nb = (int)p.buckets.size();
     std::vector<hipEvent_t> ev(tuning ? (size_t)nb * 8 : 0, nullptr);
@@ -1382,6 +1456,8 @@ hipError_t launch_ns_adjoint_local(Plan& p, const double* w, const double* q, co
     a.mu = p.mu;
     a.prandtl = p.prm.prandtl;
     a.cfl = p.prm.cfl;
+    a.sc_eps0 = p.prm.sc_eps0;
+    a.sc_beta = p.prm.sc_beta;
     NsAdjArgs b{};
     b.einfo = p.d_einfo;
     b.face_off = p.d_face_off;

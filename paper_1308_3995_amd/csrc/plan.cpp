@@ -266,10 +266,6 @@ hdg_status build_plan(Plan& P, const double* xy, int nv, const int32_t* tri, int
         set_error("invalid flow parameters");
         return HDG_ERR_INVALID_ARG;
     }
-    if (P.ns && prm.sc_eps0 > 0.0) {
-        set_error("shock capturing is built for the Euler equations");
-        return HDG_ERR_INVALID_ARG;
-    }
     P.pmax = 0;
     for (int e = 0; e < ne; ++e) {
         if (degree[e] < 1 || degree[e] > kMaxDegree) { set_error("degree outside 1..5 at element " + std::to_string(e)); return HDG_ERR_INVALID_ARG; }

@@ -281,3 +281,45 @@ def test_ns_mixed_skeleton_solve_meets_gate(hdg, which, degree):
         ref_w[e], ref_q[e] = O.unpack_local(step.mesh, e, step.du[e], case.W.shape[2])
     assert rel(dw.cpu().numpy(), ref_w) < 1e-6
     assert rel(dq.cpu().numpy(), ref_q) < 1e-6
+
+
+def test_ns_shock_capturing_matches_oracle(hdg):
+    """The viscous form of the shock capturing (Sec. 3.2, q_h in place of grad w_h) with a
+    pseudo-time step: element blocks (inspection path), local solutions, K and E (condensation
+    path), and the back-substitution."""
+    import torch
+    case = hi.make_case("ns", 3, [1, 2, 3], 0.8, 1.25, 8e-2, seed=43, reynolds=200.0)
+    case.sc_eps0 = 0.2
+    case.cfl = 5.0
+    _say("ns shock capturing")
+    step = O.newton_step(case)
+    mesh = step.mesh
+    eps = [O.shock_viscosity(mesh, e, case.W[e, :, :hi.n_modes(int(case.degree[e]))],
+                             case.Q[e, :, :hi.n_modes(int(case.degree[e]))]) for e in range(case.n_elements)]
+    _say(f"  eps_K max {max(eps):.3e}")
+    assert max(eps) > 1e-4        # the term is switched on
+    plan = hdg.HDGPlan.from_case(case)
+    w, q, lam = _state(plan, case)
+    for e in range(case.n_elements):
+        gb = plan.debug_element_blocks(e, w, lam, q)
+        for k, ref in (("A", step.blocks[e].A), ("r", step.blocks[e].r)):
+            tol = TOL if k == "A" else tol_resid(step.blocks[e].A)
+            assert rel(gb[k], ref) < tol, (e, k, rel(gb[k], ref))
+    plan.hdg_assemble_condense(w, lam, q=q)
+    torch.cuda.synchronize()
+    for e in range(case.n_elements):
+        X, y = plan.debug_local_solution(e)
+        c = step.cond[e]
+        assert rel(X, c.X) < TOL, (e, rel(X, c.X))
+        assert rel(y, c.y) < tol_resid(step.blocks[e].A), (e, rel(y, c.y))
+    assert rel(plan.skeleton_matrix_dense(), step.K.toarray()) < TOL
+    assert rel(plan.rhs.cpu().numpy(), step.E) < TOL
+    dl = torch.tensor(step.dlam, dtype=torch.float64, device=plan.device)
+    dw = torch.zeros_like(w)
+    dq = torch.zeros_like(q)
+    plan.hdg_back_substitute(dl, dw, dq)
+    rw, rq = np.zeros_like(case.W), np.zeros_like(case.Q)
+    for e in range(case.n_elements):
+        rw[e], rq[e] = O.unpack_local(step.mesh, e, step.du[e], case.W.shape[2])
+    assert rel(dw.cpu().numpy(), rw) < 1e-11
+    assert rel(dq.cpu().numpy(), rq) < 1e-11

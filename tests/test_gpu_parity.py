@@ -256,11 +256,21 @@ def test_shock_capturing_matches_oracle(hdg, which):
     assert rel(dw.cpu().numpy(), ref) < 1e-10
 
 
-def test_shock_capturing_is_refused_for_navier_stokes(hdg):
-    case = hi.make_case("ns", 3, [2, 3], 0.5, 1.0, 2e-2, seed=21, reynolds=200.0)
-    case.sc_eps0 = 0.2
-    with pytest.raises(hdg.HdgError):
-        hdg.HDGPlan.from_case(case)
+def test_shock_capturing_leaves_the_free_stream_steady(hdg):
+    """The shock-capturing term vanishes at a uniform free stream (d(w) = 0 there), for Euler and
+    for the viscous form of Navier-Stokes: E = 0 with the term switched on."""
+    import torch
+    for ph in ("euler", "ns"):
+        case = hi.make_case(ph, 4, [1, 2, 3], 0.5, 2.0, 0.0, seed=9, free_stream_only=True,
+                            reynolds=200.0 if ph == "ns" else 0.0)
+        case.sc_eps0 = 0.2
+        _say(f"shock capturing at the free stream ({ph})")
+        plan = hdg.HDGPlan.from_case(case)
+        w = torch.tensor(case.W, dtype=torch.float64, device=plan.device)
+        lam = torch.tensor(plan.pack_lambda(case.lam), dtype=torch.float64, device=plan.device)
+        q = torch.tensor(case.Q, dtype=torch.float64, device=plan.device) if case.Q is not None else None
+        nrm = plan.hdg_assemble_condense(w, lam, q=q, want_norm=True)
+        assert nrm < 1e-12, (ph, nrm)
 
 
 def test_free_stream_gives_zero_rhs(hdg):
