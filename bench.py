@@ -440,9 +440,9 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--poly-degree", type=int, default=20,
+    ap.add_argument("--poly-degree", type=int, default=30,
                     help="degree of the GMRES polynomial preconditioner (0: plain block-Jacobi GMRES)")
     ap.add_argument("--poly-fp32", action="store_true",
                     help="mixed mode: the polynomial's products read the float32 matrix, not a float16 copy")

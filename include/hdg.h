@@ -168,7 +168,7 @@ hdg_status hdg_plan_pattern(const hdg_plan* plan, int64_t* row_ptr_host, int32_t
  * elem_status_dev asks it to look (that needs a synchronisation).
  * Batching: one launch per (element degree, face degree) bucket. Euler buckets have four
  * kernel variants (blocked Gauss-Jordan on the matrix cores or the register-resident one, each
- * at a 128- and a 256-VGPR budget). The first call on a plan times the variants of every
+ * at a 128- and a 256-VGPR budget; with shock capturing on as well). The first call on a plan times the variants of every
  * bucket shape the process has not met yet, keeps the fastest, runs it and synchronises the
  * stream once; the choice is kept per (physics, degree, face degree, precision, shock
  * capturing, element-count class) for every later plan of the process, so plans agree bit for
@@ -206,7 +206,7 @@ hdg_status hdg_assemble_condense_batch(int32_t n, hdg_plan* const* plans, const 
  * with right block-Jacobi preconditioning on the face-diagonal blocks and classical
  * Gram-Schmidt (a second pass when the first one cancels), all in float64 (HDG_MIXED: inner
  * solves on a float32 preconditioned matrix inside float64 iterative refinement).
- * With a polynomial degree d >= 2 (hdg_set_poly_degree, default 20) the first restart cycle
+ * With a polynomial degree d >= 2 (hdg_set_poly_degree, default 30) the first restart cycle
  * has d steps; the harmonic Ritz values of its Hessenberg matrix are the roots of a GMRES
  * residual polynomial 1 - Khat p(Khat) of degree d (Khat = K M^-1, M the block-Jacobi
  * matrix), and the later cycles run GMRES on Khat p(Khat) (a flexible update keeps
@@ -378,8 +378,18 @@ hdg_status hdg_debug_element_blocks(hdg_plan* plan, int64_t element, const doubl
 hdg_status hdg_debug_local_solution(hdg_plan* plan, const void* local_store_dev, int64_t element,
                                     double* X_host, double* y_host, int32_t* n_out, int32_t* f_out);
 
+/* Inspection entry for tests: the float64 Euler condensation of this plan runs kernel variant
+ * `variant` on every bucket (Sec. 3.4, eq. hybridsystem, the same condensed system up to
+ * rounding): 0 / 1 the register-resident elimination at a 128- / 256-VGPR budget, 2 / 3 the
+ * blocked matrix-core elimination at 128 / 256; -1 returns to the timed choice (the
+ * process-wide one, see hdg_assemble_condense). A plan with a forced variant is condensed on
+ * its own by hdg_assemble_condense_batch. No effect on Navier-Stokes plans or on the buckets
+ * the mixed-precision condensation covers. Host only; takes effect at the next condensation.
+ * Errors: HDG_ERR_INVALID_ARG (null plan, variant outside -1..3). */
+hdg_status hdg_debug_condense_variant(hdg_plan* plan, int32_t variant);
+
 /* Degree d of the GMRES polynomial preconditioner of hdg_skeleton_solve on this plan
- * (0 or 1: plain block-Jacobi GMRES; at most 32; default 20) and, for HDG_MIXED, the storage
+ * (0 or 1: plain block-Jacobi GMRES; at most 32; default 30) and, for HDG_MIXED, the storage
  * of the preconditioned matrix its products read: fp16_matrix = 1 (default) a float16 copy,
  * 0 the float32 copy of the inner solve. The polynomial is only a preconditioner (the outer
  * Arnoldi products and the float64 refinement residual are unchanged), so its storage changes

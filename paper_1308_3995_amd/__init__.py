@@ -121,7 +121,7 @@ class HDGPlan:
                                              C.byref(nrm) if want_norm else None, _stream(stream)))
         return nrm.value if want_norm else None
 
-    def hdg_skeleton_solve(self, dlam, rtol: float = 1e-12, restart: int = 30, max_iter: int = 200000,
+    def hdg_skeleton_solve(self, dlam, rtol: float = 1e-12, restart: int = 20, max_iter: int = 200000,
                            stream=None, raise_on_fail: bool = True):
         it = C.c_int32(0)
         rr = C.c_double(0.0)
@@ -155,7 +155,7 @@ class HDGPlan:
 
     def hdg_pseudo_transient_solve(self, w, lam, q=None, c0: float = 1e6, c1: float = 1e3, n0: int = 4,
                                    max_steps: int = 20, rel_tol: float = 1e-10, abs_tol: float = 0.0,
-                                   gmres_rtol: float = 1e-8, restart: int = 30, max_iter: int = 200000,
+                                   gmres_rtol: float = 1e-8, restart: int = 20, max_iter: int = 200000,
                                    stream=None) -> dict:
         """Relaxed Newton iteration of the state (w, lam[, q]) in place; returns the report and
         the residual and CFL histories."""
@@ -192,7 +192,7 @@ class HDGPlan:
                                          _vp(wt), _vp(qt), _vp(eta), _vp(self.ws), _vp(elem_status),
                                          _stream(stream)))
 
-    def hdg_adjoint_solve(self, w, lam, fw, q=None, fq=None, rtol: float = 1e-12, restart: int = 30,
+    def hdg_adjoint_solve(self, w, lam, fw, q=None, fq=None, rtol: float = 1e-12, restart: int = 20,
                           max_iter: int = 200000, stream=None):
         """The whole hybridized adjoint at the state (w, lam[, q]) for the functional derivative
         (fw[, fq]): returns (Lambda~, W~, eta, gmres iterations), and Q~ as a fifth entry for
@@ -278,6 +278,10 @@ class HDGPlan:
                                                 C.byref(no), C.byref(fo)))
         n, f = no.value, fo.value
         return X[: n * f].reshape(f, n).T, y[:n].copy()
+
+    def debug_condense_variant(self, variant: int):
+        """Force condensation kernel variant 0..3 on every float64 Euler bucket (-1: the timed choice)."""
+        check(self.lib.hdg_debug_condense_variant(self.handle, int(variant)))
 
     def skeleton_matrix_dense(self, values=None) -> np.ndarray:
         """Dense copy of the assembled skeleton matrix, or of other values in its block pattern

@@ -18,7 +18,7 @@ HDG_EULER, HDG_NS = 0, 1
 HDG_FP64, HDG_MIXED, HDG_MIXED_CONDENSE = 0, 1, 2
 
 EXPORTS = ["hdg_plan_create", "hdg_plan_sizes", "hdg_plan_faces", "hdg_plan_pattern", "hdg_assemble_condense",
-           "hdg_assemble_condense_batch", "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution",
+           "hdg_assemble_condense_batch", "hdg_skeleton_solve", "hdg_back_substitute", "hdg_debug_element_blocks", "hdg_debug_local_solution", "hdg_debug_condense_variant",
            "hdg_set_kernel_timing", "hdg_kernel_timing", "hdg_set_cfl", "hdg_residual_norm", "hdg_apply_update",
            "hdg_cfl_schedule", "hdg_pseudo_transient_solve", "hdg_skeleton_transpose", "hdg_adjoint_rhs",
            "hdg_adjoint_local", "hdg_mark_elements", "hdg_mark_elements_noalloc", "hdg_set_poly_degree", "hdg_debug_hessenberg_eigenvalues",
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
     lib.hdg_back_substitute.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.hdg_debug_element_blocks.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(i32), P(i32)]
     lib.hdg_debug_local_solution.argtypes = [vp, vp, i64, vp, vp, P(i32), P(i32)]
+    lib.hdg_debug_condense_variant.argtypes = [vp, i32]
     lib.hdg_set_kernel_timing.argtypes = [vp, i32]
     lib.hdg_kernel_timing.argtypes = [vp, i32, P(i64), P(dbl), P(dbl), i32]
     lib.hdg_set_poly_degree.argtypes = [vp, i32, i32]

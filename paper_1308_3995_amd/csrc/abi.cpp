@@ -244,6 +244,7 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
             uint64_t cfl_bits;
             std::memcpy(&cfl_bits, &p.prm.cfl, 8);   // the CFL is a kernel argument baked into the graph
             key = (key ^ cfl_bits) * 1099511628211ull;
+            key = (key ^ (uint64_t)(p.forced_variant + 2)) * 1099511628211ull;   // and so is the variant
             hipGraphExec_t x = graph_find(p, key);
             if (!x) x = graph_capture(p, key, enqueue);
             if (x) {
@@ -806,6 +807,18 @@ hdg_status hdg_set_poly_degree(hdg_plan* plan, int32_t degree, int32_t fp16_matr
     }
     plan->p.poly_degree = degree;
     plan->p.poly_half = fp16_matrix;
+    return HDG_OK;
+}
+
+hdg_status hdg_debug_condense_variant(hdg_plan* plan, int32_t variant) {
+    if (!plan || variant < -1 || variant > 3) {
+        set_error("hdg_debug_condense_variant: null plan or variant outside -1..3");
+        return HDG_ERR_INVALID_ARG;
+    }
+    Plan& p = plan->p;
+    std::lock_guard<std::mutex> g(p.cache_mu);
+    p.forced_variant = variant;
+    p.tuned = false;   // the next call takes the forced variant, or the timed choice again
     return HDG_OK;
 }
 

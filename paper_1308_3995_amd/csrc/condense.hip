@@ -340,11 +340,13 @@ static hipError_t launch_bucket(const Plan& p, const Bucket& bk, CondArgs a, boo
     a.start = bk.start;
     constexpr int nth = 64 * EulerShape<P>::NW;
     if (a.sc_eps0 > 0.0) {
-        // shock capturing on: one kernel shape (every tuning variant launches it)
-        if (dbg)
-            hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, true, false>), dim3(bk.count), dim3(nth), 0, s, a);
-        else
-            hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, true, false>), dim3(bk.count), dim3(nth), 0, s, a);
+        // shock capturing on: the same four variants, instantiated with the viscosity terms
+        const dim3 g(bk.count), t(nth);
+        if (dbg) hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, true, false>), g, t, 0, s, a);
+        else if (variant == 1) hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, true, false>), g, t, 0, s, a);
+        else if (variant == 2) hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, true, true>), g, t, 0, s, a);
+        else if (variant == 3) hipLaunchKernelGGL((k_condense_euler<P, PF, false, 2, true, true>), g, t, 0, s, a);
+        else hipLaunchKernelGGL((k_condense_euler<P, PF, false, 4, true, false>), g, t, 0, s, a);
     } else if (dbg) {
         hipLaunchKernelGGL((k_condense_euler<P, PF, true, 4, false, false>), dim3(bk.count), dim3(nth), 0, s, a);
     } else {
@@ -500,7 +502,11 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
         if (!bucket_supported(bk)) return hipErrorInvalidValue;
     // HDG_MIXED_CONDENSE: float32 elimination with float64 refinement of y_K for degree <= 4
     const bool mixed = p.prm.precision == HDG_MIXED_CONDENSE;
-    if (!debug && !p.tuned) {
+    if (!debug && p.forced_variant >= 0) {
+        // inspection: every bucket runs the requested variant (no timing, no process-wide choice)
+        p.variant.assign(p.buckets.size(), p.forced_variant);
+        p.tuned = true;
+    } else if (!debug && !p.tuned) {
         const int nb = (int)p.buckets.size();
         p.variant.assign(nb, 0);
         std::vector<int> todo;
@@ -550,7 +556,7 @@ static hipError_t dispatch_batch_group(int p, int pf, int variant, int blocks, c
 }
 
 bool condense_batchable(Plan& p) {
-    if (p.ns || p.prm.sc_eps0 > 0.0 || p.prm.precision == HDG_MIXED_CONDENSE) return false;
+    if (p.ns || p.prm.sc_eps0 > 0.0 || p.prm.precision == HDG_MIXED_CONDENSE || p.forced_variant >= 0) return false;
     for (const Bucket& bk : p.buckets)
         if (!bucket_supported(bk)) return false;
     if (!p.tuned) {

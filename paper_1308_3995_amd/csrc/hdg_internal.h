@@ -153,7 +153,7 @@ struct Plan {
     double t_ms[2] = {0.0, 0.0}, t_bytes[2] = {0.0, 0.0};
     // degree of the GMRES polynomial preconditioner (< 2: plain block-Jacobi GMRES) and its
     // matrix storage in the mixed mode (1: float16 copy of Khat, 0: the float32 copy)
-    int poly_degree = 20;
+    int poly_degree = 30;
     int poly_half = 1;
     std::vector<hipEvent_t> t_events;
     // Captured launch sequences, replayed with hipGraphLaunch: GMRES restart cycles and the
@@ -167,6 +167,7 @@ struct Plan {
     // condensation: register-budget variant per bucket (chosen by timing on the first call)
     std::vector<int> variant;             // per bucket, -1 until tuned
     bool tuned = false;
+    int forced_variant = -1;              // inspection: >= 0 runs that variant on every bucket
 };
 
 // The captured graph of `key` (nullptr if none). Call with p.cache_mu held.

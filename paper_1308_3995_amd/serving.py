@@ -166,7 +166,7 @@ class _CondenseBatcher:
 
 class ServingEngine:
     def __init__(self, max_slots: int = 8, hbm_budget_bytes: Optional[int] = None, precision: str = "mixed",
-                 restart: int = 30, max_iter: int = 20000, keep_results: bool = False, device: int = 0,
+                 restart: int = 20, max_iter: int = 20000, keep_results: bool = False, device: int = 0,
                  prep_threads: int = 2, poly_degree: Optional[int] = None, batch_condense: bool = True):
         import torch
         self.max_slots = max_slots
