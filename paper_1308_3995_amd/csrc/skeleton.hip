@@ -719,16 +719,21 @@ __global__ __launch_bounds__(kThreads) void k_update_dots(GmArgs a) {
 template <int CNT>
 __global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a, int j) {
     constexpr int cnt = CNT;
-    __shared__ double sh[8];
-    __shared__ double h[kMaxV];
+    static_assert(CNT <= kMaxRestart, "one accumulator per basis vector");
+    __shared__ double sh[4 * kMaxRestart];
+    __shared__ double h[kMaxRestart];
     if (a.scal[SC_DONE] != 0.0 || a.scal[SC_REORTH] == 0.0) return;
-    for (int i = 0; i < cnt; ++i) {
-        const double* Pi = a.P2 + (int64_t)i * a.B2;
-        double v = 0.0;
-        for (int b = threadIdx.x; b < a.B2; b += blockDim.x) v += Pi[b];
-        const double t = block_sum1(v, sh);
-        if (threadIdx.x == 0) h[i] = t;
+    // all cnt coefficients in one sweep over the partials (their loads in flight together),
+    // then one reduction of the cnt sums over the block
+    double acc[kMaxRestart];
+#pragma unroll
+    for (int i = 0; i < kMaxRestart; ++i) acc[i] = 0.0;
+    for (int b = threadIdx.x; b < a.B2; b += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < kMaxRestart; ++i)
+            if (i < cnt) acc[i] += a.P2[(int64_t)i * a.B2 + b];
     }
+    block_sum_vec(acc, cnt, h, 1, sh);
     __syncthreads();
     if (blockIdx.x == 0 && (int)threadIdx.x < cnt) {
         double* hc = a.H + (int64_t)j * kMaxV;
@@ -740,7 +745,7 @@ __global__ __launch_bounds__(kThreads) void k_update_norm(GmArgs a, int j) {
     for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
         double wv = a.w[k];
 #pragma unroll
-        for (int i = 0; i < kMaxV; ++i)
+        for (int i = 0; i < kMaxRestart; ++i)
             if (i < cnt) wv -= h[i] * a.V[(int64_t)i * a.n + k];
         a.w[k] = wv;
         nacc += wv * wv;
