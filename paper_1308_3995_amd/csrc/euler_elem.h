@@ -422,6 +422,9 @@ __device__ __forceinline__ void a_row_entries(const CondArgs& a, const ElemInfo*
         const double* ji = E->jinv;
         const double g00 = ji[0] * ji[0] + ji[1] * ji[1], g01 = ji[0] * ji[2] + ji[1] * ji[3];
         const double g11 = ji[2] * ji[2] + ji[3] * ji[3];
+        // kept rolled: unrolled beside the volume loop above, the reference gradients of every
+        // point would be loaded ahead of both and held in registers
+#pragma unroll 1
         for (int q = 0; q < Q; ++q) {
             const double wgt = eps * a.vw[q] * E->detj;
             const double a0 = sVg[q * NP + ii], a1 = sVg[(Q + q) * NP + ii];
@@ -457,6 +460,7 @@ __device__ __forceinline__ double r_entry(const CondArgs& a, const ElemInfo* E, 
         const double g00 = ji[0] * ji[0] + ji[1] * ji[1], g01 = ji[0] * ji[2] + ji[1] * ji[3];
         const double g11 = ji[2] * ji[2] + ji[3] * ji[3];
         double s = 0.0;
+#pragma unroll 1
         for (int q = 0; q < Q; ++q) {
             const double a0 = sVg[q * NP + ii], a1 = sVg[(Q + q) * NP + ii];
             s += a.vw[q] * ((g00 * a0 + g01 * a1) * scb[(q * 2) * 4 + fa] + (g01 * a0 + g11 * a1) * scb[(q * 2 + 1) * 4 + fa]);
