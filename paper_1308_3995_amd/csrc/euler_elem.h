@@ -390,6 +390,7 @@ __device__ __forceinline__ void a_row_entries(const CondArgs& a, const ElemInfo*
     constexpr int NP = n_modes(P), Q = n_vol_q(P), QF = PF + 2;
 #pragma unroll
     for (int j = 0; j < NPW; ++j) out[j] = 0.0;
+#pragma unroll 1
     for (int q = 0; q < Q; ++q) {
         const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
         const double s = -(g0 * sh.sK[q][0][fa * 4 + b] + g1 * sh.sK[q][1][fa * 4 + b]);
@@ -444,6 +445,7 @@ __device__ __forceinline__ double r_entry(const CondArgs& a, const ElemInfo* E, 
                                           const double* sVg, const double* sFp, const double* scb, int fa, int ii) {
     constexpr int NP = n_modes(P), Q = n_vol_q(P), QF = PF + 2;
     double v = 0.0;
+#pragma unroll 1
     for (int q = 0; q < Q; ++q) {
         const double g0 = sVg[q * NP + ii], g1 = sVg[(Q + q) * NP + ii];
         v += g0 * sh.sF[q][0][fa] + g1 * sh.sF[q][1][fa];
