@@ -166,9 +166,12 @@ hdg_status hdg_plan_pattern(const hdg_plan* plan, int64_t* row_ptr_host, int32_t
  * (optional): if non-NULL the call synchronises and returns ||E||_2. The call itself
  * returns HDG_ERR_SINGULAR_LOCAL or HDG_ERR_NONFINITE only when res_norm_host or
  * elem_status_dev asks it to look (that needs a synchronisation).
- * Batching: one launch per (element degree, face degree) bucket. Euler buckets have four
- * kernel variants (blocked Gauss-Jordan on the matrix cores or the register-resident one, each
- * at a 128- and a 256-VGPR budget; with shock capturing on as well). The first call on a plan times the variants of every
+ * Batching: one launch per (element degree, face degree) bucket; the Euler buckets run
+ * concurrently on the plan's side streams, forked from `stream` and joined back into it
+ * before the call's later work (the plan creates them at its first condensation). Euler
+ * buckets have four kernel variants (blocked Gauss-Jordan on the matrix cores or the
+ * register-resident one, each at a 128- and a 256-VGPR budget; with shock capturing on as
+ * well). The first call on a plan times the variants of every
  * bucket shape the process has not met yet, keeps the fastest, runs it and synchronises the
  * stream once; the choice is kept per (physics, degree, face degree, precision, shock
  * capturing, element-count class) for every later plan of the process, so plans agree bit for

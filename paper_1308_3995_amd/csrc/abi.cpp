@@ -212,6 +212,11 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
     int32_t* status = elem_status_dev ? elem_status_dev : (int32_t*)(ws + p.ws_status);
     int32_t* flag = (int32_t*)(ws + p.ws_status) + p.ne;
     CHECK_HIP(hipSetDevice(p.device));
+    if (!p.ns) {
+        // the side streams of the concurrent bucket launches, made before any capture
+        std::lock_guard<std::mutex> plan_lock(p.cache_mu);
+        ensure_side_streams(p);
+    }
     // the whole sequence: clear the status words, condense every bucket, sum the face diagonals
     auto enqueue = [&](hipStream_t q) -> hipError_t {
         hipError_t e = launch_clear_status(p, status, flag, q);

@@ -533,16 +533,69 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
         p.tuned = true;
         // the chosen variants run once more below, so the outputs come from them
     }
-    for (size_t b = 0; b < p.buckets.size(); ++b) {
+    // The buckets are independent (every element writes only its own slots), so outside the
+    // inspection path they run concurrently: forked from s onto the plan's side streams, the
+    // largest first, each to the lane with the least estimated work (elements x n^3), and joined
+    // back into s. The assignment is the same at every call.
+    const int nb = (int)p.buckets.size();
+    const bool fork = !debug && nb > 1 && p.fork_ev != nullptr;
+    std::vector<int> lane(nb, 0);
+    if (fork) {
+        std::vector<int> order(nb);
+        for (int b = 0; b < nb; ++b) order[b] = b;
+        auto cost = [&](int b) { const double n = 4.0 * n_modes(p.buckets[b].p); return p.buckets[b].count * n * n * n; };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+        double load[1 + Plan::kSideStreams] = {};
+        for (int b : order) {
+            int best = 0;
+            for (int l = 1; l <= Plan::kSideStreams; ++l)
+                if (load[l] < load[best]) best = l;
+            lane[b] = best;
+            load[best] += cost(b);
+        }
+        hipError_t e = hipEventRecord(p.fork_ev, s);
+        for (int i = 0; i < Plan::kSideStreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(p.side[i], p.fork_ev, 0);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t first = hipSuccess;
+    for (int b = 0; b < nb && first == hipSuccess; ++b) {
         const Bucket& bk = p.buckets[b];
         if (debug && !(debug_slot >= bk.start && debug_slot < bk.start + bk.count)) continue;
         a.store = store + bk.store_off;
-        const int v = debug || b >= p.variant.size() ? 0 : p.variant[b];
-        hipError_t e = !debug && mixed && mixed_bucket_supported(bk) ? dispatch_condense_mixed(p, bk, a, s)
-                                                                     : dispatch_condense(p, bk, a, debug != nullptr, v, s);
-        if (e != hipSuccess) return e;
+        const int v = debug || b >= (int)p.variant.size() ? 0 : p.variant[b];
+        const hipStream_t q = lane[b] == 0 ? s : p.side[lane[b] - 1];
+        first = !debug && mixed && mixed_bucket_supported(bk) ? dispatch_condense_mixed(p, bk, a, q)
+                                                              : dispatch_condense(p, bk, a, debug != nullptr, v, q);
     }
-    return hipSuccess;
+    if (fork) {
+        // always joined, also after a failed launch, so that a capture never ends with open branches
+        for (int i = 0; i < Plan::kSideStreams; ++i) {
+            hipError_t e = hipEventRecord(p.join_ev[i], p.side[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, p.join_ev[i], 0);
+            if (first == hipSuccess) first = e;
+        }
+    }
+    return first;
+}
+
+void ensure_side_streams(Plan& p) {
+    if (p.fork_ev) return;
+    bool ok = hipEventCreateWithFlags(&p.fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < Plan::kSideStreams && ok; ++i)
+        ok = hipStreamCreateWithFlags(&p.side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&p.join_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        // one stream for every bucket (the fork needs all of them)
+        (void)hipGetLastError();
+        for (int i = 0; i < Plan::kSideStreams; ++i) {
+            if (p.side[i]) (void)hipStreamDestroy(p.side[i]);
+            if (p.join_ev[i]) (void)hipEventDestroy(p.join_ev[i]);
+            p.side[i] = nullptr;
+            p.join_ev[i] = nullptr;
+        }
+        if (p.fork_ev) (void)hipEventDestroy(p.fork_ev);
+        p.fork_ev = nullptr;
+    }
 }
 
 // ---- condensation of several plans' elements in one launch per bucket shape (serving)

@@ -168,6 +168,12 @@ struct Plan {
     std::vector<int> variant;             // per bucket, -1 until tuned
     bool tuned = false;
     int forced_variant = -1;              // inspection: >= 0 runs that variant on every bucket
+    // condensation buckets run concurrently: side streams forked from the caller's stream and
+    // joined back into it by events (created before any capture, on the plan's device)
+    static constexpr int kSideStreams = 3;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kSideStreams] = {};
 };
 
 // The captured graph of `key` (nullptr if none). Call with p.cache_mu held.
@@ -214,6 +220,9 @@ hipError_t launch_condense(Plan& p, const double* w, const double* q, const doub
                            double* store, int32_t* status, int32_t* flag, double* debug, int debug_slot,
                            hipStream_t s);
 hipError_t launch_clear_status(const Plan& p, int32_t* status, int32_t* flag, hipStream_t s);
+// Creates the plan's side streams and fork/join events once (the plan's device current; call
+// outside any stream capture). On failure the condensation runs its buckets in one stream.
+void ensure_side_streams(Plan& p);
 // One plan of a batched condensation and its buffers (ws: the plan's workspace).
 struct CondenseBatchItem {
     const Plan* p;

@@ -615,6 +615,14 @@ void free_plan(Plan& P) {
     P.graphs.clear();
     if (P.capture_stream) (void)hipStreamDestroy(P.capture_stream);
     P.capture_stream = nullptr;
+    for (int i = 0; i < Plan::kSideStreams; ++i) {
+        if (P.side[i]) (void)hipStreamDestroy(P.side[i]);
+        if (P.join_ev[i]) (void)hipEventDestroy(P.join_ev[i]);
+        P.side[i] = nullptr;
+        P.join_ev[i] = nullptr;
+    }
+    if (P.fork_ev) (void)hipEventDestroy(P.fork_ev);
+    P.fork_ev = nullptr;
     void* ptrs[] = {P.d_einfo, P.d_tab, P.d_bproj, P.d_face_off, P.d_face_deg, P.d_row_ptr, P.d_col,
                     P.d_val_off, P.d_diag_off, P.d_hat_row_ptr, P.d_hat_col, P.d_hat_val_off, P.d_hat_src,
                     P.d_k_desc, P.d_hat_desc,
