@@ -194,8 +194,9 @@ hdg_status hdg_assemble_condense(hdg_plan* plan, const double* w_dev, const doub
  * capturing and with float64 condensation are condensed together: one launch per (element
  * degree, face degree, kernel variant) over the elements of up to 8 plans, then each plan's face
  * sums. The other plans (Navier-Stokes, HDG_MIXED_CONDENSE, shock capturing, a first call) are
- * condensed one by one within the call. All work is enqueued on `stream`; nothing is captured in
- * a graph. The plans must be distinct and live on one device; their buffers must not overlap.
+ * condensed one by one within the call. All work is ordered on `stream` (the launches run
+ * concurrently on the first joined plan's side streams, forked from and joined back into
+ * `stream`); nothing is captured in a graph. The plans must be distinct and live on one device; their buffers must not overlap.
  * Arrays have n entries (q_dev may be NULL for Euler plans). batched_out (optional): the number of
  * plans condensed together. Errors: HDG_ERR_INVALID_ARG for n < 0, null arrays or entries, a
  * repeated plan or plans on different devices; otherwise as hdg_assemble_condense. */

@@ -342,6 +342,7 @@ hdg_status hdg_assemble_condense_batch(int32_t n, hdg_plan* const* plans, const 
     for (const CondenseBatchItem& it : items) locks.push_back(&const_cast<Plan*>(it.p)->cache_mu);
     std::sort(locks.begin(), locks.end());
     for (std::mutex* m : locks) m->lock();
+    ensure_side_streams(*const_cast<Plan*>(items[0].p));   // the streams the launches spread over
     int launches = 0;
     const hipError_t e = launch_condense_batch(items, &launches, stream);
     for (auto m = locks.rbegin(); m != locks.rend(); ++m) (*m)->unlock();

@@ -642,12 +642,19 @@ hipError_t launch_condense_batch(const std::vector<CondenseBatchItem>& items, in
         int32_t* status = (int32_t*)(it.ws + p.ws_status);
         if (e == hipSuccess) e = launch_clear_status(p, status, status + p.ne, s);
     }
-    int nl = 0;
+    // every launch of the call (up to kCondBatch bucket entries each), then the launches spread
+    // over the first plan's side streams as in launch_condense (they write disjoint slots)
+    struct GroupLaunch {
+        int p, pf, variant, blocks;
+        double cost;
+        CondBatch ba;
+    };
+    std::vector<GroupLaunch> gl;
     for (const auto& g : groups) {
         const auto& ents = g.second;
-        for (size_t k0 = 0; k0 < ents.size() && e == hipSuccess; k0 += kCondBatch) {
-            CondBatch ba{};
-            int blocks = 0;
+        for (size_t k0 = 0; k0 < ents.size(); k0 += kCondBatch) {
+            GroupLaunch L{std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), 0, 0.0, CondBatch{}};
+            CondBatch& ba = L.ba;
             ba.n = (int)std::min<size_t>(kCondBatch, ents.size() - k0);
             for (int k = 0; k < ba.n; ++k) {
                 const CondenseBatchItem& it = items[ents[k0 + k].first];
@@ -658,12 +665,47 @@ hipError_t launch_condense_batch(const std::vector<CondenseBatchItem>& items, in
                                         (double*)(it.ws + p.ws_g_part), (double*)(it.ws + p.ws_res_elem),
                                         (double*)(it.ws + p.ws_rl_part), status, status + p.ne, nullptr, -1);
                 set_bucket_args(p, bk, it.store, ba.a[k]);
-                ba.first[k] = blocks;
-                blocks += bk.count;
+                ba.first[k] = L.blocks;
+                L.blocks += bk.count;
             }
-            ba.first[ba.n] = blocks;
-            e = dispatch_batch_group(std::get<0>(g.first), std::get<1>(g.first), std::get<2>(g.first), blocks, ba, s);
-            ++nl;
+            ba.first[ba.n] = L.blocks;
+            const double n = 4.0 * n_modes(L.p);
+            L.cost = L.blocks * n * n * n;
+            gl.push_back(L);
+        }
+    }
+    const int ng = (int)gl.size();
+    const Plan& p0 = *items[0].p;
+    const bool fork = ng > 1 && p0.fork_ev != nullptr && e == hipSuccess;
+    std::vector<int> lane(ng, 0);
+    if (fork) {
+        std::vector<int> order(ng);
+        for (int k = 0; k < ng; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gl[x].cost > gl[y].cost; });
+        double load[1 + Plan::kSideStreams] = {};
+        for (int k : order) {
+            int best = 0;
+            for (int l = 1; l <= Plan::kSideStreams; ++l)
+                if (load[l] < load[best]) best = l;
+            lane[k] = best;
+            load[best] += gl[k].cost;
+        }
+        e = hipEventRecord(p0.fork_ev, s);
+        for (int i = 0; i < Plan::kSideStreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(p0.side[i], p0.fork_ev, 0);
+        if (e != hipSuccess) return e;
+    }
+    int nl = 0;
+    for (int k = 0; k < ng && e == hipSuccess; ++k) {
+        const hipStream_t q = lane[k] == 0 ? s : p0.side[lane[k] - 1];
+        e = dispatch_batch_group(gl[k].p, gl[k].pf, gl[k].variant, gl[k].blocks, gl[k].ba, q);
+        ++nl;
+    }
+    if (fork) {
+        // always joined, also after a failed launch
+        for (int i = 0; i < Plan::kSideStreams; ++i) {
+            hipError_t je = hipEventRecord(p0.join_ev[i], p0.side[i]);
+            if (je == hipSuccess) je = hipStreamWaitEvent(s, p0.join_ev[i], 0);
+            if (e == hipSuccess) e = je;
         }
     }
     for (const CondenseBatchItem& it : items) {
